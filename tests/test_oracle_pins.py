@@ -1,0 +1,422 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Nothing here compares the oracle with itself: the expected values come from
+the paper's worked example (Sections 3.2, 4.1, 4.2), from schedules derived by
+hand from the paper's rules (tests/golden/hand_cases.json, each case with its
+derivation), from closed forms of special DAGs, from lower bounds any valid
+schedule obeys, from brute-force enumeration of every dispatch order in the
+block execution model (Section 2.2), and from structural claims the paper
+makes (Sections 3.1, 3.2, 4.1).
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def load(name):
+    with open(os.path.join(GOLDEN, name)) as f:
+        return json.load(f)
+
+
+def edges_of(case):
+    e = np.asarray(case["edges"], np.int32).reshape(-1, 2)
+    return e[:, 0].copy(), e[:, 1].copy()
+
+
+def reachability(n, src, dst):
+    """Ancestor matrix by Warshall's transitive closure (independent of the
+    oracle's backward search): R[v, u] = u is a transitive predecessor of v."""
+    R = np.zeros((n, n), bool)
+    for u, v in zip(src, dst):
+        R[v, u] = True
+    for k in range(n):
+        R |= R[:, [k]] & R[[k], :]
+    return R
+
+
+# ---------------------------------------------------------------- worked example
+
+def test_worked_example_division():
+    ex = load("worked_example.json")
+    src, dst = edges_of(ex)
+    d = oracle.division(ex["n"], src, dst, ex["wcet"], ex["par"], ex["M"])
+    exp = ex["expect"]
+    assert d.theta == exp["theta"]
+    blocks = [sorted(np.nonzero(d.block == k)[0].tolist()) for k in range(len(d.theta) + 1)]
+    assert blocks == exp["blocks"]
+    assert [sorted(g) for g in d.groups] == exp["groups_as_sets"]
+    # Eq. 2 checked against a transitive closure computed independently
+    R = reachability(ex["n"], src, dst)
+    w = np.asarray(ex["wcet"])
+    assert d.wanc.tolist() == (w + (R * w[None, :]).sum(1)).tolist()
+
+
+def test_worked_example_paths_are_in_block_forests():
+    # Section 3.1: inside a block each node has at most one in-block
+    # predecessor; the local complete paths of the example follow from it.
+    ex = load("worked_example.json")
+    src, dst = edges_of(ex)
+    d = oracle.division(ex["n"], src, dst, ex["wcet"], ex["par"], ex["M"])
+    for k, exp_paths in enumerate(ex["expect"]["paths"]):
+        members = set(np.nonzero(d.block == k)[0].tolist())
+        succ = {v: [t for s, t in zip(src, dst) if s == v and t in members] for v in members}
+        has_pred = {t for s, t in zip(src, dst) if s in members and t in members}
+        paths = []
+
+        def walk(p):
+            nxt = succ[p[-1]]
+            if not nxt:
+                paths.append(p)
+            for t in nxt:
+                walk(p + [int(t)])
+
+        for v in sorted(members - has_pred):
+            walk([v])
+        assert sorted(paths) == sorted(exp_paths)
+
+
+def test_worked_example_schedule_and_bound():
+    ex = load("worked_example.json")
+    src, dst = edges_of(ex)
+    s = oracle.bound(ex["n"], src, dst, ex["wcet"], ex["par"], ex["M"], trace=True)
+    exp = ex["expect"]
+    assert s.bound == exp["bound"] == 5  # Section 4.2: R(G) <= 5
+    slot2 = s.slots[1]
+    members = {p.node: p for p in slot2.parts if p.kind == 0}
+    assert {str(k): v.m for k, v in members.items()} == exp["slot2"]["m"]  # m3 = m4 = 2
+    # WS_2 = max C * (M - sum m) = 1 * (6 - 4) = 2 (Eq. 6)
+    sum_m_members = sum(p.m for p in members.values())
+    assert slot2.maxC * (ex["M"] - sum_m_members) == exp["slot2"]["WS"]
+    segs = [p for p in slot2.parts if p.kind == 2]
+    assert len(segs) == 1
+    seg = exp["slot2"]["segment"]
+    assert (segs[0].node, segs[0].m, segs[0].load) == (seg["node"], seg["m"], seg["load"])
+    # the residual of v2 runs with its own group pi_3 (Section 4.1 example)
+    res = [p for p in s.slots[2].parts if p.node == seg["node"]]
+    assert len(res) == 1 and res[0].kind == 0 and res[0].load == seg["residual"]
+    got_edges = {(a, ap, b, bp) for (_, a, ap, b, bp) in s.edges}
+    for e in exp["extra_edges_contain"]:
+        assert tuple(e) in got_edges
+
+
+def test_worked_example_greedy_overload():
+    # Section 4.2: under Greedy (m_i = m_i^max, paper mode m^max = C_hat) the
+    # concurrent sets {v2,v3,v4} and {v5,v6} ask for more than M SMs.
+    ex = load("worked_example.json")
+    mmax = np.minimum(np.asarray(ex["par"]), np.asarray(ex["wcet"]))
+    for S in ex["expect"]["greedy_overload"]:
+        assert mmax[S].sum() > ex["M"]
+
+
+# ---------------------------------------------------------------- hand cases
+
+@pytest.mark.parametrize("case", load("hand_cases.json")["cases"], ids=lambda c: c["name"][:40])
+def test_hand_case(case):
+    src, dst = edges_of(case)
+    n, M = case["n"], case["M"]
+    d = oracle.division(n, src, dst, case["wcet"], case["par"], M)
+    exp = case["expect"]
+    assert d.groups == exp["groups"]
+    s = oracle.bound(n, src, dst, case["wcet"], case["par"], M, case.get("r"), trace=True)
+    assert (s.bound, s.cp, s.intf) == (exp["bound"], exp["cp"], exp["intf"])
+    assert len(s.slots) == len(exp["slots"])
+    for got, want in zip(s.slots, exp["slots"]):
+        assert got.R == want["R"] and got.maxC == want["maxC"]
+        assert [[p.node, p.kind, p.m, p.C, p.load] for p in got.parts] == want["parts"]
+    if "extra_edges_contain" in exp:
+        got_edges = {(a, ap, b, bp) for (_, a, ap, b, bp) in s.edges}
+        for e in exp["extra_edges_contain"]:
+            assert tuple(e) in got_edges
+    if "worst_makespan_slot" in exp:
+        for sl, want in zip(s.slots, exp["worst_makespan_slot"]):
+            ms = [p.m for p in sl.parts]
+            Cs = [p.C for p in sl.parts]
+            assert oracle.worst_makespan(ms, Cs, [[] for _ in ms], M) == want
+
+
+# ---------------------------------------------------------------- Eq. 1
+
+def test_exec_time_eq1():
+    # Eq. 1, t_min = 1: one wave for m <= M, ceil(m/M) waves above
+    assert oracle.exec_time(10, 3, 8) == 4
+    assert oracle.exec_time(10, 10, 8) == 2  # two waves of 10/10 -> 2 ticks
+    assert oracle.exec_time(1, 5, 8) == 1  # never below t_min
+    for load in range(1, 40):
+        for m in range(1, 20):
+            for M in (1, 4, 8, 16):
+                waves = -(-m // M)
+                assert oracle.exec_time(load, m, M) == max(1, -(-(waves * load) // m))
+
+
+# ---------------------------------------------------------------- closed forms
+
+def chain(n, wcet, par):
+    src = np.arange(n - 1, dtype=np.int32)
+    return src, src + 1
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_chain_closed_form(seed):
+    # A chain has one node per group and nothing to launch beside it; each
+    # node runs with m = min(r or p, p, C_hat, M), so the bound is the sum of
+    # ceil(C_hat / m); with p = 1 it is the summed WCET.
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(1, 30))
+    M = int(rng.integers(1, 20))
+    w = rng.integers(1, 200, n)
+    p = rng.integers(1, 12, n)
+    src, dst = chain(n, w, p)
+    r = W.random_alloc(rng, p + 3, 300, zero_frac=0.3)  # some r above p: clamped
+    for rr in (None, r):
+        b, cp, intf = oracle.bound(n, src, dst, w, p, M, rr)
+        mm = np.minimum(np.minimum(p, w), M)
+        if rr is not None:
+            mm = np.where(rr > 0, np.minimum(mm, rr), mm)
+        assert b == int(sum(-(-w // mm)))
+        assert intf == 0
+    b1, _, _ = oracle.bound(n, src, dst, w, np.ones(n, np.int32), M)
+    assert b1 == int(w.sum())
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_independent_set_closed_form(seed):
+    # source -> k unit-parallelism nodes -> sink: groups are the middle nodes
+    # in chunks of M by descending load; each chunk runs as long as its
+    # largest load.
+    rng = np.random.default_rng(100 + seed)
+    k = int(rng.integers(1, 25))
+    M = int(rng.integers(1, 9))
+    mid = rng.integers(1, 50, k)
+    n = k + 2
+    src = np.r_[np.zeros(k), np.arange(1, k + 1)].astype(np.int32)
+    dst = np.r_[np.arange(1, k + 1), np.full(k, k + 1)].astype(np.int32)
+    w = np.r_[[3], mid, [2]].astype(np.int64)
+    p = np.ones(n, np.int32)
+    b, _, _ = oracle.bound(n, src, dst, w, p, M)
+    # Top order: descending W^anc = 3 + load, ties by smaller id (stable sort)
+    order = sorted(range(k), key=lambda i: (-int(mid[i]), i))
+    expect = 3 + sum(int(mid[order[q]]) for q in range(0, k, M)) + 2
+    assert b == expect
+
+
+@pytest.mark.parametrize("k,M,c", [(1, 8, 5), (2, 8, 3), (4, 8, 7), (8, 8, 7), (2, 16, 15), (4, 4, 1),
+                                   (3, 8, 8), (5, 4, 9), (2, 6, 6)])
+def test_equal_load_group_closed_form(k, M, c):
+    # k | M nodes of equal load c < M, p >= c: Eq. 5 gives each m = min(c, M/k),
+    # so the group needs max(1, ceil(k*c/M)) ticks.  With c >= M Rule 2 makes
+    # each node a group of its own running on all M SMs: k * ceil(c/M) ticks.
+    n = k + 2
+    src = np.r_[np.zeros(k), np.arange(1, k + 1)].astype(np.int32)
+    dst = np.r_[np.arange(1, k + 1), np.full(k, k + 1)].astype(np.int32)
+    w = np.r_[[1], np.full(k, c), [1]].astype(np.int64)
+    p = np.r_[[1], np.full(k, c + 5), [1]].astype(np.int32)
+    b, cp, intf = oracle.bound(n, src, dst, w, p, M)
+    if k == 1:
+        assert b == 1 + -(-c // min(c, M)) + 1
+    elif c < M:
+        assert b == 1 + max(1, -(-(k * c) // M)) + 1
+    else:
+        assert b == 1 + k * -(-c // M) + 1
+    assert intf == 0
+
+
+# ---------------------------------------------------------------- invariants
+
+def division_invariants(n, src, dst, w, p, M):
+    d = oracle.division(n, src, dst, w, p, M)
+    R = reachability(n, src, dst) if n <= 400 else None
+    # Theta: join nodes, ascending W^anc, ties by smaller id
+    indeg = np.bincount(dst, minlength=n)
+    joins = sorted(np.nonzero(indeg >= 2)[0].tolist(), key=lambda v: (int(d.wanc[v]), v))
+    assert d.theta == joins
+    # Eq. 3: blocks
+    assigned = np.full(n, -1)
+    if R is not None:
+        for k, t in enumerate(d.theta):
+            anc = np.nonzero(R[t])[0]
+            new = anc[assigned[anc] < 0]
+            assigned[new] = k
+        assigned[assigned < 0] = len(d.theta)
+        assert assigned.tolist() == d.block.tolist()
+    # in-block in-degree <= 1 (Section 3.1)
+    inb = np.zeros(n, int)
+    for s, t in zip(src, dst):
+        if d.block[s] == d.block[t]:
+            inb[t] += 1
+    assert inb.max(initial=0) <= 1
+    # groups partition V, |pi| <= M, Rule 2, antichains, linear extension
+    flat = [v for g in d.groups for v in g]
+    assert sorted(flat) == list(range(n))
+    gof = np.empty(n, int)
+    for j, g in enumerate(d.groups):
+        gof[g] = j
+        assert 1 <= len(g) <= M
+        if len(g) > 1:
+            assert all(min(int(p[v]), int(w[v])) < M for v in g)
+        if R is not None:
+            for a in g:
+                for b in g:
+                    assert not R[a, b]
+        # members in Top order
+        assert g == sorted(g, key=lambda v: (-int(d.wanc[v]), v))
+    for s, t in zip(src, dst):
+        assert gof[s] < gof[t]
+    return d
+
+
+def schedule_invariants(n, src, dst, w, p, M, r):
+    s = oracle.bound(n, src, dst, w, p, M, r, trace=True)
+    done_load = np.zeros(n, np.int64)
+    finished = np.zeros(n, int)
+    for sl in s.slots:
+        segs = [q for q in sl.parts if q.kind == 2]
+        assert len(segs) <= 1  # at most one segmentation per group (Section 4.1)
+        for q in sl.parts:
+            # m never exceeds the useful parallelism C_hat / t_min (Section 2.2)
+            assert 1 <= q.m <= min(M, q.load)
+            assert q.C == -(-q.load // q.m)
+            assert q.C <= sl.maxC
+            done_load[q.node] += q.load
+            if q.kind != 2:
+                finished[q.node] += 1
+        if any(q.kind != 0 for q in sl.parts):
+            assert sl.sum_m <= M  # launching only fills spare SMs
+        if sl.nP:
+            assert sl.R >= sl.maxC
+            assert sl.R == sl.maxC or sl.sum_m > M
+    assert done_load.tolist() == np.asarray(w).tolist()
+    assert finished.tolist() == [1] * n
+    assert s.bound == sum(sl.R for sl in s.slots) == s.cp + s.intf
+    return s
+
+
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_invariants_on_workloads(k):
+    wl = W.WORKLOADS[k]
+    batch = W.generate_workload(k, count=40 if k < 3 else 6)
+    rng = np.random.default_rng(k)
+    for dgi in range(batch.num_dags):
+        n, src, dst, w, p = batch.dag(dgi)
+        division_invariants(n, src, dst, w, p, wl.num_cus)
+        for rr in (None, W.random_alloc(rng, p, wl.num_cus), W.random_alloc(rng, p, wl.num_cus, 0.5)):
+            schedule_invariants(n, src, dst, w, p, wl.num_cus, rr)
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_invariants_random_small(seed):
+    rng = np.random.default_rng(1000 + seed)
+    n = int(rng.integers(1, 14))
+    M = int(rng.integers(1, 10))
+    n, src, dst, w, p = W.random_small_dag(rng, n, float(rng.uniform(0.1, 0.6)), 30, 12)
+    division_invariants(n, src, dst, w, p, M)
+    schedule_invariants(n, src, dst, w, p, M, W.random_alloc(rng, p, M, 0.4))
+
+
+def longest_path(n, src, dst, weight):
+    order = []
+    indeg = np.bincount(dst, minlength=n).tolist()
+    succ = [[] for _ in range(n)]
+    for s, t in zip(src, dst):
+        succ[s].append(t)
+    q = [v for v in range(n) if indeg[v] == 0]
+    while q:
+        v = q.pop()
+        order.append(v)
+        for t in succ[v]:
+            indeg[t] -= 1
+            if indeg[t] == 0:
+                q.append(t)
+    dist = [0] * n
+    for v in order:
+        dist[v] += int(weight[v])
+        for t in succ[v]:
+            dist[t] = max(dist[t], dist[v])
+    return max(dist, default=0)
+
+
+@pytest.mark.parametrize("seed", range(30))
+def test_lower_bounds(seed):
+    # Any schedule in the block model needs at least the critical path at
+    # full parallelism and the total work spread over M SMs.
+    rng = np.random.default_rng(2000 + seed)
+    n, src, dst, w, p = W.random_small_dag(rng, int(rng.integers(2, 40)), 0.15, 500, 40)
+    M = int(rng.integers(1, 64))
+    r = W.random_alloc(rng, p, M, 0.3)
+    for rr in (None, r):
+        b, _, _ = oracle.bound(n, src, dst, w, p, M, rr)
+        fast = -(-w // np.minimum(np.minimum(p, w), M))
+        assert b >= longest_path(n, src, dst, fast)
+        assert b >= -(-int(w.sum()) // M)
+
+
+# ---------------------------------------------------------------- brute force
+
+def _check_safe(n, src, dst, w, p, M, r, early_seeds=3):
+    s = oracle.bound(n, src, dst, w, p, M, r, trace=True)
+    m, C, preds = oracle.schedule_parts(s, barriers=True)
+    worst = oracle.worst_makespan(m, C, preds, M, node_limit=2_000_000)
+    if worst < 0:
+        return None
+    assert worst <= s.bound
+    if all(sl.sum_m <= M for sl in s.slots):
+        # Lemma 1 is exact when every group fits: every dispatch order gives
+        # the same makespan (the schedule is predictable)
+        assert worst == s.bound
+    for k in range(early_seeds):
+        # early completion never exceeds the bound (sustainability)
+        assert oracle.random_makespan(m, C, preds, M, seed=k, early=True) <= s.bound
+    return worst
+
+
+@pytest.mark.parametrize("seed", range(60))
+def test_bound_safe_against_every_dispatch(seed):
+    rng = np.random.default_rng(3000 + seed)
+    n = int(rng.integers(2, 8))
+    M = int(rng.integers(1, 7))
+    n, src, dst, w, p = W.random_small_dag(rng, n, float(rng.uniform(0.15, 0.6)), 6, 6)
+    r = W.random_alloc(rng, p, 255, zero_frac=float(rng.uniform(0, 1)))
+    _check_safe(n, src, dst, w, p, M, r)
+    _check_safe(n, src, dst, w, p, M, None)
+
+
+def test_bound_tight_on_oversubscribed_group():
+    # 5 blocks of 2 ticks on 4 SMs: the list-scheduling response 2 + (10-2)/4
+    # is reached by the dispatch that leaves one block for the end.
+    case = load("hand_cases.json")["cases"][0]
+    src, dst = edges_of(case)
+    worst = _check_safe(case["n"], src, dst, case["wcet"], case["par"], case["M"], None)
+    assert worst == case["expect"]["bound"]
+
+
+# ---------------------------------------------------------------- input checks
+
+def test_rejects_bad_inputs():
+    w = [1, 1, 1]
+    p = [1, 1, 1]
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.bound(3, [0, 1, 2], [1, 2, 0], w, p, 4)
+    assert e.value.code == oracle.E_CYCLE
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.bound(3, [0, 0], [1, 1], w, p, 4)
+    assert e.value.code == oracle.E_DUP_EDGE
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.bound(3, [1], [1], w, p, 4)
+    assert e.value.code == oracle.E_CYCLE
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.bound(3, [0], [3], w, p, 4)
+    assert e.value.code == oracle.E_RANGE
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.bound(3, [0], [1], [1, 0, 1], p, 4)
+    assert e.value.code == oracle.E_RANGE
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.bound(3, [0], [1], w, [1, 1, 0], 4)
+    assert e.value.code == oracle.E_RANGE
+    assert oracle.bound(0, [], [], [], [], 4) == (0, 0, 0)
