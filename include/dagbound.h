@@ -1,0 +1,209 @@
+/*
+ * libdagbound -- batched exact evaluation of the makespan bound of
+ * DAG-structured GPU tasks on AMD Instinct MI355X (gfx950).
+ *
+ * Method: Zhang et al., "Exploiting Dependency and Parallelism: Real-Time
+ * Scheduling and Analysis for GPU Tasks" (DAC 2026).
+ *   - Task model (Section 2.1): a DAG G = (V, E); node v is a kernel with
+ *     load C_hat_v (its execution time on one compute unit, integer ticks,
+ *     t_min = 1) and maximum parallelism p_v; the GPU has M compute units.
+ *   - Sub-graph division (Section 3, Eqs. 2-4, Algorithm 1) splits G into an
+ *     ordered list of balanced groups.
+ *   - Scheduling (Section 4.1, Eqs. 1, 5-7, Algorithm 2) sets each kernel's
+ *     parallelism, launches parallel nodes into spare compute units, splits
+ *     nodes that do not fit (segmentation) and adds extra dependencies.
+ *   - Analysis (Section 4.2, Lemma 1, Theorem 1): the makespan is bounded by
+ *     the sum of the groups' responses.
+ * A candidate allocation r (one byte per node) replaces the paper's
+ * parallelism rule for nodes with r_v > 0: as a group member the node runs
+ * with m = min(r_v, p_v, remaining load, M) instead of Eq. 5; as a parallel
+ * node its greedy target min(m^max, S) uses r_v instead of m^max.  r_v = 0
+ * keeps the paper's rule.  Candidate 0 of every DAG is the paper's own
+ * schedule (its bytes are ignored).  The bound of a group whose compute-unit
+ * demand exceeds M (Eq. 5 rounding, or explicit r) adds the list-scheduling
+ * interference term floor((A - maxC) / M), A = sum of m * C over the group.
+ *
+ * All results are exact int64, bit-identical to the plain CPU definition.
+ *
+ * Conventions shared by every call:
+ *   - Status: 0 on success, a negative DAGBOUND_E_* code on failure;
+ *     dagbound_last_error() then returns a message (per thread).  On failure
+ *     outputs are not written and the batch is unchanged.
+ *   - ptr_kind: DAGBOUND_PTR_HOST (host memory) or DAGBOUND_PTR_DEVICE
+ *     (device memory of the current HIP device, e.g. a torch tensor's
+ *     data_ptr()).  It applies to every array argument of the call.
+ *   - hip_stream: a hipStream_t, or NULL.  With NULL, and for any call with
+ *     host pointers, the call returns after the work is complete.  With a
+ *     stream and device pointers the work is ordered on that stream and the
+ *     call may return before it completes.  Calls on one batch must be
+ *     ordered (one stream, or synchronized by the caller).
+ *   - A batch is bound to the HIP device that was current at creation.
+ */
+#ifndef DAGBOUND_H
+#define DAGBOUND_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dagbound_batch dagbound_batch; /* opaque; owns its device memory */
+typedef struct dagbound_model dagbound_model; /* opaque learned proposal (reserved) */
+typedef int32_t dagbound_status;
+
+enum {
+  DAGBOUND_OK = 0,
+  DAGBOUND_E_ARG = -1,        /* bad argument (null pointer, negative count, bad enum) */
+  DAGBOUND_E_CYCLE = -2,      /* a DAG has a cycle or a self-loop */
+  DAGBOUND_E_RANGE = -3,      /* a node id, load or parallelism is out of range */
+  DAGBOUND_E_DUP_EDGE = -4,   /* a DAG lists the same edge twice */
+  DAGBOUND_E_OOM = -5,        /* device memory exhausted */
+  DAGBOUND_E_DEVICE = -6,     /* HIP runtime error, or no usable device */
+  DAGBOUND_E_STATE = -7,      /* call out of order (e.g. eval before set_allocations) */
+  DAGBOUND_E_OVERFLOW = -8,   /* a DAG's summed load reaches 2^40 */
+  DAGBOUND_E_UNSUPPORTED = -9 /* valid input this build does not handle */
+};
+enum { DAGBOUND_PTR_HOST = 0, DAGBOUND_PTR_DEVICE = 1 };
+enum { DAGBOUND_ALLOC_EXPLICIT = 0, DAGBOUND_ALLOC_SEEDED = 1 };
+enum { DAGBOUND_SEARCH_EXHAUSTIVE = 0, DAGBOUND_SEARCH_SURROGATE = 1 };
+
+/* Limits of this build. */
+#define DAGBOUND_MAX_NODES_PER_DAG 512   /* N_d, source and sink included */
+#define DAGBOUND_MAX_CANDIDATES (1 << 22)
+
+/*
+ * dagbound_create_batch -- ingest num_dags DAG tasks and run the
+ * allocation-independent part of the method on the GPU: input validation,
+ * the ancestor closure and cumulative ancestor workload W^anc (Eq. 2), the
+ * join-node list Theta, blocks (Eq. 3), local complete paths (Eq. 4) and the
+ * balanced groups of Algorithm 1 (Rules 1-2), for M = num_cus compute units.
+ *
+ *   num_dags   D >= 0.
+ *   node_off   int64 [D+1]: DAG d owns nodes node_off[d] .. node_off[d+1]-1
+ *              of wcet/max_par; node_off[0] = 0, nondecreasing.  A DAG may be
+ *              empty (bound 0).  N_d <= DAGBOUND_MAX_NODES_PER_DAG.
+ *   edge_off   int64 [D+1]: DAG d owns edges edge_off[d] .. edge_off[d+1]-1;
+ *              edge_off[0] = 0, nondecreasing.
+ *   edge_src, edge_dst  int32 [edge_off[D]]: DAG-local node ids in
+ *              [0, N_d); edge (u, v) means v starts after u completes.
+ *              Any order; a single source/sink is not required.
+ *   wcet       int64 [node_off[D]]: load C_hat_v, 1 <= C_hat_v <= 2^31-1;
+ *              per DAG the sum must stay below 2^40.
+ *   max_par    int32 [node_off[D]]: p_v >= 1.
+ *   num_cus    M, 1 <= M <= 65535.
+ *   out        receives the batch handle (untouched on failure).
+ * Errors: E_ARG, E_CYCLE (cycle or self-loop), E_RANGE, E_DUP_EDGE,
+ * E_OVERFLOW, E_OOM, E_DEVICE, E_UNSUPPORTED (a DAG above the node limit);
+ * the message names the first failing DAG.  The batch copies what it needs;
+ * the caller may free or reuse the inputs when the call returns.  This call
+ * always waits for its GPU work (it must see the validation result).
+ */
+dagbound_status dagbound_create_batch(int32_t num_dags, const int64_t* node_off,
+                                      const int64_t* edge_off, const int32_t* edge_src,
+                                      const int32_t* edge_dst, const int64_t* wcet,
+                                      const int32_t* max_par, int32_t num_cus, uint32_t ptr_kind,
+                                      void* hip_stream, dagbound_batch** out);
+
+/*
+ * dagbound_set_allocations -- define K candidate allocations per DAG.
+ *
+ *   K      1 <= K <= DAGBOUND_MAX_CANDIDATES.
+ *   mode   DAGBOUND_ALLOC_EXPLICIT: `alloc` holds K * node_off[D] bytes; the
+ *          byte r of (DAG d, candidate c, local node v) sits at
+ *          K * node_off[d] + c * N_d + v.  Bytes of candidate 0 are ignored.
+ *          With PTR_HOST the bytes are copied into the batch.  With
+ *          PTR_DEVICE the batch keeps the pointer and reads the bytes in
+ *          place at each later evaluation: the caller keeps that memory
+ *          alive and unchanged until the last evaluation that uses it.
+ *          DAGBOUND_ALLOC_SEEDED: `alloc` is ignored; for c >= 1 the byte is
+ *          drawn on the GPU by the counter-based hash
+ *            mix(z): z ^= z>>30; z *= 0xBF58476D1CE4E5B9; z ^= z>>27;
+ *                    z *= 0x94D049BB133111EB; z ^= z>>31   (SplitMix64
+ *                    finalizer, Steele, Lea and Flood, OOPSLA 2014)
+ *            key  = mix(seed ^ mix(d * 0x9E3779B97F4A7C15))
+ *            word = mix(key ^ ((c << 32) | (v >> 2)))
+ *            h16  = (word >> (16 * (v & 3))) & 0xFFFF
+ *            r    = 1 + ((h16 * range) >> 16),  range = min(p_v, M, 255)
+ *          (d is the DAG's index in the batch, all arithmetic mod 2^64).
+ *   seed   used by SEEDED only.
+ * Errors: E_ARG.  Replaces any earlier allocation set.
+ */
+dagbound_status dagbound_set_allocations(dagbound_batch* batch, int32_t K, uint32_t mode,
+                                         const uint8_t* alloc, uint64_t seed, uint32_t ptr_kind);
+
+/*
+ * dagbound_eval_bounds -- the bound of every (DAG, candidate) pair: the
+ * scheduling of Algorithm 2 (Eqs. 1, 5-7, segmentation, extra dependencies
+ * as slot order) and the analysis of Lemma 1 / Theorem 1.
+ *
+ *   bounds     int64 [D * K]: bounds[d * K + c] = sum over groups of R_j
+ *              (may be NULL only when D * K = 0).
+ *   cp_term    int64 [D * K] or NULL: sum over groups of max C (the Lemma 1
+ *              terms); intf_term int64 [D * K] or NULL: sum of the
+ *              interference terms.  bounds = cp_term + intf_term.
+ * Errors: E_ARG, E_STATE (no allocations set), E_DEVICE.
+ */
+dagbound_status dagbound_eval_bounds(dagbound_batch* batch, int64_t* bounds, int64_t* cp_term,
+                                     int64_t* intf_term, uint32_t ptr_kind, void* hip_stream);
+
+/*
+ * dagbound_best_allocation -- per DAG, the candidate of least bound (ties to
+ * the smallest candidate index) and that bound.
+ *
+ *   search     DAGBOUND_SEARCH_EXHAUSTIVE: every candidate is evaluated
+ *              exactly (when dagbound_eval_bounds already ran on the current
+ *              allocation set, its per-DAG minimum is reused).
+ *              DAGBOUND_SEARCH_SURROGATE: reserved; returns E_UNSUPPORTED.
+ *   top_k      ignored by EXHAUSTIVE.
+ *   model      NULL for EXHAUSTIVE.
+ *   best_idx   int32 [D]; best_bound int64 [D] (NULL only when D = 0).  An
+ *              empty DAG reports candidate 0 with bound 0.
+ * Errors: E_ARG, E_STATE, E_UNSUPPORTED, E_DEVICE.
+ */
+dagbound_status dagbound_best_allocation(dagbound_batch* batch, uint32_t search, int32_t top_k,
+                                         const dagbound_model* model, int32_t* best_idx,
+                                         int64_t* best_bound, uint32_t ptr_kind, void* hip_stream);
+
+/*
+ * dagbound_get_division -- inspection of DAG d's sub-graph division as the
+ * GPU computed it (host outputs, each may be NULL).
+ *   wanc       int64 [N_d]: W^anc of each local node (Eq. 2).
+ *   group_of   int32 [N_d]: index of the balanced group holding each node.
+ *   order      int32 [N_d]: the nodes in group order (groups in Pi order,
+ *              members of a group by descending W^anc, ties smaller id).
+ *   num_groups receives |Pi|.
+ * Waits for the batch's work.  Errors: E_ARG, E_DEVICE.
+ */
+dagbound_status dagbound_get_division(dagbound_batch* batch, int32_t d, int64_t* wanc,
+                                      int32_t* group_of, int32_t* order, int32_t* num_groups);
+
+/*
+ * dagbound_set_tuning -- launch-plan options of the evaluation kernels; they
+ * never change results.
+ *   "residual_slots"  1..12 (default 12): per-candidate table slots for the
+ *                     remaining loads of segmented nodes in the first
+ *                     evaluation pass; a 64-candidate tile that needs more is
+ *                     re-evaluated by the second pass, whose tables live in
+ *                     global memory and hold every node.
+ *   "eval_path"       0 (default): first pass, then the second pass for the
+ *                     tiles it hands over; 1: the second pass for every tile.
+ * Errors: E_ARG (unknown key or value).
+ */
+dagbound_status dagbound_set_tuning(dagbound_batch* batch, const char* key, int64_t value);
+
+/* Release the batch and its device memory (waits for its work).  NULL is a
+ * no-op. */
+void dagbound_destroy_batch(dagbound_batch* batch);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* dagbound_last_error(void);
+
+/* Library version string. */
+const char* dagbound_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DAGBOUND_H */

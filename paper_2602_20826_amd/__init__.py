@@ -1,0 +1,11 @@
+"""libdagbound: batched exact evaluation of the makespan bound of DAG-structured
+GPU tasks (Zhang et al., DAC 2026) on AMD Instinct MI355X.
+
+The C-ABI library (``libdagbound.so``, HIP kernels for gfx950) does the work;
+``dagbound`` is its thin Python binding with the same call names.
+"""
+from .dagbound import (  # noqa: F401
+    ALLOC_EXPLICIT, ALLOC_SEEDED, PTR_DEVICE, PTR_HOST, SEARCH_EXHAUSTIVE, SEARCH_SURROGATE,
+    Batch, DagboundError, best_allocation, create_batch, destroy_batch, eval_bounds,
+    get_division, last_error, load_library, set_allocations, set_tuning, version,
+)

@@ -1,0 +1,565 @@
+// C-ABI of libdagbound (declared in include/dagbound.h): argument checks,
+// device memory, and the order of the kernel launches.  Every step of the
+// method runs in the gfx950 kernels of prep.hip and sweep.hip; this file only
+// moves buffers and launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "dagbound.h"
+#include "internal.h"
+
+using namespace dagbound;
+
+namespace {
+
+thread_local std::string g_err;
+
+dagbound_status fail(dagbound_status code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+dagbound_status hip_fail(hipError_t e, const char* what) {
+  return fail(e == hipErrorOutOfMemory ? DAGBOUND_E_OOM : DAGBOUND_E_DEVICE, "%s: %s", what,
+              hipGetErrorString(e));
+}
+
+// ---------------------------------------------------------------------------
+// Device memory: freed batch blocks are kept per device and handed to the next
+// batch of similar size, so repeated create/destroy cycles do not go back to
+// the HIP allocator each time.
+struct CachedBlock {
+  void* p;
+  size_t size;
+  int device;
+};
+std::mutex g_mu;
+std::vector<CachedBlock> g_cache;
+size_t g_cached_bytes = 0;
+constexpr size_t CACHE_CAP = 16ull << 30;
+constexpr size_t GRAIN = 2ull << 20;
+
+void cache_trim_locked(size_t cap) {
+  while (g_cached_bytes > cap && !g_cache.empty()) {
+    CachedBlock b = g_cache.front();
+    g_cache.erase(g_cache.begin());
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(b.device);
+    (void)hipFree(b.p);
+    (void)hipSetDevice(cur);
+    g_cached_bytes -= b.size;
+  }
+}
+
+hipError_t dev_alloc(void** p, size_t* size, int device) {
+  size_t need = std::max<size_t>(GRAIN, (*size + GRAIN - 1) / GRAIN * GRAIN);
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    int best = -1;
+    for (size_t i = 0; i < g_cache.size(); i++) {
+      const CachedBlock& b = g_cache[i];
+      if (b.device == device && b.size >= need && b.size <= 2 * need &&
+          (best < 0 || b.size < g_cache[best].size))
+        best = (int)i;
+    }
+    if (best >= 0) {
+      *p = g_cache[best].p;
+      *size = g_cache[best].size;
+      g_cached_bytes -= g_cache[best].size;
+      g_cache.erase(g_cache.begin() + best);
+      return hipSuccess;
+    }
+  }
+  hipError_t e = hipMalloc(p, need);
+  if (e == hipErrorOutOfMemory) {
+    (void)hipGetLastError();
+    {
+      std::lock_guard<std::mutex> lk(g_mu);
+      cache_trim_locked(0);
+    }
+    e = hipMalloc(p, need);
+  }
+  if (e == hipSuccess) *size = need;
+  return e;
+}
+
+void dev_release(void* p, size_t size, int device) {
+  if (!p) return;
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_cache.push_back({p, size, device});
+  g_cached_bytes += size;
+  cache_trim_locked(CACHE_CAP);
+}
+
+// Restores the caller's current device on scope exit.
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) == hipSuccess && prev != dev) (void)hipSetDevice(dev);
+    else prev = -1;
+  }
+  ~DeviceGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+// Bump allocator over one device block.
+struct Carve {
+  char* base;
+  size_t off = 0;
+  explicit Carve(void* b) : base((char*)b) {}
+  template <class T>
+  T* take(size_t count) {
+    off = (off + 255) & ~(size_t)255;
+    T* p = (T*)(base + off);
+    off += count * sizeof(T);
+    return p;
+  }
+};
+
+size_t table_bytes(int64_t D, int64_t tn, int64_t te, int64_t max_n) {
+  return 18 * 256 + (size_t)(D + 1) * 8 * 2 + (size_t)tn * 8 + (size_t)D * 8 + 16 +
+         (size_t)tn * 4 + (size_t)(tn + D) * 4 + (size_t)D * 4 + (size_t)tn * 2 * 4 +
+         (size_t)te * 2 + (size_t)GLOBAL_PASS_GRID * (size_t)max_n * 64 * 4;
+}
+
+}  // namespace
+
+struct dagbound_batch {
+  int device = 0;
+  int32_t D = 0, M = 1;
+  int64_t tn = 0, te = 0;
+  int32_t max_n = 0, max_e = 0;
+  std::vector<int64_t> node_off, edge_off;  // host copies
+  void* block = nullptr;
+  size_t block_size = 0;
+  Tables t{};
+  unsigned long long* best = nullptr;  // [D] packed per-DAG minimum
+  unsigned long long* err = nullptr;   // [2] first failing DAG, largest load
+  uint32_t* gres = nullptr;            // residual tables of the global evaluation pass
+  bool small_loads = false;            // every load < 2^22
+  // per-allocation-set scratch: tiles handed to the global pass
+  void* ovf_block = nullptr;
+  size_t ovf_block_size = 0;
+  uint32_t* ovf_list = nullptr;
+  uint32_t* ovf_count = nullptr;
+  // tuning
+  int32_t res_slots = RES_SLOTS;
+  int32_t eval_path = EVAL_PATH_AUTO;
+  // candidate allocations
+  bool has_alloc = false;
+  int32_t K = 0;
+  uint32_t mode = DAGBOUND_ALLOC_EXPLICIT;
+  const uint8_t* alloc = nullptr;
+  void* alloc_owned = nullptr;
+  size_t alloc_owned_size = 0;
+  uint64_t seed = 0;
+  uint64_t alloc_gen = 0;
+  uint64_t best_gen = ~0ull;
+};
+
+namespace {
+
+void batch_free(dagbound_batch* b) {
+  if (!b) return;
+  {
+    DeviceGuard g(b->device);
+    (void)hipDeviceSynchronize();
+  }
+  dev_release(b->block, b->block_size, b->device);
+  dev_release(b->alloc_owned, b->alloc_owned_size, b->device);
+  dev_release(b->ovf_block, b->ovf_block_size, b->device);
+  delete b;
+}
+
+SweepArgs sweep_args(const dagbound_batch* b) {
+  SweepArgs a{};
+  a.t = b->t;
+  a.D = b->D;
+  a.M = b->M;
+  a.K = b->K;
+  a.alloc = b->mode == DAGBOUND_ALLOC_EXPLICIT ? b->alloc : nullptr;
+  a.seed = b->seed;
+  a.max_n = b->max_n;
+  a.max_e = b->max_e;
+  a.ovf_list = b->ovf_list;
+  a.ovf_count = b->ovf_count;
+  a.gres = b->gres;
+  a.res_slots = b->res_slots;
+  a.path = b->eval_path;
+  a.small_loads = b->small_loads ? 1 : 0;
+  return a;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* dagbound_last_error(void) { return g_err.c_str(); }
+
+const char* dagbound_version(void) { return "libdagbound 0.1 (gfx950)"; }
+
+dagbound_status dagbound_create_batch(int32_t num_dags, const int64_t* node_off,
+                                      const int64_t* edge_off, const int32_t* edge_src,
+                                      const int32_t* edge_dst, const int64_t* wcet,
+                                      const int32_t* max_par, int32_t num_cus, uint32_t ptr_kind,
+                                      void* hip_stream, dagbound_batch** out) {
+  g_err.clear();
+  if (!out) return fail(DAGBOUND_E_ARG, "out is NULL");
+  if (num_dags < 0) return fail(DAGBOUND_E_ARG, "num_dags < 0");
+  if (ptr_kind > DAGBOUND_PTR_DEVICE) return fail(DAGBOUND_E_ARG, "bad ptr_kind %u", ptr_kind);
+  if (num_cus < 1 || num_cus > 65535) return fail(DAGBOUND_E_ARG, "num_cus %d outside [1, 65535]", num_cus);
+  if (!node_off || !edge_off) return fail(DAGBOUND_E_ARG, "node_off/edge_off is NULL");
+  int device = 0;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
+    (void)hipGetLastError();
+    return fail(DAGBOUND_E_DEVICE, "no HIP device");
+  }
+  if (hipGetDevice(&device) != hipSuccess) return fail(DAGBOUND_E_DEVICE, "hipGetDevice failed");
+  hipStream_t st = (hipStream_t)hip_stream;
+  const int64_t D = num_dags;
+
+  std::vector<int64_t> no(D + 1), eo(D + 1);
+  if (ptr_kind == DAGBOUND_PTR_HOST) {
+    memcpy(no.data(), node_off, (D + 1) * sizeof(int64_t));
+    memcpy(eo.data(), edge_off, (D + 1) * sizeof(int64_t));
+  } else {
+    hipError_t e = hipMemcpyAsync(no.data(), node_off, (D + 1) * 8, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(eo.data(), edge_off, (D + 1) * 8, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "reading node_off/edge_off");
+  }
+  if (no[0] != 0 || eo[0] != 0) return fail(DAGBOUND_E_ARG, "node_off[0] and edge_off[0] must be 0");
+  int64_t max_n = 0, max_e = 0;
+  for (int64_t d = 0; d < D; d++) {
+    const int64_t n = no[d + 1] - no[d], e = eo[d + 1] - eo[d];
+    if (n < 0 || e < 0) return fail(DAGBOUND_E_ARG, "DAG %lld: offsets decrease", (long long)d);
+    if (n > DAGBOUND_MAX_NODES_PER_DAG)
+      return fail(DAGBOUND_E_UNSUPPORTED, "DAG %lld has %lld nodes; this build handles at most %d",
+                  (long long)d, (long long)n, DAGBOUND_MAX_NODES_PER_DAG);
+    max_n = std::max(max_n, n);
+    max_e = std::max(max_e, e);
+  }
+  const int64_t tn = no[D], te = eo[D];
+  if (tn > 0 && (!wcet || !max_par)) return fail(DAGBOUND_E_ARG, "wcet/max_par is NULL");
+  if (te > 0 && (!edge_src || !edge_dst)) return fail(DAGBOUND_E_ARG, "edge_src/edge_dst is NULL");
+
+  dagbound_batch* b = new dagbound_batch();
+  b->device = device;
+  b->D = num_dags;
+  b->M = num_cus;
+  b->tn = tn;
+  b->te = te;
+  b->max_n = (int32_t)max_n;
+  b->max_e = (int32_t)std::min<int64_t>(max_e, INT32_MAX);
+  b->node_off = no;
+  b->edge_off = eo;
+  b->block_size = table_bytes(D, tn, te, max_n);
+  hipError_t e = dev_alloc(&b->block, &b->block_size, device);
+  if (e != hipSuccess) {
+    delete b;
+    return hip_fail(e, "allocating batch tables");
+  }
+  Carve cv(b->block);
+  int64_t* d_no = cv.take<int64_t>(D + 1);
+  int64_t* d_eo = cv.take<int64_t>(D + 1);
+  b->t.node_off = d_no;
+  b->t.edge_off = d_eo;
+  b->t.wanc = cv.take<int64_t>(tn);
+  b->best = cv.take<unsigned long long>(D);
+  b->err = cv.take<unsigned long long>(2);
+  b->gres = cv.take<uint32_t>((size_t)GLOBAL_PASS_GRID * (size_t)max_n * 64);
+  b->t.wc = cv.take<uint32_t>(tn);
+  b->t.soff = cv.take<uint32_t>(tn + D);
+  b->t.ngroups = cv.take<int32_t>(D);
+  b->t.gl = cv.take<uint16_t>(tn);
+  b->t.pp = cv.take<uint16_t>(tn);
+  b->t.indeg = cv.take<uint16_t>(tn);
+  b->t.inv = cv.take<uint16_t>(tn);
+  b->t.succ = cv.take<uint16_t>(te);
+
+  // Inputs: device pointers are read in place; host arrays go through a
+  // staging block that is released when this call returns.
+  PrepInputs in{edge_src, edge_dst, wcet, max_par};
+  void* stage = nullptr;
+  size_t stage_size = 0;
+  e = hipMemcpyAsync(d_no, no.data(), (D + 1) * 8, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(d_eo, eo.data(), (D + 1) * 8, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess && ptr_kind == DAGBOUND_PTR_HOST && (tn + te) > 0) {
+    stage_size = 4 * 256 + (size_t)te * 8 + (size_t)tn * 12;
+    e = dev_alloc(&stage, &stage_size, device);
+    if (e == hipSuccess) {
+      Carve sc(stage);
+      int32_t* s_src = sc.take<int32_t>(te);
+      int32_t* s_dst = sc.take<int32_t>(te);
+      int64_t* s_w = sc.take<int64_t>(tn);
+      int32_t* s_p = sc.take<int32_t>(tn);
+      e = hipMemcpyAsync(s_src, edge_src, te * 4, hipMemcpyHostToDevice, st);
+      if (e == hipSuccess) e = hipMemcpyAsync(s_dst, edge_dst, te * 4, hipMemcpyHostToDevice, st);
+      if (e == hipSuccess) e = hipMemcpyAsync(s_w, wcet, tn * 8, hipMemcpyHostToDevice, st);
+      if (e == hipSuccess) e = hipMemcpyAsync(s_p, max_par, tn * 4, hipMemcpyHostToDevice, st);
+      in = PrepInputs{s_src, s_dst, s_w, s_p};
+    }
+  }
+  if (e == hipSuccess) e = hipMemsetAsync(b->err, 0xFF, sizeof(unsigned long long), st);
+  if (e == hipSuccess) e = hipMemsetAsync(b->err + 1, 0, sizeof(unsigned long long), st);
+  if (e == hipSuccess) e = launch_prep(b->t, in, num_dags, num_cus, (int32_t)max_n, b->err, st);
+  unsigned long long errw[2] = {~0ull, 0};
+  if (e == hipSuccess) e = hipMemcpyAsync(errw, b->err, sizeof errw, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  dev_release(stage, stage_size, device);
+  if (e != hipSuccess) {
+    batch_free(b);
+    return hip_fail(e, "preprocessing");
+  }
+  const unsigned long long err = errw[0];
+  b->small_loads = errw[1] < (1ull << 22);
+  if (err != ~0ull) {
+    const long long d = (long long)(err >> 8);
+    const unsigned code = (unsigned)(err & 0xFF);
+    batch_free(b);
+    switch (code) {
+      case PREP_E_CYCLE: return fail(DAGBOUND_E_CYCLE, "DAG %lld has a cycle or a self-loop", d);
+      case PREP_E_RANGE: return fail(DAGBOUND_E_RANGE, "DAG %lld: node id, load or parallelism out of range", d);
+      case PREP_E_DUP: return fail(DAGBOUND_E_DUP_EDGE, "DAG %lld lists an edge twice", d);
+      case PREP_E_OVERFLOW: return fail(DAGBOUND_E_OVERFLOW, "DAG %lld: summed load reaches 2^40", d);
+      default: return fail(DAGBOUND_E_DEVICE, "DAG %lld: internal preprocessing error %u", d, code);
+    }
+  }
+  // Checked after validation, so an invalid DAG reports its own error first.
+  if (sweep_lds_need((int)max_n, (int)b->max_e) > LDS_LIMIT) {
+    batch_free(b);
+    return fail(DAGBOUND_E_UNSUPPORTED,
+                "largest DAG (%lld nodes, %lld edges) exceeds the evaluation kernel's LDS budget",
+                (long long)max_n, (long long)max_e);
+  }
+  *out = b;
+  return DAGBOUND_OK;
+}
+
+dagbound_status dagbound_set_allocations(dagbound_batch* b, int32_t K, uint32_t mode,
+                                         const uint8_t* alloc, uint64_t seed, uint32_t ptr_kind) {
+  g_err.clear();
+  if (!b) return fail(DAGBOUND_E_ARG, "batch is NULL");
+  if (K < 1 || K > DAGBOUND_MAX_CANDIDATES) return fail(DAGBOUND_E_ARG, "K = %d outside [1, %d]", K, DAGBOUND_MAX_CANDIDATES);
+  if (mode > DAGBOUND_ALLOC_SEEDED) return fail(DAGBOUND_E_ARG, "bad mode %u", mode);
+  if (ptr_kind > DAGBOUND_PTR_DEVICE) return fail(DAGBOUND_E_ARG, "bad ptr_kind %u", ptr_kind);
+  DeviceGuard g(b->device);
+  if (mode == DAGBOUND_ALLOC_EXPLICIT) {
+    if (b->tn > 0 && !alloc) return fail(DAGBOUND_E_ARG, "alloc is NULL");
+    const size_t bytes = (size_t)K * (size_t)b->tn;
+    if (ptr_kind == DAGBOUND_PTR_HOST && bytes > 0) {
+      if (b->alloc_owned_size < bytes) {
+        dev_release(b->alloc_owned, b->alloc_owned_size, b->device);
+        b->alloc_owned = nullptr;
+        b->alloc_owned_size = bytes;
+        hipError_t e = dev_alloc(&b->alloc_owned, &b->alloc_owned_size, b->device);
+        if (e != hipSuccess) {
+          b->alloc_owned = nullptr;
+          b->alloc_owned_size = 0;
+          b->has_alloc = false;
+          return hip_fail(e, "allocating candidate bytes");
+        }
+      }
+      hipError_t e = hipMemcpy(b->alloc_owned, alloc, bytes, hipMemcpyHostToDevice);
+      if (e != hipSuccess) {
+        b->has_alloc = false;
+        return hip_fail(e, "copying candidate bytes");
+      }
+      b->alloc = (const uint8_t*)b->alloc_owned;
+    } else {
+      b->alloc = alloc;
+    }
+  } else {
+    b->alloc = nullptr;
+    b->seed = seed;
+  }
+  const size_t tiles = (size_t)b->D * (size_t)((K + 63) / 64);
+  const size_t need = 512 + tiles * 4;
+  if (b->ovf_block_size < need) {
+    dev_release(b->ovf_block, b->ovf_block_size, b->device);
+    b->ovf_block = nullptr;
+    b->ovf_block_size = need;
+    hipError_t e = dev_alloc(&b->ovf_block, &b->ovf_block_size, b->device);
+    if (e != hipSuccess) {
+      b->ovf_block = nullptr;
+      b->ovf_block_size = 0;
+      b->has_alloc = false;
+      return hip_fail(e, "allocating evaluation scratch");
+    }
+  }
+  Carve oc(b->ovf_block);
+  b->ovf_count = oc.take<uint32_t>(1);
+  b->ovf_list = oc.take<uint32_t>(tiles);
+  b->K = K;
+  b->mode = mode;
+  b->has_alloc = true;
+  b->alloc_gen++;
+  return DAGBOUND_OK;
+}
+
+dagbound_status dagbound_eval_bounds(dagbound_batch* b, int64_t* bounds, int64_t* cp_term,
+                                     int64_t* intf_term, uint32_t ptr_kind, void* hip_stream) {
+  g_err.clear();
+  if (!b) return fail(DAGBOUND_E_ARG, "batch is NULL");
+  if (ptr_kind > DAGBOUND_PTR_DEVICE) return fail(DAGBOUND_E_ARG, "bad ptr_kind %u", ptr_kind);
+  if (!b->has_alloc) return fail(DAGBOUND_E_STATE, "set_allocations has not been called");
+  const size_t n = (size_t)b->D * (size_t)b->K;
+  if (!bounds && n > 0) return fail(DAGBOUND_E_ARG, "bounds is NULL");
+  DeviceGuard g(b->device);
+  hipStream_t st = (hipStream_t)hip_stream;
+  SweepArgs a = sweep_args(b);
+  void* tmp = nullptr;
+  size_t tmp_size = 0;
+  hipError_t e = hipSuccess;
+  if (ptr_kind == DAGBOUND_PTR_HOST && n > 0) {
+    tmp_size = 3 * 256 + n * 8 * (1 + (cp_term != nullptr) + (intf_term != nullptr));
+    e = dev_alloc(&tmp, &tmp_size, b->device);
+    if (e != hipSuccess) return hip_fail(e, "allocating output staging");
+    Carve c(tmp);
+    a.bounds = c.take<int64_t>(n);
+    a.cp = cp_term ? c.take<int64_t>(n) : nullptr;
+    a.intf = intf_term ? c.take<int64_t>(n) : nullptr;
+  } else {
+    a.bounds = bounds;
+    a.cp = cp_term;
+    a.intf = intf_term;
+  }
+  a.best = b->best;
+  e = launch_sweep(a, st);
+  if (e == hipSuccess && ptr_kind == DAGBOUND_PTR_HOST && n > 0) {
+    e = hipMemcpyAsync(bounds, a.bounds, n * 8, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess && cp_term) e = hipMemcpyAsync(cp_term, a.cp, n * 8, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess && intf_term) e = hipMemcpyAsync(intf_term, a.intf, n * 8, hipMemcpyDeviceToHost, st);
+  }
+  if (e == hipSuccess && (ptr_kind == DAGBOUND_PTR_HOST || !st)) e = hipStreamSynchronize(st);
+  if (tmp) {
+    if (e != hipSuccess) (void)hipDeviceSynchronize();
+    dev_release(tmp, tmp_size, b->device);
+  }
+  if (e != hipSuccess) {
+    b->best_gen = ~0ull;
+    return hip_fail(e, "evaluating bounds");
+  }
+  b->best_gen = b->alloc_gen;
+  return DAGBOUND_OK;
+}
+
+dagbound_status dagbound_best_allocation(dagbound_batch* b, uint32_t search, int32_t top_k,
+                                         const dagbound_model* model, int32_t* best_idx,
+                                         int64_t* best_bound, uint32_t ptr_kind, void* hip_stream) {
+  g_err.clear();
+  (void)top_k;
+  if (!b) return fail(DAGBOUND_E_ARG, "batch is NULL");
+  if ((!best_idx || !best_bound) && b->D > 0) return fail(DAGBOUND_E_ARG, "best_idx/best_bound is NULL");
+  if (ptr_kind > DAGBOUND_PTR_DEVICE) return fail(DAGBOUND_E_ARG, "bad ptr_kind %u", ptr_kind);
+  if (search == DAGBOUND_SEARCH_SURROGATE) {
+    if (!model) return fail(DAGBOUND_E_ARG, "surrogate search needs a model");
+    return fail(DAGBOUND_E_UNSUPPORTED, "surrogate search is not available in this build");
+  }
+  if (search != DAGBOUND_SEARCH_EXHAUSTIVE) return fail(DAGBOUND_E_ARG, "bad search %u", search);
+  if (!b->has_alloc) return fail(DAGBOUND_E_STATE, "set_allocations has not been called");
+  DeviceGuard g(b->device);
+  hipStream_t st = (hipStream_t)hip_stream;
+  hipError_t e = hipSuccess;
+  if (b->best_gen != b->alloc_gen) {
+    SweepArgs a = sweep_args(b);
+    a.best = b->best;
+    e = launch_sweep(a, st);
+    if (e != hipSuccess) {
+      b->best_gen = ~0ull;
+      return hip_fail(e, "evaluating bounds");
+    }
+    b->best_gen = b->alloc_gen;
+  }
+  void* tmp = nullptr;
+  size_t tmp_size = 0;
+  int32_t* oi = best_idx;
+  int64_t* ob = best_bound;
+  if (ptr_kind == DAGBOUND_PTR_HOST && b->D > 0) {
+    tmp_size = 512 + (size_t)b->D * 12;
+    e = dev_alloc(&tmp, &tmp_size, b->device);
+    if (e != hipSuccess) return hip_fail(e, "allocating output staging");
+    Carve c(tmp);
+    ob = c.take<int64_t>(b->D);
+    oi = c.take<int32_t>(b->D);
+  }
+  e = launch_best_final(b->best, b->D, oi, ob, st);
+  if (e == hipSuccess && ptr_kind == DAGBOUND_PTR_HOST && b->D > 0) {
+    e = hipMemcpyAsync(best_idx, oi, (size_t)b->D * 4, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(best_bound, ob, (size_t)b->D * 8, hipMemcpyDeviceToHost, st);
+  }
+  if (e == hipSuccess && (ptr_kind == DAGBOUND_PTR_HOST || !st)) e = hipStreamSynchronize(st);
+  if (tmp) {
+    if (e != hipSuccess) (void)hipDeviceSynchronize();
+    dev_release(tmp, tmp_size, b->device);
+  }
+  if (e != hipSuccess) return hip_fail(e, "selecting best candidates");
+  return DAGBOUND_OK;
+}
+
+dagbound_status dagbound_get_division(dagbound_batch* b, int32_t d, int64_t* wanc,
+                                      int32_t* group_of, int32_t* order, int32_t* num_groups) {
+  g_err.clear();
+  if (!b) return fail(DAGBOUND_E_ARG, "batch is NULL");
+  if (d < 0 || d >= b->D) return fail(DAGBOUND_E_ARG, "DAG index %d outside [0, %d)", d, b->D);
+  DeviceGuard g(b->device);
+  const int64_t n0 = b->node_off[d];
+  const int n = (int)(b->node_off[d + 1] - n0);
+  std::vector<uint16_t> gl(n), inv(n);
+  std::vector<int64_t> w(n);
+  int32_t ng = 0;
+  hipError_t e = hipDeviceSynchronize();
+  if (e == hipSuccess && n > 0) e = hipMemcpy(gl.data(), b->t.gl + n0, n * 2, hipMemcpyDeviceToHost);
+  if (e == hipSuccess && n > 0) e = hipMemcpy(inv.data(), b->t.inv + n0, n * 2, hipMemcpyDeviceToHost);
+  if (e == hipSuccess && n > 0) e = hipMemcpy(w.data(), b->t.wanc + n0, n * 8, hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = hipMemcpy(&ng, b->t.ngroups + d, 4, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e, "reading division tables");
+  std::vector<int32_t> perm(n);
+  for (int v = 0; v < n; v++) perm[inv[v]] = v;
+  int gi = 0;
+  for (int i = 0; i < n; i++) {
+    const int v = perm[gl[i] & 0x7FFF];
+    if (order) order[i] = v;
+    if (group_of) group_of[v] = gi;
+    if (gl[i] & 0x8000) gi++;
+  }
+  if (wanc) std::copy(w.begin(), w.end(), wanc);
+  if (num_groups) *num_groups = ng;
+  return DAGBOUND_OK;
+}
+
+dagbound_status dagbound_set_tuning(dagbound_batch* b, const char* key, int64_t value) {
+  g_err.clear();
+  if (!b || !key) return fail(DAGBOUND_E_ARG, "batch or key is NULL");
+  if (!strcmp(key, "residual_slots")) {
+    if (value < 1 || value > RES_SLOTS) return fail(DAGBOUND_E_ARG, "residual_slots outside [1, %d]", RES_SLOTS);
+    b->res_slots = (int32_t)value;
+  } else if (!strcmp(key, "eval_path")) {
+    if (value != EVAL_PATH_AUTO && value != EVAL_PATH_GLOBAL) return fail(DAGBOUND_E_ARG, "eval_path must be 0 or 1");
+    b->eval_path = (int32_t)value;
+  } else {
+    return fail(DAGBOUND_E_ARG, "unknown tuning key '%s'", key);
+  }
+  b->best_gen = ~0ull;
+  return DAGBOUND_OK;
+}
+
+void dagbound_destroy_batch(dagbound_batch* b) { batch_free(b); }
+
+}  // extern "C"

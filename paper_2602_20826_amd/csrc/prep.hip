@@ -1,0 +1,392 @@
+// Allocation-independent preprocessing on gfx950: input validation, ancestor
+// closure and W^anc (Eq. 2), the join-node list Theta and blocks (Eq. 3),
+// the in-block forests whose root-to-leaf paths are the local complete paths
+// (Eq. 4), and the balanced groups of Algorithm 1 (Rules 1 and 2).
+//
+// One 64-lane wavefront per DAG.  Node sets are bitsets of NW 64-bit words in
+// LDS (NW = ceil(N_d / 64)).  The tables it writes are indexed by sigma rank,
+// the order of descending W^anc with ties to the smaller local id; that order
+// is the Top_M order of Algorithm 1 and the launch order of parallel nodes in
+// Section 4.1, so the evaluation kernel never sorts.
+#include <climits>
+
+#include "internal.h"
+
+namespace dagbound {
+namespace {
+
+constexpr int WAVE = 64;
+
+__device__ inline int wave_min_i32(int x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x = min(x, __shfl_xor(x, o));
+  return x;
+}
+__device__ inline uint32_t wave_max_u32(uint32_t x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x = max(x, (uint32_t)__shfl_xor((int)x, o));
+  return x;
+}
+__device__ inline uint32_t wave_sum_u32(uint32_t x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x += (uint32_t)__shfl_xor((int)x, o);
+  return x;
+}
+__device__ inline uint32_t wave_incl_scan_u32(uint32_t x, int lane) {
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    uint32_t y = (uint32_t)__shfl_up((int)x, o);
+    if (lane >= o) x += y;
+  }
+  return x;
+}
+__device__ inline uint64_t lanes_below(int lane) { return lane ? (~0ull >> (64 - lane)) : 0ull; }
+
+// Bytes of dynamic LDS the kernel carves for NW words per bitset.
+__host__ __device__ constexpr size_t prep_lds_bytes(int NW) {
+  return (size_t)NW * 64 * NW * 8 * 2   // pred, anc bitsets
+         + (size_t)NW * 64 * 8          // wanc
+         + (size_t)NW * 8 + 8           // done bitset, summed load
+         + (size_t)NW * 64 * 4 * 6      // wcet, par, indeg, outdeg/cursor, block, parent
+         + 8 * 4                        // misc scalars
+         + (size_t)NW * 64 * 2 * 3      // sig, perm, theta
+         + (size_t)NW * 64 * 2;         // state, removed bytes
+}
+
+template <int NW>
+__global__ __launch_bounds__(64) void k_prep(Tables t, PrepInputs in, int32_t M,
+                                            unsigned long long* err) {
+  constexpr int NMAX = NW * 64;
+  extern __shared__ __align__(16) unsigned char smem[];
+  uint64_t* s_pred = (uint64_t*)smem;                // [NMAX][NW]: predecessors of v
+  uint64_t* s_anc = s_pred + NMAX * NW;              // [NMAX][NW]: ance(v)
+  int64_t* s_wanc = (int64_t*)(s_anc + NMAX * NW);   // [NMAX]
+  uint64_t* s_done = (uint64_t*)(s_wanc + NMAX);     // [NW]
+  unsigned long long* s_sum = (unsigned long long*)(s_done + NW);
+  uint32_t* s_wcet = (uint32_t*)(s_sum + 1);         // [NMAX]
+  uint32_t* s_par = s_wcet + NMAX;                   // [NMAX] p, saturated at 2^31-1
+  uint32_t* s_indeg = s_par + NMAX;
+  uint32_t* s_cursor = s_indeg + NMAX;               // out-degree, then fill cursor
+  int32_t* s_block = (int32_t*)(s_cursor + NMAX);
+  int32_t* s_parent = s_block + NMAX;
+  uint32_t* s_misc = (uint32_t*)(s_parent + NMAX);   // [0] error code, [1] theta count
+  uint16_t* s_sig = (uint16_t*)(s_misc + 8);         // sigma rank of local id
+  uint16_t* s_perm = s_sig + NMAX;                   // local id of sigma rank
+  uint16_t* s_theta = s_perm + NMAX;                 // join nodes in Theta order
+  uint8_t* s_state = (uint8_t*)(s_theta + NMAX);     // closure state: 0 open, 1 done, 2 new
+  uint8_t* s_removed = s_state + NMAX;               // grouped already (by local id)
+
+  const int d = blockIdx.x;
+  const int lane = threadIdx.x;
+  const int64_t n0 = t.node_off[d];
+  const int N = (int)(t.node_off[d + 1] - n0);
+  const int64_t e0 = t.edge_off[d];
+  const int64_t E = t.edge_off[d + 1] - e0;
+
+  if (lane == 0) { s_misc[0] = 0; s_misc[1] = 0; *s_sum = 0; }
+  for (int i = lane; i < N * NW; i += WAVE) { s_pred[i] = 0; s_anc[i] = 0; }
+  for (int w = lane; w < NW; w += WAVE) s_done[w] = 0;
+  for (int v = lane; v < N; v += WAVE) {
+    s_indeg[v] = 0; s_cursor[v] = 0; s_state[v] = 0; s_removed[v] = 0;
+  }
+  __syncthreads();
+
+  // Task model (Section 2.1): loads and parallelism.
+  uint32_t wmax = 0;
+  for (int v = lane; v < N; v += WAVE) {
+    int64_t w = in.wcet[n0 + v];
+    int32_t p = in.par[n0 + v];
+    if (w < 1 || w > 0x7fffffffLL || p < 1) { atomicCAS(&s_misc[0], 0u, (uint32_t)PREP_E_RANGE); w = 1; p = 1; }
+    s_wcet[v] = (uint32_t)w;
+    s_par[v] = (uint32_t)p;
+    atomicAdd(s_sum, (unsigned long long)w);
+    wmax = max(wmax, (uint32_t)w);
+  }
+  wmax = wave_max_u32(wmax);
+  if (lane == 0 && N > 0) atomicMax(&err[1], (unsigned long long)wmax);
+  // Edges: range, self-loop, duplicates (an LDS bitset of predecessors).
+  for (int64_t k = lane; k < E; k += WAVE) {
+    int32_t u = in.src[e0 + k], v = in.dst[e0 + k];
+    if (u < 0 || u >= N || v < 0 || v >= N) { atomicCAS(&s_misc[0], 0u, (uint32_t)PREP_E_RANGE); continue; }
+    if (u == v) { atomicCAS(&s_misc[0], 0u, (uint32_t)PREP_E_CYCLE); continue; }
+    uint64_t bit = 1ull << (u & 63);
+    uint64_t old = atomicOr((unsigned long long*)&s_pred[v * NW + (u >> 6)], (unsigned long long)bit);
+    if (old & bit) { atomicCAS(&s_misc[0], 0u, (uint32_t)PREP_E_DUP); continue; }
+    atomicAdd(&s_indeg[v], 1u);
+    atomicAdd(&s_cursor[u], 1u);
+  }
+  __syncthreads();
+  if (s_misc[0] == 0 && *s_sum >= (1ull << 40)) {
+    if (lane == 0) s_misc[0] = PREP_E_OVERFLOW;
+  }
+  __syncthreads();
+  if (s_misc[0]) {
+    if (lane == 0) atomicMin(err, ((unsigned long long)d << 8) | s_misc[0]);
+    return;
+  }
+
+  // Ancestor closure in topological waves: a node whose predecessors are all
+  // closed takes ance(v) = union of (ance(u) + u) over its predecessors u.
+  for (;;) {
+    for (int v = lane; v < N; v += WAVE) {
+      if (s_state[v]) continue;
+      bool ready = true;
+#pragma unroll
+      for (int w = 0; w < NW; w++) ready = ready && !(s_pred[v * NW + w] & ~s_done[w]);
+      if (!ready) continue;
+      uint64_t acc[NW];
+#pragma unroll
+      for (int w = 0; w < NW; w++) acc[w] = s_pred[v * NW + w];
+#pragma unroll
+      for (int w = 0; w < NW; w++) {
+        uint64_t b = s_pred[v * NW + w];
+        while (b) {
+          int u = w * 64 + __builtin_ctzll(b);
+          b &= b - 1;
+#pragma unroll
+          for (int x = 0; x < NW; x++) acc[x] |= s_anc[u * NW + x];
+        }
+      }
+#pragma unroll
+      for (int w = 0; w < NW; w++) s_anc[v * NW + w] = acc[w];
+      s_state[v] = 2;
+    }
+    __syncthreads();
+    uint32_t fresh = 0;
+    for (int v = lane; v < N; v += WAVE)
+      if (s_state[v] == 2) {
+        s_state[v] = 1;
+        atomicOr((unsigned long long*)&s_done[v >> 6], 1ull << (v & 63));
+        fresh++;
+      }
+    fresh = wave_sum_u32(fresh);
+    __syncthreads();
+    if (!fresh) break;
+  }
+  {
+    uint32_t closed = 0;
+    for (int w = lane; w < NW; w += WAVE) closed += __popcll(s_done[w]);
+    closed = wave_sum_u32(closed);
+    if ((int)closed != N) {  // some node never became ready: a cycle
+      if (lane == 0) atomicMin(err, ((unsigned long long)d << 8) | PREP_E_CYCLE);
+      return;
+    }
+  }
+
+  // Eq. 2: W^anc(v) = C_hat_v + sum of C_hat over ance(v).
+  for (int v = lane; v < N; v += WAVE) {
+    int64_t sum = s_wcet[v];
+#pragma unroll
+    for (int w = 0; w < NW; w++) {
+      uint64_t b = s_anc[v * NW + w];
+      while (b) { sum += s_wcet[w * 64 + __builtin_ctzll(b)]; b &= b - 1; }
+    }
+    s_wanc[v] = sum;
+  }
+  __syncthreads();
+
+  // Sigma rank (descending W^anc, ties to the smaller id) and the Theta rank
+  // of join nodes (in-degree >= 2; ascending W^anc, ties to the smaller id).
+  for (int v = lane; v < N; v += WAVE) {
+    const int64_t wv = s_wanc[v];
+    const bool join = s_indeg[v] >= 2;
+    int r = 0, th = 0;
+    for (int u = 0; u < N; u++) {
+      const int64_t wu = s_wanc[u];
+      r += (wu > wv) | ((wu == wv) & (u < v));
+      th += (s_indeg[u] >= 2) & ((wu < wv) | ((wu == wv) & (u < v)));
+    }
+    s_sig[v] = (uint16_t)r;
+    s_perm[r] = (uint16_t)v;
+    if (join) { s_theta[th] = (uint16_t)v; atomicAdd(&s_misc[1], 1u); }
+  }
+  __syncthreads();
+  const int nth = (int)s_misc[1];
+
+  // Eq. 3: B_k = ance(theta_k) minus earlier blocks, i.e. v lands in the
+  // first block (in Theta order) whose join node has v as an ancestor; the
+  // rest form the residual block (index nth).
+  for (int v = lane; v < N; v += WAVE) {
+    int b = nth;
+    for (int k = 0; k < nth; k++) {
+      const int th = s_theta[k];
+      if ((s_anc[th * NW + (v >> 6)] >> (v & 63)) & 1) { b = k; break; }
+    }
+    s_block[v] = b;
+  }
+  __syncthreads();
+  // In-block parent: a node has at most one predecessor in its own block, so
+  // each block is a forest whose root-to-leaf paths are its local complete
+  // paths (Eq. 4).
+  for (int v = lane; v < N; v += WAVE) {
+    int parent = -1, cnt = 0;
+#pragma unroll
+    for (int w = 0; w < NW; w++) {
+      uint64_t b = s_pred[v * NW + w];
+      while (b) {
+        int u = w * 64 + __builtin_ctzll(b);
+        b &= b - 1;
+        if (s_block[u] == s_block[v]) { parent = u; cnt++; }
+      }
+    }
+    if (cnt > 1) atomicCAS(&s_misc[0], 0u, (uint32_t)PREP_E_INTERNAL);
+    s_parent[v] = parent;
+  }
+  __syncthreads();
+  if (s_misc[0]) {
+    if (lane == 0) atomicMin(err, ((unsigned long long)d << 8) | s_misc[0]);
+    return;
+  }
+
+  // Algorithm 1, balanced groups.  Blocks are taken in order; within the
+  // current block the heads of the local complete paths are the ungrouped
+  // nodes whose in-block parent is grouped (or absent).  Lane l holds sigma
+  // ranks l, l+64, ...; heads are picked in sigma order (Top_M, Rule 1) and
+  // Rule 2 keeps only the first node of largest m^max = min(p, C_hat) when
+  // that reaches M.
+  bool grouped[NW];
+#pragma unroll
+  for (int k = 0; k < NW; k++) grouped[k] = false;
+  uint16_t* gl = t.gl + n0;
+  int gpos = 0, ng = 0;
+  for (;;) {
+    int bmin = INT_MAX;
+#pragma unroll
+    for (int k = 0; k < NW; k++) {
+      const int s = k * 64 + lane;
+      if (s < N && !grouped[k]) bmin = min(bmin, s_block[s_perm[s]]);
+    }
+    bmin = wave_min_i32(bmin);
+    if (bmin == INT_MAX) break;
+    bool head[NW];
+    uint64_t hb[NW];
+    int nh = 0;
+#pragma unroll
+    for (int k = 0; k < NW; k++) {
+      const int s = k * 64 + lane;
+      head[k] = false;
+      if (s < N && !grouped[k]) {
+        const int v = s_perm[s];
+        if (s_block[v] == bmin) {
+          const int p = s_parent[v];
+          head[k] = (p < 0) || s_removed[p];
+        }
+      }
+      hb[k] = __ballot(head[k]);
+      nh += __popcll(hb[k]);
+    }
+    const int take = min(nh, (int)M);
+    bool sel[NW];
+    uint64_t sb[NW];
+    int before = 0;
+#pragma unroll
+    for (int k = 0; k < NW; k++) {
+      sel[k] = head[k] && (before + __popcll(hb[k] & lanes_below(lane)) < take);
+      sb[k] = __ballot(sel[k]);
+      before += __popcll(hb[k]);
+    }
+    if (take > 1) {
+      uint32_t mx = 0;
+#pragma unroll
+      for (int k = 0; k < NW; k++)
+        if (sel[k]) {
+          const int v = s_perm[k * 64 + lane];
+          mx = max(mx, min(s_par[v], s_wcet[v]));
+        }
+      mx = wave_max_u32(mx);
+      if (mx >= (uint32_t)M) {
+        bool found = false;
+#pragma unroll
+        for (int k = 0; k < NW; k++) {
+          bool hit = false;
+          if (sel[k]) {
+            const int v = s_perm[k * 64 + lane];
+            hit = min(s_par[v], s_wcet[v]) == mx;
+          }
+          uint64_t hbits = __ballot(hit);
+          uint64_t keep = 0;
+          if (!found && hbits) { keep = hbits & (~hbits + 1); found = true; }
+          sb[k] = keep;
+          sel[k] = (keep >> lane) & 1;
+        }
+      }
+    }
+    int cnt = 0;
+#pragma unroll
+    for (int k = 0; k < NW; k++) cnt += __popcll(sb[k]);
+    int base = 0;
+#pragma unroll
+    for (int k = 0; k < NW; k++) {
+      if (sel[k]) {
+        const int s = k * 64 + lane;
+        const int pos = gpos + base + __popcll(sb[k] & lanes_below(lane));
+        gl[pos] = (uint16_t)(s | (pos == gpos + cnt - 1 ? 0x8000 : 0));
+        grouped[k] = true;
+        s_removed[s_perm[s]] = 1;
+      }
+      base += __popcll(sb[k]);
+    }
+    gpos += cnt;
+    ng++;
+    __syncthreads();
+  }
+  if (lane == 0) t.ngroups[d] = ng;
+
+  // Tables by sigma rank.
+  for (int s = lane; s < N; s += WAVE) {
+    const int v = s_perm[s];
+    t.wc[n0 + s] = s_wcet[v];
+    t.pp[n0 + s] = (uint16_t)min(s_par[v], (uint32_t)M);
+    t.indeg[n0 + s] = (uint16_t)s_indeg[v];
+  }
+  for (int v = lane; v < N; v += WAVE) {
+    t.inv[n0 + v] = s_sig[v];
+    t.wanc[n0 + v] = s_wanc[v];
+  }
+  // Successor lists in sigma order: offsets by an exclusive scan of the
+  // out-degrees, then each edge drops its head's sigma rank into its tail's
+  // list.
+  uint32_t* soff = t.soff + n0 + d;
+  uint32_t carry = 0;
+  for (int b = 0; b < N; b += WAVE) {
+    const int s = b + lane;
+    const uint32_t x = s < N ? s_cursor[s_perm[s]] : 0u;
+    const uint32_t incl = wave_incl_scan_u32(x, lane);
+    if (s < N) soff[s] = carry + incl - x;
+    carry += (uint32_t)__shfl((int)incl, 63);
+  }
+  if (lane == 0) soff[N] = carry;
+  __syncthreads();
+  for (int s = lane; s < N; s += WAVE) s_cursor[s_perm[s]] = soff[s];
+  __syncthreads();
+  for (int64_t k = lane; k < E; k += WAVE) {
+    const int32_t u = in.src[e0 + k], v = in.dst[e0 + k];
+    const uint32_t pos = atomicAdd(&s_cursor[u], 1u);
+    t.succ[e0 + pos] = s_sig[v];
+  }
+}
+
+template <int NW>
+hipError_t launch_prep_nw(const Tables& t, const PrepInputs& in, int32_t D, int32_t M,
+                          unsigned long long* err, hipStream_t stream) {
+  const size_t lds = prep_lds_bytes(NW);
+  hipError_t e = hipFuncSetAttribute((const void*)k_prep<NW>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_prep<NW>, dim3(D), dim3(64), lds, stream, t, in, M, err);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_prep(const Tables& t, const PrepInputs& in, int32_t D, int32_t M, int32_t max_n,
+                       unsigned long long* err, hipStream_t stream) {
+  if (D <= 0) return hipSuccess;
+  if (max_n <= 64) return launch_prep_nw<1>(t, in, D, M, err, stream);
+  if (max_n <= 128) return launch_prep_nw<2>(t, in, D, M, err, stream);
+  if (max_n <= 256) return launch_prep_nw<4>(t, in, D, M, err, stream);
+  if (max_n <= 512) return launch_prep_nw<8>(t, in, D, M, err, stream);
+  return hipErrorInvalidValue;
+}
+
+}  // namespace dagbound

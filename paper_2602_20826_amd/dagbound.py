@@ -1,0 +1,230 @@
+"""Python binding of libdagbound (include/dagbound.h): argument marshalling only.
+
+Every step of the bound runs in the library's gfx950 kernels; this module
+turns numpy arrays (host memory) or torch tensors (device memory of the
+current HIP device, or host) into pointers and status codes into exceptions.
+It fails loudly when the library is not built: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Any, Optional, Sequence, Tuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdagbound.so")
+
+OK, E_ARG, E_CYCLE, E_RANGE, E_DUP_EDGE, E_OOM, E_DEVICE, E_STATE, E_OVERFLOW, E_UNSUPPORTED = (
+    0, -1, -2, -3, -4, -5, -6, -7, -8, -9)
+PTR_HOST, PTR_DEVICE = 0, 1
+ALLOC_EXPLICIT, ALLOC_SEEDED = 0, 1
+SEARCH_EXHAUSTIVE, SEARCH_SURROGATE = 0, 1
+MAX_NODES_PER_DAG = 512
+MAX_CANDIDATES = 1 << 22
+
+# Every symbol include/dagbound.h declares.
+EXPORTS = (
+    "dagbound_create_batch", "dagbound_set_allocations", "dagbound_eval_bounds",
+    "dagbound_best_allocation", "dagbound_get_division", "dagbound_set_tuning",
+    "dagbound_destroy_batch",
+    "dagbound_last_error", "dagbound_version",
+)
+
+_lib: Optional[ctypes.CDLL] = None
+
+
+class DagboundError(RuntimeError):
+    def __init__(self, code: int, message: str):
+        super().__init__(f"libdagbound status {code}: {message}")
+        self.code = code
+        self.message = message
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libdagbound.so (built by paper_2602_20826_amd/build.py)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is not built; run `python -c 'import __graft_entry__ as g; g.build()'`")
+    lib = ctypes.CDLL(path)
+    P, I32, U32, U64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint32, ctypes.c_uint64
+    lib.dagbound_create_batch.restype = I32
+    lib.dagbound_create_batch.argtypes = [I32, P, P, P, P, P, P, I32, U32, P, ctypes.POINTER(P)]
+    lib.dagbound_set_allocations.restype = I32
+    lib.dagbound_set_allocations.argtypes = [P, I32, U32, P, U64, U32]
+    lib.dagbound_eval_bounds.restype = I32
+    lib.dagbound_eval_bounds.argtypes = [P, P, P, P, U32, P]
+    lib.dagbound_best_allocation.restype = I32
+    lib.dagbound_best_allocation.argtypes = [P, U32, I32, P, P, P, U32, P]
+    lib.dagbound_get_division.restype = I32
+    lib.dagbound_get_division.argtypes = [P, I32, P, P, P, P]
+    lib.dagbound_set_tuning.restype = I32
+    lib.dagbound_set_tuning.argtypes = [P, ctypes.c_char_p, ctypes.c_int64]
+    lib.dagbound_destroy_batch.restype = None
+    lib.dagbound_destroy_batch.argtypes = [P]
+    lib.dagbound_last_error.restype = ctypes.c_char_p
+    lib.dagbound_last_error.argtypes = []
+    lib.dagbound_version.restype = ctypes.c_char_p
+    lib.dagbound_version.argtypes = []
+    _lib = lib
+    return lib
+
+
+def last_error() -> str:
+    return load_library().dagbound_last_error().decode()
+
+
+def version() -> str:
+    return load_library().dagbound_version().decode()
+
+
+def _check(rc: int) -> None:
+    if rc != OK:
+        raise DagboundError(rc, last_error())
+
+
+def _is_torch(x: Any) -> bool:
+    return type(x).__module__.startswith("torch")
+
+
+_NP = {"int64": np.int64, "int32": np.int32, "uint8": np.uint8}
+
+
+def _marshal(arrays: Sequence[Tuple[Any, str]]):
+    """Pointers for (array, dtype name) pairs; all must live in one kind of
+    memory.  Returns (pointers, ptr_kind, keepalive)."""
+    kinds = set()
+    ptrs = []
+    keep = []
+    for a, dt in arrays:
+        if a is None:
+            ptrs.append(None)
+            continue
+        if _is_torch(a):
+            import torch
+
+            want = getattr(torch, dt)
+            if a.dtype != want:
+                raise TypeError(f"expected a {dt} tensor, got {a.dtype}")
+            if not a.is_contiguous():
+                raise ValueError("tensors must be contiguous")
+            kinds.add(PTR_DEVICE if a.is_cuda else PTR_HOST)
+            ptrs.append(a.data_ptr() if a.numel() else None)
+            keep.append(a)
+        else:
+            arr = np.asarray(a)
+            if arr.dtype != _NP[dt]:
+                raise TypeError(f"expected {dt}, got {arr.dtype}")
+            if not arr.flags.c_contiguous:
+                raise ValueError("arrays must be C-contiguous")
+            kinds.add(PTR_HOST)
+            ptrs.append(arr.ctypes.data if arr.size else None)
+            keep.append(arr)
+    if len(kinds) > 1:
+        raise ValueError("all arrays of one call must be in the same memory (host or device)")
+    return ptrs, (kinds.pop() if kinds else PTR_HOST), keep
+
+
+def _stream_ptr(stream) -> Optional[int]:
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return stream
+    return int(stream.cuda_stream)
+
+
+class Batch:
+    """Owning handle of a dagbound_batch."""
+
+    def __init__(self, handle: int, num_dags: int, node_off_host: np.ndarray):
+        self.handle = handle
+        self.num_dags = num_dags
+        self.node_off = node_off_host
+        self.K = 0
+
+    def close(self) -> None:
+        if self.handle:
+            load_library().dagbound_destroy_batch(ctypes.c_void_p(self.handle))
+            self.handle = 0
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def create_batch(node_off, edge_off, edge_src, edge_dst, wcet, max_par, num_cus: int,
+                 stream=None) -> Batch:
+    """dagbound_create_batch: ingest and preprocess a batch of DAG tasks."""
+    lib = load_library()
+    (p_no, p_eo, p_s, p_t, p_w, p_p), kind, keep = _marshal(
+        [(node_off, "int64"), (edge_off, "int64"), (edge_src, "int32"), (edge_dst, "int32"),
+         (wcet, "int64"), (max_par, "int32")])
+    num_dags = int(len(node_off)) - 1
+    out = ctypes.c_void_p()
+    _check(lib.dagbound_create_batch(num_dags, p_no, p_eo, p_s, p_t, p_w, p_p, int(num_cus), kind,
+                                     _stream_ptr(stream), ctypes.byref(out)))
+    if _is_torch(node_off):
+        no = node_off.detach().cpu().numpy()
+    else:
+        no = np.asarray(node_off)
+    return Batch(out.value, num_dags, no.astype(np.int64))
+
+
+def set_allocations(batch: Batch, K: int, mode: int = ALLOC_EXPLICIT, alloc=None, seed: int = 0) -> None:
+    """dagbound_set_allocations: explicit bytes (host array or device tensor) or a seed."""
+    lib = load_library()
+    (p_a,), kind, keep = _marshal([(alloc, "uint8")])
+    _check(lib.dagbound_set_allocations(ctypes.c_void_p(batch.handle), int(K), int(mode), p_a,
+                                        ctypes.c_uint64(seed & (2**64 - 1)), kind))
+    batch.K = int(K)
+    batch._alloc_keep = keep  # explicit device bytes are read in place later
+
+
+def eval_bounds(batch: Batch, bounds, cp_term=None, intf_term=None, stream=None) -> None:
+    """dagbound_eval_bounds: bounds[d*K + c] (+ optional terms), written in place."""
+    lib = load_library()
+    (p_b, p_c, p_i), kind, keep = _marshal([(bounds, "int64"), (cp_term, "int64"), (intf_term, "int64")])
+    _check(lib.dagbound_eval_bounds(ctypes.c_void_p(batch.handle), p_b, p_c, p_i, kind,
+                                    _stream_ptr(stream)))
+
+
+def best_allocation(batch: Batch, best_idx, best_bound, search: int = SEARCH_EXHAUSTIVE,
+                    top_k: int = 0, model=None, stream=None) -> None:
+    """dagbound_best_allocation: per-DAG argmin candidate and its bound."""
+    lib = load_library()
+    (p_i, p_b), kind, keep = _marshal([(best_idx, "int32"), (best_bound, "int64")])
+    _check(lib.dagbound_best_allocation(ctypes.c_void_p(batch.handle), int(search), int(top_k),
+                                        model, p_i, p_b, kind, _stream_ptr(stream)))
+
+
+def get_division(batch: Batch, d: int):
+    """dagbound_get_division: (wanc, group_of, order, num_groups) of DAG d."""
+    lib = load_library()
+    n = int(batch.node_off[d + 1] - batch.node_off[d])
+    wanc = np.zeros(max(n, 1), np.int64)
+    gof = np.zeros(max(n, 1), np.int32)
+    order = np.zeros(max(n, 1), np.int32)
+    ng = ctypes.c_int32(0)
+    _check(lib.dagbound_get_division(ctypes.c_void_p(batch.handle), int(d), wanc.ctypes.data,
+                                     gof.ctypes.data, order.ctypes.data, ctypes.byref(ng)))
+    return wanc[:n], gof[:n], order[:n], int(ng.value)
+
+
+def set_tuning(batch: Batch, key: str, value: int) -> None:
+    """dagbound_set_tuning: launch-plan options (never change results)."""
+    _check(load_library().dagbound_set_tuning(ctypes.c_void_p(batch.handle), key.encode(), int(value)))
+
+
+def destroy_batch(batch: Batch) -> None:
+    batch.close()
