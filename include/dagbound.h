@@ -49,7 +49,7 @@ extern "C" {
 #endif
 
 typedef struct dagbound_batch dagbound_batch; /* opaque; owns its device memory */
-typedef struct dagbound_model dagbound_model; /* opaque learned proposal (reserved) */
+typedef struct dagbound_model dagbound_model; /* opaque learned candidate proposal */
 typedef int32_t dagbound_status;
 
 enum {
@@ -154,12 +154,16 @@ dagbound_status dagbound_eval_bounds(dagbound_batch* batch, int64_t* bounds, int
  *   search     DAGBOUND_SEARCH_EXHAUSTIVE: every candidate is evaluated
  *              exactly (when dagbound_eval_bounds already ran on the current
  *              allocation set, its per-DAG minimum is reused).
- *              DAGBOUND_SEARCH_SURROGATE: reserved; returns E_UNSUPPORTED.
- *   top_k      ignored by EXHAUSTIVE.
+ *              DAGBOUND_SEARCH_SURROGATE: seeded candidates only; `model`
+ *              scores every candidate (dagbound_model_select with 32 nodes),
+ *              and candidate 0 plus the top_k best-scored ones are evaluated
+ *              exactly.  The result is exact for the candidates evaluated;
+ *              ties go to the candidate listed first (0, then by score).
+ *   top_k      SURROGATE: 1..min(63, K-1); ignored by EXHAUSTIVE.
  *   model      NULL for EXHAUSTIVE.
  *   best_idx   int32 [D]; best_bound int64 [D] (NULL only when D = 0).  An
  *              empty DAG reports candidate 0 with bound 0.
- * Errors: E_ARG, E_STATE, E_UNSUPPORTED, E_DEVICE.
+ * Errors: E_ARG, E_STATE, E_DEVICE.
  */
 dagbound_status dagbound_best_allocation(dagbound_batch* batch, uint32_t search, int32_t top_k,
                                          const dagbound_model* model, int32_t* best_idx,
@@ -191,6 +195,61 @@ dagbound_status dagbound_get_division(dagbound_batch* batch, int32_t d, int64_t*
  * Errors: E_ARG (unknown key or value).
  */
 dagbound_status dagbound_set_tuning(dagbound_batch* batch, const char* key, int64_t value);
+
+/* ------------------------------------------------------------------------
+ * Learned candidate proposal.  Not part of the paper: it ranks candidate
+ * allocations so that only the best-ranked ones need exact evaluation.
+ *
+ * Model (per DAG, N(v) = predecessors and successors of v, hidden width 128):
+ *   x_v  8 features: log2 C_hat/16, log2 min(p,M)/8, log2 W^anc/24,
+ *        log2 |group|/8, group position in [0,1], log2(1+in-degree)/6,
+ *        log2(1+out-degree)/6, C_hat / load of the node's group;
+ *   H0 = relu(X W0 + b0); G_l = mean over N(v) of H_{l-1} (0 without
+ *   neighbours); H_l = relu(H_{l-1} Ws_l + G_l Wm_l + b_l), l = 1..3;
+ *   A = H3 Wa + ba, a_v = A[v][0..2].
+ *   Score of candidate bytes r (lower = smaller predicted bound):
+ *   (1/N) sum_v a_v . (t, t^2, 1/t), t = r_v / min(p_v, M, 255).
+ * Layer GEMMs run in BF16 on the matrix cores with FP32 accumulation;
+ * parameters are FP32 (Adam).  The flat parameter vector holds W0 [8x128],
+ * b0 [128], then per layer Ws [128x128], Wm [128x128], b [128], then
+ * Wa [128x4], ba [4]; matrices row-major, input index first.
+ * Calls on one model must be ordered; the model keeps activation scratch
+ * sized for the last batch it saw.
+ */
+#define DAGBOUND_MODEL_PARAMS 100356
+
+/* New model on the current device, weights Glorot-uniform from `seed`. */
+dagbound_status dagbound_model_create(uint64_t seed, dagbound_model** out);
+void dagbound_model_destroy(dagbound_model* model);
+
+/* Host copies of the parameters (get, [DAGBOUND_MODEL_PARAMS]) and of the
+ * last gradient (grad); `set` replaces the parameters; step receives the
+ * number of optimizer steps taken.  Each pointer may be NULL. */
+dagbound_status dagbound_model_params(dagbound_model* model, float* get, const float* set, float* grad,
+                                      int64_t* step);
+
+/* Per-node head coefficients a_v (float [node_off[D]][3], the batch's node
+ * numbering).  Waits for its work. */
+dagbound_status dagbound_model_forward(dagbound_model* model, dagbound_batch* batch, float* node_out,
+                                       uint32_t ptr_kind, void* hip_stream);
+
+/* One training step on a batch whose seeded candidates (K per DAG, seed)
+ * have exact bounds `bounds` [D*K] (as dagbound_eval_bounds writes them):
+ * the loss is the mean over c >= 1 of (score_c - (ln bound_c - ln bound_0))^2;
+ * gradient by the hand-written backward pass; Adam (0.9, 0.999, 1e-8) with
+ * learning rate lr (lr = 0: gradient only).  loss receives the loss before
+ * the update.  Waits for its work. */
+dagbound_status dagbound_model_train_step(dagbound_model* model, dagbound_batch* batch, int32_t K,
+                                          uint64_t seed, const int64_t* bounds, float lr, float* loss,
+                                          uint32_t ptr_kind, void* hip_stream);
+
+/* Candidate selection for a seeded candidate set (K, seed): scores from the
+ * `nodes` (1..64) nodes of largest |a0| + |a1| + range*|a2|, then per DAG
+ * cand [D][top_k+1] = {0, the top_k smallest-scored candidates >= 1}
+ * (ties to the smaller index); scores [D*K] may be NULL.  Device pointers. */
+dagbound_status dagbound_model_select(dagbound_model* model, dagbound_batch* batch, int32_t K, uint64_t seed,
+                                      int32_t top_k, int32_t nodes, int32_t* cand, float* scores,
+                                      uint32_t ptr_kind, void* hip_stream);
 
 /* Release the batch and its device memory (waits for its work).  NULL is a
  * no-op. */

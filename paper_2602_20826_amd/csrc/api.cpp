@@ -207,6 +207,9 @@ SweepArgs sweep_args(const dagbound_batch* b) {
 
 }  // namespace
 
+dagbound_status surrogate_best(dagbound_batch* b, dagbound_model* m, int32_t top_k, int32_t* best_idx,
+                               int64_t* best_bound, uint32_t ptr_kind, hipStream_t st);
+
 extern "C" {
 
 const char* dagbound_last_error(void) { return g_err.c_str(); }
@@ -470,7 +473,12 @@ dagbound_status dagbound_best_allocation(dagbound_batch* b, uint32_t search, int
   if (ptr_kind > DAGBOUND_PTR_DEVICE) return fail(DAGBOUND_E_ARG, "bad ptr_kind %u", ptr_kind);
   if (search == DAGBOUND_SEARCH_SURROGATE) {
     if (!model) return fail(DAGBOUND_E_ARG, "surrogate search needs a model");
-    return fail(DAGBOUND_E_UNSUPPORTED, "surrogate search is not available in this build");
+    if (!b->has_alloc) return fail(DAGBOUND_E_STATE, "set_allocations has not been called");
+    if (b->mode != DAGBOUND_ALLOC_SEEDED) return fail(DAGBOUND_E_ARG, "surrogate search needs seeded candidates");
+    if (top_k < 1 || top_k > 63 || top_k >= b->K)
+      return fail(DAGBOUND_E_ARG, "top_k = %d outside [1, min(63, K-1)]", top_k);
+    return surrogate_best(b, const_cast<dagbound_model*>(model), top_k, best_idx, best_bound, ptr_kind,
+                          (hipStream_t)hip_stream);
   }
   if (search != DAGBOUND_SEARCH_EXHAUSTIVE) return fail(DAGBOUND_E_ARG, "bad search %u", search);
   if (!b->has_alloc) return fail(DAGBOUND_E_STATE, "set_allocations has not been called");
@@ -499,7 +507,7 @@ dagbound_status dagbound_best_allocation(dagbound_batch* b, uint32_t search, int
     ob = c.take<int64_t>(b->D);
     oi = c.take<int32_t>(b->D);
   }
-  e = launch_best_final(b->best, b->D, oi, ob, st);
+  e = launch_best_final(b->best, b->D, oi, ob, nullptr, 0, st);
   if (e == hipSuccess && ptr_kind == DAGBOUND_PTR_HOST && b->D > 0) {
     e = hipMemcpyAsync(best_idx, oi, (size_t)b->D * 4, hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipMemcpyAsync(best_bound, ob, (size_t)b->D * 8, hipMemcpyDeviceToHost, st);
@@ -563,3 +571,319 @@ dagbound_status dagbound_set_tuning(dagbound_batch* b, const char* key, int64_t 
 void dagbound_destroy_batch(dagbound_batch* b) { batch_free(b); }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Learned candidate proposal.
+
+struct dagbound_model {
+  int device = 0;
+  void* block = nullptr;  // parameters, gradient, Adam moments, BF16 weights
+  size_t block_size = 0;
+  float *p = nullptr, *g = nullptr, *m1 = nullptr, *m2 = nullptr;
+  __bf16 *wfwd = nullptr, *wbwd = nullptr;
+  int64_t step = 0;
+  void* ws = nullptr;  // activations for the last batch size
+  size_t ws_size = 0;
+};
+
+namespace {
+
+// Glorot-uniform initial weights from the SplitMix64 finalizer of (seed, i);
+// biases start at zero.
+void model_init_params(uint64_t seed, std::vector<float>& h) {
+  h.assign((size_t)SUR_PARAMS, 0.f);
+  auto mix = [](uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+  };
+  auto fill = [&](int64_t off, int fan_in, int fan_out) {
+    const double a = std::sqrt(6.0 / (fan_in + fan_out));
+    for (int64_t i = 0; i < (int64_t)fan_in * fan_out; i++) {
+      const double u = (double)(mix(seed ^ mix((uint64_t)(off + i))) >> 11) / 9007199254740992.0;
+      h[(size_t)(off + i)] = (float)((2.0 * u - 1.0) * a);
+    }
+  };
+  fill(SUR_OFF_W0, SUR_FIN, SUR_HID);
+  for (int l = 0; l < SUR_LAYERS; l++) {
+    fill(SUR_OFF_L1 + l * SUR_LAYER_STRIDE, 2 * SUR_HID, SUR_HID);
+    fill(SUR_OFF_L1 + l * SUR_LAYER_STRIDE + SUR_HID * SUR_HID, 2 * SUR_HID, SUR_HID);
+  }
+  fill(SUR_OFF_WA, SUR_HID, SUR_OUT);
+}
+
+// Activation workspace of a batch; returns the argument block.
+dagbound_status model_workspace(dagbound_model* m, const dagbound_batch* b, SurArgs* s) {
+  const int64_t R = b->tn, D = b->D;
+  const int64_t nchunk = (R + SUR_CHUNK - 1) / SUR_CHUNK;
+  const size_t need = 32 * 256 + (size_t)R * sur_node_bytes() + (size_t)(R + D) * 4 + (size_t)b->te * 4 +
+                      (size_t)nchunk * (256 * 128 + 128) * 4 + (size_t)D * 4;
+  if (m->ws_size < need) {
+    dev_release(m->ws, m->ws_size, m->device);
+    m->ws = nullptr;
+    m->ws_size = need;
+    hipError_t e = dev_alloc(&m->ws, &m->ws_size, m->device);
+    if (e != hipSuccess) {
+      m->ws = nullptr;
+      m->ws_size = 0;
+      return hip_fail(e, "allocating surrogate activations");
+    }
+  }
+  Carve c(m->ws);
+  *s = SurArgs{};
+  s->t = b->t;
+  s->D = b->D;
+  s->M = b->M;
+  s->max_n = b->max_n;
+  s->rows = R;
+  s->p = m->p;
+  s->g = m->g;
+  s->m1 = m->m1;
+  s->m2 = m->m2;
+  s->wfwd = m->wfwd;
+  s->wbwd = m->wbwd;
+  s->X = c.take<float>((size_t)R * SUR_FIN);
+  s->A = c.take<float>((size_t)R * SUR_OUT);
+  s->dA = c.take<float>((size_t)R * SUR_OUT);
+  for (int l = 0; l <= SUR_LAYERS; l++) s->H[l] = c.take<__bf16>((size_t)R * SUR_HID);
+  for (int l = 0; l < SUR_LAYERS; l++) s->G[l] = c.take<__bf16>((size_t)R * SUR_HID);
+  s->dZ[0] = c.take<__bf16>((size_t)R * SUR_HID);
+  s->dZ[1] = c.take<__bf16>((size_t)R * SUR_HID);
+  s->DT = c.take<float>((size_t)R * 256);
+  s->dag_of = c.take<int32_t>((size_t)R);
+  s->nboff = c.take<uint32_t>((size_t)(R + D));
+  s->nb = c.take<uint16_t>((size_t)b->te * 2);
+  s->partial = c.take<float>((size_t)nchunk * 256 * 128);
+  s->partial2 = c.take<float>((size_t)nchunk * 128);
+  s->loss_part = c.take<float>((size_t)D);
+  return DAGBOUND_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+dagbound_status dagbound_model_create(uint64_t seed, dagbound_model** out) {
+  g_err.clear();
+  if (!out) return fail(DAGBOUND_E_ARG, "out is NULL");
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
+    (void)hipGetLastError();
+    return fail(DAGBOUND_E_DEVICE, "no HIP device");
+  }
+  dagbound_model* m = new dagbound_model();
+  (void)hipGetDevice(&m->device);
+  m->block_size = 8 * 256 + (size_t)SUR_PARAMS * 4 * 4 + (size_t)SUR_LAYERS * 256 * 128 * 2 * 2;
+  hipError_t e = dev_alloc(&m->block, &m->block_size, m->device);
+  if (e != hipSuccess) {
+    delete m;
+    return hip_fail(e, "allocating the model");
+  }
+  Carve c(m->block);
+  m->p = c.take<float>(SUR_PARAMS);
+  m->g = c.take<float>(SUR_PARAMS);
+  m->m1 = c.take<float>(SUR_PARAMS);
+  m->m2 = c.take<float>(SUR_PARAMS);
+  m->wfwd = c.take<__bf16>((size_t)SUR_LAYERS * 256 * 128);
+  m->wbwd = c.take<__bf16>((size_t)SUR_LAYERS * 256 * 128);
+  std::vector<float> h;
+  model_init_params(seed, h);
+  e = hipMemcpy(m->p, h.data(), h.size() * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemset(m->g, 0, (size_t)SUR_PARAMS * 4 * 3);
+  SurArgs s{};
+  s.p = m->p;
+  s.wfwd = m->wfwd;
+  s.wbwd = m->wbwd;
+  if (e == hipSuccess) e = sur_refresh_weights(s, nullptr);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) {
+    dev_release(m->block, m->block_size, m->device);
+    delete m;
+    return hip_fail(e, "initialising the model");
+  }
+  *out = m;
+  return DAGBOUND_OK;
+}
+
+void dagbound_model_destroy(dagbound_model* m) {
+  if (!m) return;
+  {
+    DeviceGuard g(m->device);
+    (void)hipDeviceSynchronize();
+  }
+  dev_release(m->block, m->block_size, m->device);
+  dev_release(m->ws, m->ws_size, m->device);
+  delete m;
+}
+
+dagbound_status dagbound_model_params(dagbound_model* m, float* get, const float* set, float* grad,
+                                      int64_t* step) {
+  g_err.clear();
+  if (!m) return fail(DAGBOUND_E_ARG, "model is NULL");
+  DeviceGuard g(m->device);
+  hipError_t e = hipDeviceSynchronize();
+  if (e == hipSuccess && get) e = hipMemcpy(get, m->p, (size_t)SUR_PARAMS * 4, hipMemcpyDeviceToHost);
+  if (e == hipSuccess && grad) e = hipMemcpy(grad, m->g, (size_t)SUR_PARAMS * 4, hipMemcpyDeviceToHost);
+  if (e == hipSuccess && set) {
+    e = hipMemcpy(m->p, set, (size_t)SUR_PARAMS * 4, hipMemcpyHostToDevice);
+    SurArgs s{};
+    s.p = m->p;
+    s.wfwd = m->wfwd;
+    s.wbwd = m->wbwd;
+    if (e == hipSuccess) e = sur_refresh_weights(s, nullptr);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+  }
+  if (e != hipSuccess) return hip_fail(e, "model parameters");
+  if (step) *step = m->step;
+  return DAGBOUND_OK;
+}
+
+dagbound_status dagbound_model_forward(dagbound_model* m, dagbound_batch* b, float* node_out,
+                                       uint32_t ptr_kind, void* hip_stream) {
+  g_err.clear();
+  if (!m || !b) return fail(DAGBOUND_E_ARG, "model or batch is NULL");
+  if (ptr_kind > DAGBOUND_PTR_DEVICE) return fail(DAGBOUND_E_ARG, "bad ptr_kind %u", ptr_kind);
+  if (!node_out && b->tn > 0) return fail(DAGBOUND_E_ARG, "node_out is NULL");
+  if (m->device != b->device) return fail(DAGBOUND_E_ARG, "model and batch live on different devices");
+  DeviceGuard g(m->device);
+  hipStream_t st = (hipStream_t)hip_stream;
+  SurArgs s;
+  dagbound_status rc = model_workspace(m, b, &s);
+  if (rc != DAGBOUND_OK) return rc;
+  hipError_t e = sur_features(s, st);
+  if (e == hipSuccess) e = sur_forward(s, st);
+  // A rows are in sigma order: copy to the caller in local-id order
+  std::vector<float> hA((size_t)b->tn * SUR_OUT);
+  std::vector<uint16_t> inv((size_t)b->tn);
+  if (e == hipSuccess && b->tn > 0) e = hipMemcpyAsync(hA.data(), s.A, hA.size() * 4, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess && b->tn > 0) e = hipMemcpyAsync(inv.data(), b->t.inv, inv.size() * 2, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(e, "surrogate forward");
+  std::vector<float> out((size_t)b->tn * 3);
+  for (int32_t d = 0; d < b->D; d++)
+    for (int64_t v = 0; v < b->node_off[d + 1] - b->node_off[d]; v++) {
+      const int64_t n0 = b->node_off[d];
+      const int64_t srow = n0 + inv[(size_t)(n0 + v)];
+      for (int j = 0; j < 3; j++) out[(size_t)(n0 + v) * 3 + j] = hA[(size_t)srow * SUR_OUT + j];
+    }
+  if (b->tn > 0) {
+    if (ptr_kind == DAGBOUND_PTR_HOST) memcpy(node_out, out.data(), out.size() * 4);
+    else if ((e = hipMemcpy(node_out, out.data(), out.size() * 4, hipMemcpyHostToDevice)) != hipSuccess)
+      return hip_fail(e, "copying node outputs");
+  }
+  return DAGBOUND_OK;
+}
+
+dagbound_status dagbound_model_train_step(dagbound_model* m, dagbound_batch* b, int32_t K, uint64_t seed,
+                                          const int64_t* bounds, float lr, float* loss, uint32_t ptr_kind,
+                                          void* hip_stream) {
+  g_err.clear();
+  if (!m || !b || !bounds) return fail(DAGBOUND_E_ARG, "model, batch or bounds is NULL");
+  if (K < 2 || K > 16384) return fail(DAGBOUND_E_ARG, "K = %d outside [2, 16384]", K);
+  if (ptr_kind > DAGBOUND_PTR_DEVICE) return fail(DAGBOUND_E_ARG, "bad ptr_kind %u", ptr_kind);
+  if (m->device != b->device) return fail(DAGBOUND_E_ARG, "model and batch live on different devices");
+  DeviceGuard g(m->device);
+  hipStream_t st = (hipStream_t)hip_stream;
+  SurArgs s;
+  dagbound_status rc = model_workspace(m, b, &s);
+  if (rc != DAGBOUND_OK) return rc;
+  const int64_t* dbounds = bounds;
+  void* tmp = nullptr;
+  size_t tmp_size = 0;
+  hipError_t e = hipSuccess;
+  if (ptr_kind == DAGBOUND_PTR_HOST) {
+    tmp_size = (size_t)b->D * K * 8;
+    e = dev_alloc(&tmp, &tmp_size, m->device);
+    if (e == hipSuccess) e = hipMemcpy(tmp, bounds, (size_t)b->D * K * 8, hipMemcpyHostToDevice);
+    dbounds = (const int64_t*)tmp;
+  }
+  const float scale = 1.f / (float)((int64_t)b->D * (K - 1));
+  if (e == hipSuccess) e = sur_features(s, st);
+  if (e == hipSuccess) e = sur_forward(s, st);
+  if (e == hipSuccess) e = sur_head_train(s, K, seed, dbounds, scale, st);
+  if (e == hipSuccess) e = sur_backward(s, st);
+  if (e == hipSuccess && lr > 0.f) {
+    m->step++;
+    e = sur_adam(s, lr, m->step, st);
+    if (e == hipSuccess) e = sur_refresh_weights(s, st);
+  }
+  std::vector<float> lp((size_t)b->D);
+  if (e == hipSuccess && b->D > 0) e = hipMemcpyAsync(lp.data(), s.loss_part, lp.size() * 4, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  dev_release(tmp, tmp_size, m->device);
+  if (e != hipSuccess) return hip_fail(e, "surrogate training step");
+  double sum = 0;
+  for (float x : lp) sum += x;
+  if (loss) *loss = (float)sum;
+  return DAGBOUND_OK;
+}
+
+dagbound_status dagbound_model_select(dagbound_model* m, dagbound_batch* b, int32_t K, uint64_t seed,
+                                      int32_t top_k, int32_t nodes, int32_t* cand, float* scores,
+                                      uint32_t ptr_kind, void* hip_stream) {
+  g_err.clear();
+  if (!m || !b || !cand) return fail(DAGBOUND_E_ARG, "model, batch or cand is NULL");
+  if (K < 1 || K > 16384) return fail(DAGBOUND_E_ARG, "K = %d outside [1, 16384]", K);
+  if (top_k < 0 || top_k > 63 || top_k >= K) return fail(DAGBOUND_E_ARG, "top_k = %d outside [0, min(63, K-1)]", top_k);
+  if (nodes < 1 || nodes > 64) return fail(DAGBOUND_E_ARG, "nodes = %d outside [1, 64]", nodes);
+  if (ptr_kind != DAGBOUND_PTR_DEVICE) return fail(DAGBOUND_E_ARG, "model_select takes device pointers");
+  if (m->device != b->device) return fail(DAGBOUND_E_ARG, "model and batch live on different devices");
+  DeviceGuard g(m->device);
+  hipStream_t st = (hipStream_t)hip_stream;
+  SurArgs s;
+  dagbound_status rc = model_workspace(m, b, &s);
+  if (rc != DAGBOUND_OK) return rc;
+  hipError_t e = sur_features(s, st);
+  if (e == hipSuccess) e = sur_forward(s, st);
+  if (e == hipSuccess) e = sur_select(s, K, seed, nodes, top_k, scores, cand, st);
+  if (e == hipSuccess && !st) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(e, "surrogate selection");
+  return DAGBOUND_OK;
+}
+
+}  // extern "C"
+
+// Surrogate-guided search: score every seeded candidate from the encoder's
+// per-node coefficients over a bounded node set, evaluate the paper's rule
+// and the top_k best-scored candidates exactly, keep the least bound.
+dagbound_status surrogate_best(dagbound_batch* b, dagbound_model* m, int32_t top_k, int32_t* best_idx,
+                               int64_t* best_bound, uint32_t ptr_kind, hipStream_t st) {
+  if (m->device != b->device) return fail(DAGBOUND_E_ARG, "model and batch live on different devices");
+  DeviceGuard g(b->device);
+  SurArgs s;
+  dagbound_status rc = model_workspace(m, b, &s);
+  if (rc != DAGBOUND_OK) return rc;
+  const int32_t kk = top_k + 1;
+  void* tmp = nullptr;
+  size_t tmp_size = 512 * 3 + (size_t)b->D * (kk * 4 + 12);
+  hipError_t e = dev_alloc(&tmp, &tmp_size, b->device);
+  if (e != hipSuccess) return hip_fail(e, "allocating surrogate scratch");
+  Carve c(tmp);
+  int32_t* cand = c.take<int32_t>((size_t)b->D * kk);
+  int64_t* ob = c.take<int64_t>((size_t)b->D);
+  int32_t* oi = c.take<int32_t>((size_t)b->D);
+  e = sur_features(s, st);
+  if (e == hipSuccess) e = sur_forward(s, st);
+  if (e == hipSuccess) e = sur_select(s, b->K, b->seed, SUR_HEAD_NODES, top_k, nullptr, cand, st);
+  if (e == hipSuccess) {
+    SweepArgs a = sweep_args(b);
+    a.K = kk;
+    a.cand_list = cand;
+    a.best = b->best;
+    e = launch_sweep(a, st);
+    b->best_gen = ~0ull;  // the per-DAG minimum now holds list positions
+  }
+  if (e == hipSuccess) {
+    const bool host = ptr_kind == DAGBOUND_PTR_HOST;
+    e = launch_best_final(b->best, b->D, host ? oi : best_idx, host ? ob : best_bound, cand, kk, st);
+    if (e == hipSuccess && host && b->D > 0) {
+      e = hipMemcpyAsync(best_idx, oi, (size_t)b->D * 4, hipMemcpyDeviceToHost, st);
+      if (e == hipSuccess) e = hipMemcpyAsync(best_bound, ob, (size_t)b->D * 8, hipMemcpyDeviceToHost, st);
+    }
+  }
+  const hipError_t es = hipStreamSynchronize(st);
+  if (e == hipSuccess) e = es;
+  dev_release(tmp, tmp_size, b->device);
+  if (e != hipSuccess) return hip_fail(e, "surrogate search");
+  return DAGBOUND_OK;
+}

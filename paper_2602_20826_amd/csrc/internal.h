@@ -61,6 +61,7 @@ struct SweepArgs {
   uint32_t* ovf_count;          // [1]
   uint32_t* gres;               // [GLOBAL_PASS_GRID][max_n][64] residual tables
   int32_t max_n, max_e;
+  const int32_t* cand_list;     // [D][K] candidate ids to evaluate, or nullptr (ids 0..K-1)
   int32_t res_slots;            // <= RES_SLOTS
   int32_t path;                 // EVAL_PATH_*
   int32_t small_loads;          // every C_hat < 2^22
@@ -76,7 +77,54 @@ constexpr size_t LDS_LIMIT = 160 * 1024;
 
 // Evaluates every (DAG, candidate) pair; also resets `best` and fills it.
 hipError_t launch_sweep(const SweepArgs& a, hipStream_t stream);
+// With `list` ([D][K] candidate ids), the packed index is a list position and
+// is translated to the candidate id.
 hipError_t launch_best_final(const unsigned long long* best, int32_t D, int32_t* idx, int64_t* bound,
-                             hipStream_t stream);
+                             const int32_t* list, int32_t K, hipStream_t stream);
+
+// ---------------------------------------------------------------------------
+// Learned candidate proposal (surrogate.hip).
+constexpr int SUR_FIN = 8, SUR_HID = 128, SUR_LAYERS = 3, SUR_OUT = 4;
+constexpr int64_t SUR_OFF_W0 = 0;
+constexpr int64_t SUR_OFF_B0 = SUR_OFF_W0 + SUR_FIN * SUR_HID;
+constexpr int64_t SUR_OFF_L1 = SUR_OFF_B0 + SUR_HID;
+constexpr int64_t SUR_LAYER_STRIDE = 2 * SUR_HID * SUR_HID + SUR_HID;  // Ws, Wm, b
+constexpr int64_t SUR_OFF_WA = SUR_OFF_L1 + SUR_LAYERS * SUR_LAYER_STRIDE;
+constexpr int64_t SUR_OFF_BA = SUR_OFF_WA + SUR_HID * SUR_OUT;
+constexpr int64_t SUR_PARAMS = SUR_OFF_BA + SUR_OUT;
+constexpr int64_t SUR_CHUNK = 8192;  // node rows per partial weight-gradient sum
+constexpr int32_t SUR_HEAD_NODES = 32;  // nodes the search head reads per candidate
+
+struct SurArgs {
+  Tables t;
+  int32_t D, M, max_n;
+  int64_t rows;            // T_N
+  float* p;                // master parameters
+  float* g;                // gradient
+  float *m1, *m2;          // Adam moments
+  __bf16 *wfwd, *wbwd;     // BF16 layer weights (see k_weights_bf16)
+  float* X;                // [rows][8]
+  float *A, *dA;           // [rows][4]
+  __bf16* H[SUR_LAYERS + 1];
+  __bf16* G[SUR_LAYERS];
+  __bf16* dZ[2];
+  float* DT;               // [rows][256]
+  int32_t* dag_of;         // [rows]
+  uint32_t* nboff;         // [rows + D]
+  uint16_t* nb;            // [2 * T_E]
+  float *partial, *partial2;
+  float* loss_part;        // [D]
+};
+
+size_t sur_node_bytes();
+hipError_t sur_features(const SurArgs& s, hipStream_t st);
+hipError_t sur_forward(const SurArgs& s, hipStream_t st);
+hipError_t sur_head_train(const SurArgs& s, int32_t K, uint64_t seed, const int64_t* bounds, float scale,
+                          hipStream_t st);
+hipError_t sur_backward(const SurArgs& s, hipStream_t st);
+hipError_t sur_adam(const SurArgs& s, float lr, int64_t step, hipStream_t st);
+hipError_t sur_refresh_weights(const SurArgs& s, hipStream_t st);
+hipError_t sur_select(const SurArgs& s, int32_t K, uint64_t seed, int32_t T, int32_t top_k, float* scores,
+                      int32_t* cand, hipStream_t st);
 
 }  // namespace dagbound

@@ -1,0 +1,730 @@
+// Learned candidate proposal on gfx950: a 3-layer message-passing encoder
+// (hidden 128) over each DAG, run once per DAG, and a per-candidate head
+// that scores candidate allocations from a bounded set of nodes, so that only
+// the best-scored candidates need exact evaluation.
+//
+// Layers (one DAG, N(v) = predecessors and successors of v):
+//   H0 = relu(X W0 + b0);  G_l = mean over N(v) of H_{l-1};
+//   H_l = relu(H_{l-1} Ws_l + G_l Wm_l + b_l) for l = 1..3;  A = H3 Wa + ba.
+// Score of candidate bytes r: (1/n) sum_v A[v,0:3] . (t, t^2, 1/t),
+// t = r_v / min(p_v, M, 255).  The layer GEMMs run on MFMA in BF16 with FP32
+// accumulation (v_mfma_f32_32x32x16_bf16); the small input and output
+// projections, the aggregation and the head are VALU.  Weight gradients are
+// summed over fixed node chunks and then reduced in a fixed order, so
+// training is deterministic.
+//
+// Node rows of every activation array use the batch's node index in sigma
+// order (node_off[d] + sigma rank).
+#include "internal.h"
+
+namespace dagbound {
+namespace {
+
+typedef __bf16 bf16;
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f16v __attribute__((ext_vector_type(16)));
+
+constexpr int WAVE = 64;
+constexpr int HID = SUR_HID;
+
+__device__ inline float bf2f(bf16 x) { return (float)x; }
+__device__ inline bf16 f2bf(float x) { return (bf16)x; }
+
+// ---------------------------------------------------------------------------
+// Features and neighbour lists, one wavefront per DAG.
+//   x0 log2 C_hat / 16      x1 log2 min(p, M) / 8   x2 log2 W^anc / 24
+//   x3 log2 group size / 8  x4 group position in [0, 1]
+//   x5 log2(1 + in-degree) / 6   x6 log2(1 + out-degree) / 6
+//   x7 C_hat / (load of the node's group)
+__global__ __launch_bounds__(64) void k_features(Tables t, int32_t M, float* X, uint32_t* nboff,
+                                                 uint16_t* nb) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int d = blockIdx.x, lane = threadIdx.x;
+  const int64_t n0 = t.node_off[d];
+  const int N = (int)(t.node_off[d + 1] - n0);
+  const int64_t e0 = t.edge_off[d];
+  unsigned long long* s_gload = (unsigned long long*)smem;  // [group] summed load
+  uint32_t* s_gsize = (uint32_t*)(s_gload + N);              // [group] size
+  uint32_t* s_gpos = s_gsize + N;                            // group of each sigma rank
+  uint32_t* s_cur = s_gpos + N;                              // predecessor fill cursor
+  const int G = t.ngroups[d];
+  // group of each position, size and load
+  {
+    int carry = 0;
+    for (int b0 = 0; b0 < N; b0 += WAVE) {
+      const int k = b0 + lane;
+      const uint32_t g = k < N ? t.gl[n0 + k] : 0u;
+      const uint64_t ends = __ballot(k < N && (g & 0x8000u));
+      const int gi = carry + __popcll(ends & (lane ? (~0ull >> (64 - lane)) : 0ull));
+      if (k < N) s_gpos[g & 0x7FFF] = (uint32_t)gi;
+      carry += __popcll(ends);
+    }
+  }
+  for (int s = lane; s < N; s += WAVE) { s_gsize[s] = 0; s_gload[s] = 0ull; }
+  __syncthreads();
+  for (int s = lane; s < N; s += WAVE) {
+    atomicAdd(&s_gsize[s_gpos[s]], 1u);
+    atomicAdd(&s_gload[s_gpos[s]], (unsigned long long)t.wc[n0 + s]);
+  }
+  __syncthreads();
+  for (int s = lane; s < N; s += WAVE) {
+    const float c = (float)t.wc[n0 + s];
+    const float p = (float)t.pp[n0 + s];
+    const uint32_t indeg = t.indeg[n0 + s];
+    const uint32_t outdeg = t.soff[n0 + d + s + 1] - t.soff[n0 + d + s];
+    const int gp = (int)s_gpos[s];
+    float* x = X + (n0 + s) * SUR_FIN;
+    x[0] = log2f(c) / 16.f;
+    x[1] = log2f(p) / 8.f;
+    x[2] = 0.f;  // filled below from W^anc (by local id)
+    x[3] = log2f((float)s_gsize[gp]) / 8.f;
+    x[4] = (float)gp / (float)max(1, G - 1);
+    x[5] = log2f(1.f + (float)indeg) / 6.f;
+    x[6] = log2f(1.f + (float)outdeg) / 6.f;
+    x[7] = (float)((double)t.wc[n0 + s] / (double)s_gload[gp]);
+  }
+  for (int v = lane; v < N; v += WAVE) {
+    const int s = t.inv[n0 + v];
+    X[(n0 + s) * SUR_FIN + 2] = (float)(log2((double)t.wanc[n0 + v]) / 24.0);
+  }
+  // neighbour lists by sigma rank: predecessors then successors
+  uint32_t* off = nboff + n0 + d;
+  uint32_t carry = 0;
+  for (int b0 = 0; b0 < N; b0 += WAVE) {
+    const int s = b0 + lane;
+    const uint32_t deg = s < N ? (uint32_t)t.indeg[n0 + s] + (t.soff[n0 + d + s + 1] - t.soff[n0 + d + s]) : 0u;
+    uint32_t incl = deg;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t y = (uint32_t)__shfl_up((int)incl, o);
+      if (lane >= o) incl += y;
+    }
+    if (s < N) { off[s] = carry + incl - deg; s_cur[s] = carry + incl - deg; }
+    carry += (uint32_t)__shfl((int)incl, 63);
+  }
+  if (lane == 0) off[N] = carry;
+  __syncthreads();
+  uint16_t* list = nb + 2 * e0;
+  for (int s = lane; s < N; s += WAVE) {
+    const uint32_t e1 = t.soff[n0 + d + s + 1];
+    for (uint32_t e = t.soff[n0 + d + s]; e < e1; e++) {
+      const int u = t.succ[e0 + e];
+      list[atomicAdd(&s_cur[u], 1u)] = (uint16_t)s;  // s is a predecessor of u
+    }
+  }
+  __syncthreads();
+  // predecessor order above depends on atomics: sort each list so the
+  // aggregation sums in a fixed order; then append the successors
+  for (int s = lane; s < N; s += WAVE) {
+    const uint32_t a0 = off[s], a1 = s_cur[s];
+    for (uint32_t i = a0 + 1; i < a1; i++) {
+      const uint16_t x = list[i];
+      uint32_t j = i;
+      while (j > a0 && list[j - 1] > x) { list[j] = list[j - 1]; j--; }
+      list[j] = x;
+    }
+    const uint32_t e1 = t.soff[n0 + d + s + 1];
+    uint32_t pos = a1;
+    for (uint32_t e = t.soff[n0 + d + s]; e < e1; e++) list[pos++] = t.succ[e0 + e];
+  }
+}
+
+// H0 = relu(X W0 + b0): one thread per (node, 8 output columns).
+__global__ void k_l0_fwd(const float* X, const float* W0, const float* b0, int64_t rows, bf16* H0) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t r = i >> 4;
+  const int c0 = (int)(i & 15) * 8;
+  if (r >= rows) return;
+  float x[SUR_FIN];
+#pragma unroll
+  for (int k = 0; k < SUR_FIN; k++) x[k] = X[r * SUR_FIN + k];
+  bf16x8 o;
+#pragma unroll
+  for (int j = 0; j < 8; j++) {
+    float acc = b0[c0 + j];
+#pragma unroll
+    for (int k = 0; k < SUR_FIN; k++) acc += x[k] * W0[k * HID + c0 + j];
+    o[j] = f2bf(fmaxf(acc, 0.f));
+  }
+  *(bf16x8*)(H0 + r * HID + c0) = o;
+}
+
+// G = mean over neighbours of H (zero without neighbours): one thread per
+// (node, 8 columns).
+__global__ void k_agg_fwd(const bf16* H, const int32_t* dag_of, const int64_t* node_off,
+                          const uint32_t* nboff, const uint16_t* nb, const int64_t* edge_off,
+                          int64_t rows, bf16* G) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t r = i >> 4;
+  const int c0 = (int)(i & 15) * 8;
+  if (r >= rows) return;
+  const int d = dag_of[r];
+  const int64_t n0 = node_off[d];
+  const int s = (int)(r - n0);
+  const uint32_t a0 = nboff[n0 + d + s], a1 = nboff[n0 + d + s + 1];
+  const uint16_t* list = nb + 2 * edge_off[d];
+  float acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (uint32_t e = a0; e < a1; e++) {
+    const bf16x8 h = *(const bf16x8*)(H + (n0 + list[e]) * HID + c0);
+#pragma unroll
+    for (int j = 0; j < 8; j++) acc[j] += bf2f(h[j]);
+  }
+  const float inv = a1 > a0 ? 1.f / (float)(a1 - a0) : 0.f;
+  bf16x8 o;
+#pragma unroll
+  for (int j = 0; j < 8; j++) o[j] = f2bf(acc[j] * inv);
+  *(bf16x8*)(G + r * HID + c0) = o;
+}
+
+// C[rows x NT*32] = epilogue(sum over parts A_p[rows x 128] B_p), B given
+// transposed: Bt[n][k] (k over the parts' 128-wide blocks, KD = 128*parts).
+// One workgroup of 4 wavefronts covers 128 rows; a wavefront computes 32 rows
+// x NT*32 columns with MFMA 32x32x16 (BF16 in, FP32 accumulate).  Bt sits in
+// LDS with rows padded by 16 bytes so the 32 rows a k-step reads spread over
+// the banks.  Epilogue: +bias, relu, store BF16 (mode 0); or store FP32
+// (mode 1).
+template <int NT, int KD>
+__global__ __launch_bounds__(256) void k_gemm_rows(const bf16* A0, const bf16* A1, const bf16* Bt,
+                                                   const float* bias, int64_t rows, int mode,
+                                                   bf16* outb, float* outf) {
+  constexpr int NC = NT * 32;
+  constexpr int LDB = KD + 8;  // padded row (bf16 elements)
+  extern __shared__ __align__(16) unsigned char smem[];
+  bf16* sB = (bf16*)smem;
+  const int tid = threadIdx.x;
+  for (int i = tid; i < NC * KD / 8; i += 256) {
+    const int n = i / (KD / 8), k8 = (i % (KD / 8)) * 8;
+    *(bf16x8*)(sB + n * LDB + k8) = *(const bf16x8*)(Bt + (int64_t)n * KD + k8);
+  }
+  __syncthreads();
+  const int wave = tid >> 6, lane = tid & 63;
+  const int64_t r0 = (int64_t)blockIdx.x * 128 + wave * 32;
+  const int64_t ra = r0 + (lane & 31);
+  const int kh = (lane >> 5) * 8;
+  f16v acc[NT];
+#pragma unroll
+  for (int t = 0; t < NT; t++) acc[t] = (f16v){};
+#pragma unroll 2
+  for (int kk = 0; kk < KD; kk += 16) {
+    const bf16* Ap = kk < 128 ? A0 : A1;
+    const int ka = (kk & 127) + kh;
+    bf16x8 a = (bf16x8){};
+    if (ra < rows) a = *(const bf16x8*)(Ap + ra * 128 + ka);
+#pragma unroll
+    for (int t = 0; t < NT; t++) {
+      const bf16x8 b = *(const bf16x8*)(sB + (t * 32 + (lane & 31)) * LDB + kk + kh);
+      acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc[t], 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < NT; t++) {
+    const int col = t * 32 + (lane & 31);
+    const float bb = bias ? bias[col] : 0.f;
+#pragma unroll
+    for (int i = 0; i < 16; i++) {
+      const int64_t row = r0 + 8 * (i / 4) + 4 * (lane >> 5) + (i % 4);
+      if (row < rows) {
+        const float v = acc[t][i] + bb;
+        if (mode == 0) outb[row * NC + col] = f2bf(fmaxf(v, 0.f));
+        else outf[row * NC + col] = v;
+      }
+    }
+  }
+}
+
+// A = H3 Wa + ba (4 outputs per node), FP32.
+__global__ void k_out_fwd(const bf16* H3, const float* Wa, const float* ba, int64_t rows, float* A) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= rows) return;
+  float acc[SUR_OUT];
+#pragma unroll
+  for (int j = 0; j < SUR_OUT; j++) acc[j] = ba[j];
+  for (int k8 = 0; k8 < HID; k8 += 8) {
+    const bf16x8 h = *(const bf16x8*)(H3 + r * HID + k8);
+#pragma unroll
+    for (int k = 0; k < 8; k++) {
+      const float hv = bf2f(h[k]);
+#pragma unroll
+      for (int j = 0; j < SUR_OUT; j++) acc[j] += hv * Wa[(k8 + k) * SUR_OUT + j];
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < SUR_OUT; j++) A[r * SUR_OUT + j] = acc[j];
+}
+
+__device__ inline uint64_t mix64(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+// Seeded candidate byte of (d, c, local id v), range = min(p_v, M, 255).
+__device__ inline uint32_t seeded_r(uint64_t key, uint64_t c, uint32_t v, uint32_t range) {
+  const uint64_t word = mix64(key ^ ((c << 32) | (uint64_t)(v >> 2)));
+  const uint32_t h16 = (uint32_t)(word >> (16 * (v & 3))) & 0xFFFFu;
+  return 1u + ((h16 * range) >> 16);
+}
+
+__device__ inline float wave_sum_f(float x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+  return x;
+}
+
+// Training head, one wavefront per DAG over its K seeded candidates (lanes
+// take candidates c = 1.., 64 at a time): scores, squared error against
+// y_c = ln(bound_c) - ln(bound_0), and dA = d loss / d A (deterministic: a
+// fixed candidate order inside one wavefront).  loss_part[d] gets the DAG's
+// summed squared error times `scale`.
+__global__ __launch_bounds__(64) void k_head_train(Tables t, int32_t K, uint64_t seed,
+                                                   const int64_t* bounds, const float* A, float scale,
+                                                   float* dA, float* loss_part) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int d = blockIdx.x, lane = threadIdx.x;
+  const int64_t n0 = t.node_off[d];
+  const int N = (int)(t.node_off[d + 1] - n0);
+  float* s_ds = (float*)smem;                           // [K] d loss / d score
+  const uint64_t key = mix64(seed ^ mix64((uint64_t)d * 0x9E3779B97F4A7C15ull));
+  const float b0 = logf((float)bounds[(int64_t)d * K]);
+  const float invn = N > 0 ? 1.f / (float)N : 0.f;
+  float lsum = 0.f;
+  for (int c0 = 1; c0 < K; c0 += WAVE) {
+    const int c = c0 + lane;
+    float sc = 0.f;
+    if (c < K) {
+      for (int v = 0; v < N; v++) {
+        const int s = t.inv[n0 + v];
+        const uint32_t range = min((uint32_t)t.pp[n0 + s], 255u);
+        const float tt = (float)seeded_r(key, (uint64_t)c, (uint32_t)v, range) / (float)range;
+        const float* a = A + (n0 + s) * SUR_OUT;
+        sc += a[0] * tt + a[1] * tt * tt + a[2] / tt;
+      }
+      sc *= invn;
+      const float y = logf((float)bounds[(int64_t)d * K + c]) - b0;
+      const float diff = sc - y;
+      lsum += diff * diff;
+      s_ds[c] = 2.f * scale * diff;
+    }
+  }
+  lsum = wave_sum_f(lsum);
+  if (lane == 0) loss_part[d] = lsum * scale;
+  __syncthreads();
+  for (int v = 0; v < N; v++) {
+    const int s = t.inv[n0 + v];
+    const uint32_t range = min((uint32_t)t.pp[n0 + s], 255u);
+    float g0 = 0.f, g1 = 0.f, g2 = 0.f;
+    for (int c = 1 + lane; c < K; c += WAVE) {
+      const float tt = (float)seeded_r(key, (uint64_t)c, (uint32_t)v, range) / (float)range;
+      const float ds = s_ds[c];
+      g0 += ds * tt;
+      g1 += ds * tt * tt;
+      g2 += ds / tt;
+    }
+    g0 = wave_sum_f(g0);
+    g1 = wave_sum_f(g1);
+    g2 = wave_sum_f(g2);
+    if (lane == 0) {
+      float* o = dA + (n0 + s) * SUR_OUT;
+      o[0] = g0 * invn;
+      o[1] = g1 * invn;
+      o[2] = g2 * invn;
+      o[3] = 0.f;
+    }
+  }
+}
+
+// dZ3 = (dA Wa^T) * (H3 > 0), BF16; one thread per (node, 8 columns).
+__global__ void k_out_bwd(const float* dA, const float* Wa, const bf16* H3, int64_t rows, bf16* dZ) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t r = i >> 4;
+  const int c0 = (int)(i & 15) * 8;
+  if (r >= rows) return;
+  float g[SUR_OUT];
+#pragma unroll
+  for (int j = 0; j < SUR_OUT; j++) g[j] = dA[r * SUR_OUT + j];
+  const bf16x8 h = *(const bf16x8*)(H3 + r * HID + c0);
+  bf16x8 o;
+#pragma unroll
+  for (int k = 0; k < 8; k++) {
+    float acc = 0.f;
+#pragma unroll
+    for (int j = 0; j < SUR_OUT; j++) acc += g[j] * Wa[(c0 + k) * SUR_OUT + j];
+    o[k] = f2bf(bf2f(h[k]) > 0.f ? acc : 0.f);
+  }
+  *(bf16x8*)(dZ + r * HID + c0) = o;
+}
+
+// dZ_prev(u) = (D(u) + sum over v in N(u) of T(v) / |N(v)|) * (H_prev(u) > 0),
+// with [D | T] = dZ [Ws^T | Wm^T] in FP32 rows of 256.
+__global__ void k_agg_bwd(const float* DT, const bf16* Hprev, const int32_t* dag_of,
+                          const int64_t* node_off, const uint32_t* nboff, const uint16_t* nb,
+                          const int64_t* edge_off, int64_t rows, bf16* dZprev) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t r = i >> 4;
+  const int c0 = (int)(i & 15) * 8;
+  if (r >= rows) return;
+  const int d = dag_of[r];
+  const int64_t n0 = node_off[d];
+  const int s = (int)(r - n0);
+  const uint32_t a0 = nboff[n0 + d + s], a1 = nboff[n0 + d + s + 1];
+  const uint16_t* list = nb + 2 * edge_off[d];
+  float acc[8];
+#pragma unroll
+  for (int j = 0; j < 8; j++) acc[j] = DT[r * 256 + c0 + j];
+  for (uint32_t e = a0; e < a1; e++) {
+    const int u = list[e];
+    const float w = 1.f / (float)(nboff[n0 + d + u + 1] - nboff[n0 + d + u]);
+#pragma unroll
+    for (int j = 0; j < 8; j++) acc[j] += DT[(n0 + u) * 256 + 128 + c0 + j] * w;
+  }
+  const bf16x8 h = *(const bf16x8*)(Hprev + r * HID + c0);
+  bf16x8 o;
+#pragma unroll
+  for (int j = 0; j < 8; j++) o[j] = f2bf(bf2f(h[j]) > 0.f ? acc[j] : 0.f);
+  *(bf16x8*)(dZprev + r * HID + c0) = o;
+}
+
+// Partial weight gradients over one chunk of CHUNK node rows:
+//   P[KD x 128] = [A0 | A1]^T dZ  (KD = 128 per part),
+// with MFMA 32x32x16: the chunk is staged 16 rows at a time in LDS,
+// transposed, so both operands are contiguous 16-byte reads.  4 wavefronts;
+// wavefront w owns dW rows [w*KD/4, (w+1)*KD/4).
+template <int KD>
+__global__ __launch_bounds__(256) void k_wgrad(const bf16* A0, const bf16* A1, const bf16* dZ,
+                                               int64_t rows, int64_t chunk, float* partial) {
+  constexpr int RT = KD / 128;  // 32-row tiles of dW per wavefront
+  __shared__ __align__(16) bf16 sAt[KD][16 + 8];
+  __shared__ __align__(16) bf16 sZt[128][16 + 8];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int64_t m0 = (int64_t)blockIdx.x * chunk;
+  const int64_t m1 = min(rows, m0 + chunk);
+  f16v acc[RT][4];
+#pragma unroll
+  for (int i = 0; i < RT; i++)
+#pragma unroll
+    for (int j = 0; j < 4; j++) acc[i][j] = (f16v){};
+  for (int64_t m = m0; m < m1; m += 16) {
+    // stage 16 rows: A^T [KD][16], dZ^T [128][16]
+    for (int i = tid; i < 16 * (KD / 8); i += 256) {
+      const int rr = i / (KD / 8), k8 = (i % (KD / 8)) * 8;
+      const int64_t row = m + rr;
+      bf16x8 v = (bf16x8){};
+      if (row < m1) v = *(const bf16x8*)((k8 < 128 ? A0 : A1) + row * 128 + (k8 & 127));
+#pragma unroll
+      for (int j = 0; j < 8; j++) sAt[k8 + j][rr] = v[j];
+    }
+    for (int i = tid; i < 16 * 16; i += 256) {
+      const int rr = i / 16, k8 = (i % 16) * 8;
+      const int64_t row = m + rr;
+      bf16x8 v = (bf16x8){};
+      if (row < m1) v = *(const bf16x8*)(dZ + row * 128 + k8);
+#pragma unroll
+      for (int j = 0; j < 8; j++) sZt[k8 + j][rr] = v[j];
+    }
+    __syncthreads();
+    const int kh = (lane >> 5) * 8;
+#pragma unroll
+    for (int i = 0; i < RT; i++) {
+      const bf16x8 a = *(const bf16x8*)&sAt[(wave * RT + i) * 32 + (lane & 31)][kh];
+#pragma unroll
+      for (int j = 0; j < 4; j++) {
+        const bf16x8 b = *(const bf16x8*)&sZt[j * 32 + (lane & 31)][kh];
+        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc[i][j], 0, 0, 0);
+      }
+    }
+    __syncthreads();
+  }
+  float* out = partial + (int64_t)blockIdx.x * KD * 128;
+#pragma unroll
+  for (int i = 0; i < RT; i++)
+#pragma unroll
+    for (int j = 0; j < 4; j++)
+#pragma unroll
+      for (int q = 0; q < 16; q++) {
+        const int row = (wave * RT + i) * 32 + 8 * (q / 4) + 4 * (lane >> 5) + (q % 4);
+        const int col = j * 32 + (lane & 31);
+        out[row * 128 + col] = acc[i][j][q];
+      }
+}
+
+// Small reductions over node chunks (FP32, fixed order inside a chunk):
+//   kind 0: column sums of a BF16 [rows x 128] matrix (bias gradient);
+//   kind 1: X^T dZ0 [8 x 128] (FP32 X, BF16 dZ0);
+//   kind 2: H3^T dA [128 x 4] and column sums of dA [4].
+// Partial layout: [chunk][width].
+__global__ void k_small_grad(int kind, const float* X, const bf16* Z, const float* dA, int64_t rows,
+                             int64_t chunk, float* partial, int width) {
+  const int64_t m0 = (int64_t)blockIdx.x * chunk;
+  const int64_t m1 = min(rows, m0 + chunk);
+  for (int o = threadIdx.x; o < width; o += blockDim.x) {
+    float acc = 0.f;
+    if (kind == 0) {
+      for (int64_t m = m0; m < m1; m++) acc += bf2f(Z[m * 128 + o]);
+    } else if (kind == 1) {
+      const int k = o / 128, c = o % 128;
+      for (int64_t m = m0; m < m1; m++) acc += X[m * SUR_FIN + k] * bf2f(Z[m * 128 + c]);
+    } else {
+      if (o < 128 * SUR_OUT) {
+        const int k = o / SUR_OUT, j = o % SUR_OUT;
+        for (int64_t m = m0; m < m1; m++) acc += bf2f(Z[m * 128 + k]) * dA[m * SUR_OUT + j];
+      } else {
+        const int j = o - 128 * SUR_OUT;
+        for (int64_t m = m0; m < m1; m++) acc += dA[m * SUR_OUT + j];
+      }
+    }
+    partial[(int64_t)blockIdx.x * width + o] = acc;
+  }
+}
+
+// out[i] = sum over chunks of partial[chunk][i], in chunk order.
+__global__ void k_reduce(const float* partial, int64_t nchunk, int width, float* out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= width) return;
+  float acc = 0.f;
+  for (int64_t c = 0; c < nchunk; c++) acc += partial[c * width + i];
+  out[i] = acc;
+}
+
+// Adam on the FP32 master parameters.
+__global__ void k_adam(float* p, const float* g, float* m1, float* m2, int64_t n, float lr, float b1,
+                       float b2, float eps, float c1, float c2) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float a = b1 * m1[i] + (1.f - b1) * gi;
+  const float b = b2 * m2[i] + (1.f - b2) * gi * gi;
+  m1[i] = a;
+  m2[i] = b;
+  p[i] -= lr * (a / c1) / (sqrtf(b / c2) + eps);
+}
+
+// BF16 copies of the layer weights in the transposed layouts the GEMMs read:
+//   fwd[l]: [128 out][256 k]  k < 128: Ws_l[k][n], k >= 128: Wm_l[k-128][n]
+//   bwd[l]: [256 out][128 k]  n < 128: Ws_l[n][k], n >= 128: Wm_l[n-128][k]
+__global__ void k_weights_bf16(const float* p, bf16* fwd, bf16* bwd) {
+  const int l = blockIdx.y;
+  const float* Ws = p + SUR_OFF_L1 + (int64_t)l * SUR_LAYER_STRIDE;
+  const float* Wm = Ws + HID * HID;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < 256 * 128; i += gridDim.x * blockDim.x) {
+    {  // fwd: i = n * 256 + k
+      const int n = i / 256, k = i % 256;
+      const float v = k < 128 ? Ws[k * HID + n] : Wm[(k - 128) * HID + n];
+      fwd[(int64_t)l * 256 * 128 + i] = f2bf(v);
+    }
+    {  // bwd: i = n * 128 + k
+      const int n = i / 128, k = i % 128;
+      const float v = n < 128 ? Ws[n * HID + k] : Wm[(n - 128) * HID + k];
+      bwd[(int64_t)l * 256 * 128 + i] = f2bf(v);
+    }
+  }
+}
+
+// Inference head, one workgroup (one wavefront) per DAG: the T nodes of
+// largest importance |a0| + |a1| + range * |a2| (nodes whose range is 1 are
+// constant over candidates and skipped), then the score of every seeded
+// candidate over those nodes, then the top_k smallest scores among c >= 1.
+// cand[d][0] = 0 (the paper's rule), cand[d][1..top_k] the chosen
+// candidates, smallest score first, ties to the smaller index.
+__global__ __launch_bounds__(64) void k_head_select(Tables t, const float* A, int32_t K, uint64_t seed,
+                                                    int32_t T, int32_t top_k, float* scores,
+                                                    int32_t* cand) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int d = blockIdx.x, lane = threadIdx.x;
+  const int64_t n0 = t.node_off[d];
+  const int N = (int)(t.node_off[d + 1] - n0);
+  float* s_imp = (float*)smem;                   // [N] importance by local id
+  int* s_sel = (int*)(s_imp + N);                // [T]
+  float* s_sc = (float*)(s_sel + 64);            // [K] scores
+  for (int v = lane; v < N; v += WAVE) {
+    const int s = t.inv[n0 + v];
+    const uint32_t range = min((uint32_t)t.pp[n0 + s], 255u);
+    const float* a = A + (n0 + s) * SUR_OUT;
+    s_imp[v] = range > 1 ? fabsf(a[0]) + fabsf(a[1]) + (float)range * fabsf(a[2]) : -1.f;
+  }
+  __syncthreads();
+  const int tsel = min(T, N);
+  int nsel = 0;
+  for (int q = 0; q < tsel; q++) {
+    float best = -1.f;
+    int bi = 0x7fffffff;
+    for (int v = lane; v < N; v += WAVE) {
+      const float x = s_imp[v];
+      if (x > best || (x == best && v < bi)) { best = x; bi = v; }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      const float ob = __shfl_xor(best, o);
+      const int oi = __shfl_xor(bi, o);
+      if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+    }
+    if (best < 0.f) break;
+    if (lane == 0) { s_sel[q] = bi; s_imp[bi] = -1.f; }
+    __syncthreads();
+    nsel++;
+  }
+  const uint64_t key = mix64(seed ^ mix64((uint64_t)d * 0x9E3779B97F4A7C15ull));
+  for (int c = lane; c < K; c += WAVE) {
+    float sc = 0.f;
+    for (int q = 0; q < nsel; q++) {
+      const int v = s_sel[q];
+      const int s = t.inv[n0 + v];
+      const uint32_t range = min((uint32_t)t.pp[n0 + s], 255u);
+      const float tt = (float)seeded_r(key, (uint64_t)c, (uint32_t)v, range) / (float)range;
+      const float* a = A + (n0 + s) * SUR_OUT;
+      sc += a[0] * tt + a[1] * tt * tt + a[2] / tt;
+    }
+    sc = N > 0 ? sc / (float)N : 0.f;
+    s_sc[c] = c == 0 ? INFINITY : sc;
+    if (scores) scores[(int64_t)d * K + c] = sc;
+  }
+  __syncthreads();
+  int32_t* out = cand + (int64_t)d * (top_k + 1);
+  if (lane == 0) out[0] = 0;
+  for (int q = 0; q < top_k; q++) {
+    float best = INFINITY;
+    int bi = 0x7fffffff;
+    for (int c = lane; c < K; c += WAVE) {
+      const float x = s_sc[c];
+      if (x < best || (x == best && c < bi)) { best = x; bi = c; }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      const float ob = __shfl_xor(best, o);
+      const int oi = __shfl_xor(bi, o);
+      if (ob < best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+    }
+    if (lane == 0) {
+      out[1 + q] = bi < K ? bi : 0;
+      if (bi < K) s_sc[bi] = INFINITY;
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void k_dag_of(const int64_t* node_off, int32_t D, int32_t* dag_of) {
+  const int d = blockIdx.x;
+  if (d >= D) return;
+  for (int64_t i = node_off[d] + threadIdx.x; i < node_off[d + 1]; i += blockDim.x) dag_of[i] = d;
+}
+
+inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+}  // namespace
+
+size_t sur_node_bytes() {
+  // X (8 fp32) + A, dA (4 fp32 each) + 4 H + 3 G (bf16 x 128) + dZ x 2 (bf16)
+  // + DT (256 fp32) + dag index
+  return 8 * 4 + 4 * 4 * 2 + 9 * 128 * 2 + 256 * 4 + 4;
+}
+
+hipError_t sur_features(const SurArgs& s, hipStream_t st) {
+  hipLaunchKernelGGL(k_dag_of, dim3(s.D), dim3(64), 0, st, s.t.node_off, s.D, s.dag_of);
+  const size_t lds = (size_t)s.max_n * 20 + 64;
+  hipLaunchKernelGGL(k_features, dim3(s.D), dim3(64), lds, st, s.t, s.M, s.X, s.nboff, s.nb);
+  return hipGetLastError();
+}
+
+hipError_t sur_forward(const SurArgs& s, hipStream_t st) {
+  const int64_t R = s.rows;
+  hipError_t e;
+  hipLaunchKernelGGL(k_l0_fwd, dim3(blocks_for(R * 16, 256)), dim3(256), 0, st, s.X, s.p + SUR_OFF_W0,
+                     s.p + SUR_OFF_B0, R, s.H[0]);
+  const size_t lds_f = (size_t)128 * (256 + 8) * 2;
+  e = hipFuncSetAttribute((const void*)k_gemm_rows<4, 256>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)lds_f);
+  if (e != hipSuccess) return e;
+  for (int l = 0; l < SUR_LAYERS; l++) {
+    hipLaunchKernelGGL(k_agg_fwd, dim3(blocks_for(R * 16, 256)), dim3(256), 0, st, s.H[l], s.dag_of,
+                       s.t.node_off, s.nboff, s.nb, s.t.edge_off, R, s.G[l]);
+    hipLaunchKernelGGL((k_gemm_rows<4, 256>), dim3(blocks_for(R, 128)), dim3(256), lds_f, st, s.H[l],
+                       s.G[l], s.wfwd + (int64_t)l * 256 * 128,
+                       s.p + SUR_OFF_L1 + (int64_t)l * SUR_LAYER_STRIDE + 2 * HID * HID, R, 0,
+                       s.H[l + 1], (float*)nullptr);
+  }
+  hipLaunchKernelGGL(k_out_fwd, dim3(blocks_for(R, 256)), dim3(256), 0, st, s.H[SUR_LAYERS],
+                     s.p + SUR_OFF_WA, s.p + SUR_OFF_BA, R, s.A);
+  return hipGetLastError();
+}
+
+hipError_t sur_backward(const SurArgs& s, hipStream_t st) {
+  const int64_t R = s.rows;
+  const int64_t chunk = SUR_CHUNK;
+  const int64_t nchunk = (R + chunk - 1) / chunk;
+  hipError_t e;
+  // output layer
+  hipLaunchKernelGGL(k_small_grad, dim3((unsigned)nchunk), dim3(256), 0, st, 2, (const float*)nullptr,
+                     s.H[SUR_LAYERS], s.dA, R, chunk, s.partial, 128 * SUR_OUT + SUR_OUT);
+  hipLaunchKernelGGL(k_reduce, dim3(blocks_for(128 * SUR_OUT + SUR_OUT, 256)), dim3(256), 0, st,
+                     s.partial, nchunk, 128 * SUR_OUT + SUR_OUT, s.g + SUR_OFF_WA);
+  hipLaunchKernelGGL(k_out_bwd, dim3(blocks_for(R * 16, 256)), dim3(256), 0, st, s.dA, s.p + SUR_OFF_WA,
+                     s.H[SUR_LAYERS], R, s.dZ[0]);
+  const size_t lds_b = (size_t)256 * (128 + 8) * 2;
+  e = hipFuncSetAttribute((const void*)k_gemm_rows<8, 128>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)lds_b);
+  if (e != hipSuccess) return e;
+  int cur = 0;
+  for (int l = SUR_LAYERS - 1; l >= 0; l--) {
+    // layer l+1 (H[l+1] = relu(H[l] Ws + G[l] Wm + b)), dZ[cur] = its pre-activation gradient
+    float* gl = s.g + SUR_OFF_L1 + (int64_t)l * SUR_LAYER_STRIDE;
+    hipLaunchKernelGGL(k_wgrad<256>, dim3((unsigned)nchunk), dim3(256), 0, st, s.H[l], s.G[l], s.dZ[cur], R,
+                       chunk, s.partial);
+    // partial rows 0..127 -> Ws, 128..255 -> Wm (both [128 x 128] row-major)
+    hipLaunchKernelGGL(k_reduce, dim3(blocks_for(256 * 128, 256)), dim3(256), 0, st, s.partial, nchunk,
+                       256 * 128, gl);
+    hipLaunchKernelGGL(k_small_grad, dim3((unsigned)nchunk), dim3(256), 0, st, 0, (const float*)nullptr,
+                       s.dZ[cur], (const float*)nullptr, R, chunk, s.partial2, 128);
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(128), 0, st, s.partial2, nchunk, 128, gl + 2 * HID * HID);
+    // data gradient: [D | T] = dZ [Ws^T | Wm^T], then aggregate and mask
+    hipLaunchKernelGGL((k_gemm_rows<8, 128>), dim3(blocks_for(R, 128)), dim3(256), lds_b, st, s.dZ[cur],
+                       (const bf16*)nullptr, s.wbwd + (int64_t)l * 256 * 128, (const float*)nullptr, R, 1,
+                       (bf16*)nullptr, s.DT);
+    hipLaunchKernelGGL(k_agg_bwd, dim3(blocks_for(R * 16, 256)), dim3(256), 0, st, s.DT, s.H[l], s.dag_of,
+                       s.t.node_off, s.nboff, s.nb, s.t.edge_off, R, s.dZ[cur ^ 1]);
+    cur ^= 1;
+  }
+  // input layer
+  hipLaunchKernelGGL(k_small_grad, dim3((unsigned)nchunk), dim3(256), 0, st, 1, s.X, s.dZ[cur],
+                     (const float*)nullptr, R, chunk, s.partial, SUR_FIN * 128);
+  hipLaunchKernelGGL(k_reduce, dim3(blocks_for(SUR_FIN * 128, 256)), dim3(256), 0, st, s.partial, nchunk,
+                     SUR_FIN * 128, s.g + SUR_OFF_W0);
+  hipLaunchKernelGGL(k_small_grad, dim3((unsigned)nchunk), dim3(256), 0, st, 0, (const float*)nullptr,
+                     s.dZ[cur], (const float*)nullptr, R, chunk, s.partial2, 128);
+  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(128), 0, st, s.partial2, nchunk, 128, s.g + SUR_OFF_B0);
+  return hipGetLastError();
+}
+
+hipError_t sur_head_train(const SurArgs& s, int32_t K, uint64_t seed, const int64_t* bounds, float scale,
+                          hipStream_t st) {
+  const size_t lds = (size_t)K * 4 + 64;
+  hipError_t e = hipFuncSetAttribute((const void*)k_head_train, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_head_train, dim3(s.D), dim3(64), lds, st, s.t, K, seed, bounds, s.A, scale, s.dA,
+                     s.loss_part);
+  return hipGetLastError();
+}
+
+hipError_t sur_adam(const SurArgs& s, float lr, int64_t step, hipStream_t st) {
+  const float b1 = 0.9f, b2 = 0.999f;
+  const float c1 = 1.f - powf(b1, (float)step), c2 = 1.f - powf(b2, (float)step);
+  hipLaunchKernelGGL(k_adam, dim3(blocks_for(SUR_PARAMS, 256)), dim3(256), 0, st, s.p, s.g, s.m1, s.m2,
+                     (int64_t)SUR_PARAMS, lr, b1, b2, 1e-8f, c1, c2);
+  return hipGetLastError();
+}
+
+hipError_t sur_refresh_weights(const SurArgs& s, hipStream_t st) {
+  hipLaunchKernelGGL(k_weights_bf16, dim3(32, SUR_LAYERS), dim3(256), 0, st, s.p, s.wfwd, s.wbwd);
+  return hipGetLastError();
+}
+
+hipError_t sur_select(const SurArgs& s, int32_t K, uint64_t seed, int32_t T, int32_t top_k, float* scores,
+                      int32_t* cand, hipStream_t st) {
+  const size_t lds = (size_t)s.max_n * 4 + 64 * 4 + (size_t)K * 4 + 64;
+  hipError_t e = hipFuncSetAttribute((const void*)k_head_select, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_head_select, dim3(s.D), dim3(64), lds, st, s.t, s.A, K, seed, T, top_k, scores,
+                     cand);
+  return hipGetLastError();
+}
+
+}  // namespace dagbound

@@ -20,8 +20,8 @@
 //     whose table would overflow is handed to a second pass of the same code
 //     whose table lives in global memory and holds every node;
 //   - candidate bytes: [node][lane] bytes in LDS.
-// Releases use per-candidate counters of unfinished predecessors
-// ([node][lane] in LDS).  All arithmetic is integer.
+// Releases use per-candidate counters of unfinished predecessors, packed in
+// LDS dwords [node][lane].  All arithmetic is integer.
 #include "internal.h"
 
 namespace dagbound {
@@ -55,6 +55,22 @@ __device__ inline int bit_first(const uint64_t (&b)[NW]) {
   int r = -1;
 #pragma unroll
   for (int k = NW - 1; k >= 0; k--) r = b[k] ? k * 64 + __builtin_ctzll(b[k]) : r;
+  return r;
+}
+// Index of the lowest set bit (or -1), cleared in place.
+template <int NW>
+__device__ inline int pop_first(uint64_t (&b)[NW]) {
+  int r = -1;
+  bool done = false;
+#pragma unroll
+  for (int k = 0; k < NW; k++) {
+    const bool take = !done && b[k] != 0;
+    if (take) {
+      r = k * 64 + __builtin_ctzll(b[k]);
+      b[k] &= b[k] - 1;
+    }
+    done = done || take;
+  }
   return r;
 }
 template <int NW>
@@ -120,14 +136,28 @@ __device__ inline uint64_t mix64(uint64_t z) {
   return z ^ (z >> 31);
 }
 
-__device__ inline uint64_t uni64(uint64_t x) {
-  return ((uint64_t)uni((uint32_t)(x >> 32)) << 32) | uni((uint32_t)x);
+// OR over the wavefront: row shifts within each row of 16 lanes, then row
+// broadcasts; lane 63 ends with the OR of all 64 lanes.
+__device__ inline uint32_t wave_or32(uint32_t x) {
+  x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xf, 0xf, false);  // row_shr:1
+  x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xf, 0xf, false);  // row_shr:2
+  x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xf, 0xf, false);  // row_shr:4
+  x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xf, 0xf, false);  // row_shr:8
+  x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xa, 0xf, false);  // row_bcast:15
+  x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xc, 0xf, false);  // row_bcast:31
+  return __builtin_amdgcn_readlane(x, 63);
+}
+__device__ inline uint64_t wave_or64(uint64_t x) {
+  return ((uint64_t)wave_or32((uint32_t)(x >> 32)) << 32) | wave_or32((uint32_t)x);
 }
 
-// Unfinished-predecessor counters: bytes while every in-degree fits
-// (N <= 256), half-words above.
-template <int NW> struct Npr { typedef uint8_t type; };
-template <> struct Npr<8> { typedef uint16_t type; };
+// Unfinished-predecessor counters, packed into dwords laid out [node / P][lane]
+// so a lane always hits its own bank: P = 4 byte counters while every
+// in-degree fits (N <= 256), P = 2 half-word counters above.  A decrement is
+// one LDS atomic subtract on the node's field (it never borrows: a counter is
+// positive until its last predecessor finishes).
+template <int NW> struct Cnt { static constexpr int PER = 4, BITS = 8; };
+template <> struct Cnt<8> { static constexpr int PER = 2, BITS = 16; };
 
 // LDS layout of one wavefront (bytes), for the batch's largest DAG.
 struct Lds {
@@ -143,7 +173,7 @@ __host__ __device__ inline Lds lds_layout(int maxn, int maxe, int nw, bool big) 
   l.ppv = o;  o += ((size_t)maxn * 2 + 15) & ~(size_t)15;  // min(p, M) by local id
   l.res = o;  o += big ? 0 : (size_t)RES_SLOTS * WAVE * 4;  // residual table
   l.r = o;    o += (size_t)maxn * WAVE;         // candidate bytes [local id][lane]
-  l.npr = o;  o += (size_t)maxn * WAVE * (nw == 8 ? 2 : 1);  // [sigma][lane]
+  l.npr = o;  o += (size_t)((maxn + 3) / 4 + 1) * WAVE * 4 * (nw == 8 ? 2 : 1);  // packed counters
   l.total = (o + 15) & ~(size_t)15;
   return l;
 }
@@ -152,13 +182,15 @@ __host__ __device__ inline Lds lds_layout(int maxn, int maxe, int nw, bool big) 
 // (nothing was written; the tile must be redone by the global-table pass).
 template <int NW, bool BIG, bool SMALL>
 __device__ bool eval_tile(const SweepArgs& a, int item, unsigned char* smem, uint32_t* gres) {
-  typedef typename Npr<NW>::type npr_t;
+  constexpr int CP = Cnt<NW>::PER, CB = Cnt<NW>::BITS;
+  constexpr uint32_t CMASK = (1u << CB) - 1u;
   const int ntile = (a.K + WAVE - 1) / WAVE;
   const int d = item / ntile;
   const int tile = item - d * ntile;
   const int lane = threadIdx.x;
-  const int c = tile * WAVE + lane;
-  const bool active = c < a.K;
+  const int slot = tile * WAVE + lane;  // output position
+  const bool active = slot < a.K;
+  const int c = a.cand_list ? (active ? a.cand_list[(int64_t)d * a.K + slot] : 0) : slot;  // candidate id
   const int64_t n0 = a.t.node_off[d];
   const int N = (int)(a.t.node_off[d + 1] - n0);
   const int64_t e0 = a.t.edge_off[d];
@@ -172,7 +204,7 @@ __device__ bool eval_tile(const SweepArgs& a, int item, unsigned char* smem, uin
   uint16_t* s_ppv = (uint16_t*)(smem + L.ppv); // [local id]
   uint32_t* res = BIG ? gres : (uint32_t*)(smem + L.res);  // [slot][lane]
   uint8_t* s_r = smem + L.r;                   // [local id][lane]
-  npr_t* s_npr = (npr_t*)(smem + L.npr);       // [sigma][lane]
+  uint32_t* s_cnt = (uint32_t*)(smem + L.npr); // [sigma / CP][lane]
   const int qcap = BIG ? a.max_n : a.res_slots;
 
   // ---- DAG tables (shared by the 64 candidates)
@@ -197,10 +229,18 @@ __device__ bool eval_tile(const SweepArgs& a, int item, unsigned char* smem, uin
   uint64_t rel[NW], seg[NW];
 #pragma unroll
   for (int w = 0; w < NW; w++) { rel[w] = 0; seg[w] = 0; }
-  for (int s = 0; s < N; s++) {
-    const uint32_t np = a.t.indeg[n0 + s];
-    s_npr[s * WAVE + lane] = (npr_t)np;
-    if (np == 0) bit_set<NW>(rel, s);
+  for (int s0 = 0; s0 < N; s0 += CP) {
+    uint32_t packed = 0;
+#pragma unroll
+    for (int i = 0; i < CP; i++) {
+      const int s = s0 + i;
+      if (s < N) {
+        const uint32_t np = a.t.indeg[n0 + s];
+        packed |= np << (CB * i);
+        if (np == 0) bit_set<NW>(rel, s);
+      }
+    }
+    s_cnt[(s0 / CP) * WAVE + lane] = packed;
   }
   // ---- candidate bytes of this lane, by local id.  Candidate 0 is the
   // paper's own rule (all zero); lanes past K run zeros and store nothing.
@@ -286,15 +326,16 @@ __device__ bool eval_tile(const SweepArgs& a, int item, unsigned char* smem, uin
     }
     // Eqs. 6-7: parallel nodes (released, outside the group) take the S spare
     // compute units, largest W^anc first; a node that does not fit in
-    // maxC * m is segmented there and the launching stops.
+    // maxC * m is segmented there and the launching stops.  The nodes taken
+    // from Q and not segmented are the ones launched whole.
     uint32_t S = (W != 0 && sm < M) ? M - sm : 0u;
     uint64_t Q[NW], Lw[NW];
 #pragma unroll
-    for (int w = 0; w < NW; w++) { Q[w] = rel[w] & ~gm[w]; Lw[w] = 0; }
+    for (int w = 0; w < NW; w++) { Q[w] = rel[w] & ~gm[w]; Lw[w] = Q[w]; }
+    int cseg = -1;
     while (S) {
-      const int cn = bit_first<NW>(Q);
+      const int cn = pop_first<NW>(Q);
       if (cn < 0) break;
-      bit_clear<NW>(Q, cn);
       const uint2 nd = s_node[cn];
       const bool sg = bit_get<NW>(seg, cn);
       int rk = 0;
@@ -309,6 +350,7 @@ __device__ bool eval_tile(const SweepArgs& a, int item, unsigned char* smem, uin
       const uint64_t cap = (uint64_t)maxC * mc;
       if ((uint64_t)cc > cap) {
         const uint32_t left = cc - (uint32_t)cap;
+        cseg = cn;
         if (sg) {
           res[rk * WAVE + lane] = left;
         } else {
@@ -324,9 +366,11 @@ __device__ bool eval_tile(const SweepArgs& a, int item, unsigned char* smem, uin
         }
         break;
       }
-      bit_set<NW>(Lw, cn);
       S -= mc;
     }
+#pragma unroll
+    for (int w = 0; w < NW; w++) Lw[w] &= ~Q[w];
+    if (cseg >= 0) bit_clear<NW>(Lw, cseg);
     // Lemma 1, plus the list-scheduling term if the members oversubscribe.
     if (W != 0) {
       uint64_t R = maxC;
@@ -334,48 +378,36 @@ __device__ bool eval_tile(const SweepArgs& a, int item, unsigned char* smem, uin
       bound += R;
       cp += maxC;
     }
-    // Finished now: the unfinished members (P) and the nodes launched whole.
-    uint64_t P[NW], gone[NW];
+    // Finished now: the unfinished members and the nodes launched whole.
+    uint64_t Dn[NW], gone[NW], Fu[NW];
 #pragma unroll
     for (int w = 0; w < NW; w++) {
-      P[w] = rel[w] & gm[w];
-      gone[w] = seg[w] & (P[w] | Lw[w]);
-      rel[w] &= ~(P[w] | Lw[w]);
+      Dn[w] = (rel[w] & gm[w]) | Lw[w];
+      gone[w] = seg[w] & Dn[w];
+      rel[w] &= ~Dn[w];
+      Fu[w] = gm[w] | wave_or64(Lw[w]);  // finished now in some lane
     }
     while (bits_any<NW>(gone)) {  // drop finished nodes from the residual table
-      const int x = bit_first<NW>(gone);
-      bit_clear<NW>(gone, x);
+      const int x = pop_first<NW>(gone);
       const int rk = bit_rank<NW>(seg, x);
       const int cnt = bit_count<NW>(seg);
       for (int i = rk; i + 1 < cnt; i++) res[i * WAVE + lane] = res[(i + 1) * WAVE + lane];
       bit_clear<NW>(seg, x);
     }
-    // Releases: each finished node decrements its successors' counters; a
-    // successor whose counter reaches zero is released.  Members are walked
-    // wave-uniformly, parallel nodes lane by lane.
-    for (int q = k; q < kend; q++) {
-      const int s = (int)(uni(s_mem[q].z) & 0x7FFFu);
-      const bool mine = bit_get<NW>(P, s);
-      if (!__ballot(mine)) continue;
-      const uint32_t e1 = uni(s_soff[s + 1]);
-      for (uint32_t e = uni(s_soff[s]); e < e1; e++) {
+    // Releases: every node finished now decrements its successors' counters
+    // in the lanes where it finished; a counter reaching zero releases its
+    // node.  The walk is wave-uniform over the nodes finished in some lane.
+    while (bits_any<NW>(Fu)) {
+      const int x = pop_first<NW>(Fu);
+      const bool mine = bit_get<NW>(Dn, x);
+      const uint32_t e1 = uni(s_soff[x + 1]);
+      for (uint32_t e = uni(s_soff[x]); e < e1; e++) {
         const int u = (int)uni(s_succ[e]);
         if (mine) {
-          const uint32_t x = (uint32_t)s_npr[u * WAVE + lane] - 1u;
-          s_npr[u * WAVE + lane] = (npr_t)x;
-          if (!x) bit_set<NW>(rel, u);
+          const int sh = CB * (u % CP);
+          const uint32_t old = atomicSub(&s_cnt[(u / CP) * WAVE + lane], 1u << sh);
+          if (((old >> sh) & CMASK) == 1u) bit_set<NW>(rel, u);
         }
-      }
-    }
-    while (bits_any<NW>(Lw)) {
-      const int x = bit_first<NW>(Lw);
-      bit_clear<NW>(Lw, x);
-      const uint32_t e1 = s_soff[x + 1];
-      for (uint32_t e = s_soff[x]; e < e1; e++) {
-        const int u = s_succ[e];
-        const uint32_t y = (uint32_t)s_npr[u * WAVE + lane] - 1u;
-        s_npr[u * WAVE + lane] = (npr_t)y;
-        if (!y) bit_set<NW>(rel, u);
       }
     }
     if (__ballot(ovf)) return true;
@@ -383,13 +415,13 @@ __device__ bool eval_tile(const SweepArgs& a, int item, unsigned char* smem, uin
   }
 
   if (active) {
-    const int64_t o = (int64_t)d * a.K + c;
+    const int64_t o = (int64_t)d * a.K + slot;
     if (a.bounds) a.bounds[o] = (int64_t)bound;
     if (a.cp) a.cp[o] = (int64_t)cp;
     if (a.intf) a.intf[o] = (int64_t)(bound - cp);
   }
   if (a.best) {
-    unsigned long long key = active ? ((bound << BEST_SHIFT) | (uint64_t)c) : ~0ull;
+    unsigned long long key = active ? ((bound << BEST_SHIFT) | (uint64_t)slot) : ~0ull;
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
       const unsigned long long y = __shfl_xor(key, o);
@@ -430,11 +462,13 @@ __global__ void k_eval_init(unsigned long long* best, int32_t D, uint32_t* ovf_c
   if (i == 0) *ovf_count = 0;
 }
 
-__global__ void k_best_final(const unsigned long long* best, int32_t D, int32_t* idx, int64_t* bnd) {
+__global__ void k_best_final(const unsigned long long* best, int32_t D, int32_t* idx, int64_t* bnd,
+                             const int32_t* list, int32_t K) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < D) {
     const unsigned long long k = best[i];
-    if (idx) idx[i] = (int32_t)(k & ((1ull << BEST_SHIFT) - 1));
+    const int32_t pos = (int32_t)(k & ((1ull << BEST_SHIFT) - 1));
+    if (idx) idx[i] = list ? list[(int64_t)i * K + pos] : pos;
     if (bnd) bnd[i] = (int64_t)(k >> BEST_SHIFT);
   }
 }
@@ -486,9 +520,10 @@ hipError_t launch_sweep(const SweepArgs& a, hipStream_t stream) {
 }
 
 hipError_t launch_best_final(const unsigned long long* best, int32_t D, int32_t* idx, int64_t* bound,
-                             hipStream_t stream) {
+                             const int32_t* list, int32_t K, hipStream_t stream) {
   if (D <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_best_final, dim3((D + 255) / 256), dim3(256), 0, stream, best, D, idx, bound);
+  hipLaunchKernelGGL(k_best_final, dim3((D + 255) / 256), dim3(256), 0, stream, best, D, idx, bound, list,
+                     K);
   return hipGetLastError();
 }
 

@@ -23,12 +23,15 @@ ALLOC_EXPLICIT, ALLOC_SEEDED = 0, 1
 SEARCH_EXHAUSTIVE, SEARCH_SURROGATE = 0, 1
 MAX_NODES_PER_DAG = 512
 MAX_CANDIDATES = 1 << 22
+MODEL_PARAMS = 100356
 
 # Every symbol include/dagbound.h declares.
 EXPORTS = (
     "dagbound_create_batch", "dagbound_set_allocations", "dagbound_eval_bounds",
     "dagbound_best_allocation", "dagbound_get_division", "dagbound_set_tuning",
-    "dagbound_destroy_batch",
+    "dagbound_destroy_batch", "dagbound_model_create", "dagbound_model_destroy",
+    "dagbound_model_params", "dagbound_model_forward", "dagbound_model_train_step",
+    "dagbound_model_select",
     "dagbound_last_error", "dagbound_version",
 )
 
@@ -67,6 +70,18 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.dagbound_destroy_batch.argtypes = [P]
     lib.dagbound_last_error.restype = ctypes.c_char_p
     lib.dagbound_last_error.argtypes = []
+    lib.dagbound_model_create.restype = I32
+    lib.dagbound_model_create.argtypes = [U64, ctypes.POINTER(P)]
+    lib.dagbound_model_destroy.restype = None
+    lib.dagbound_model_destroy.argtypes = [P]
+    lib.dagbound_model_params.restype = I32
+    lib.dagbound_model_params.argtypes = [P, P, P, P, P]
+    lib.dagbound_model_forward.restype = I32
+    lib.dagbound_model_forward.argtypes = [P, P, P, U32, P]
+    lib.dagbound_model_train_step.restype = I32
+    lib.dagbound_model_train_step.argtypes = [P, P, I32, U64, P, ctypes.c_float, P, U32, P]
+    lib.dagbound_model_select.restype = I32
+    lib.dagbound_model_select.argtypes = [P, P, I32, U64, I32, I32, P, P, U32, P]
     lib.dagbound_version.restype = ctypes.c_char_p
     lib.dagbound_version.argtypes = []
     _lib = lib
@@ -90,7 +105,7 @@ def _is_torch(x: Any) -> bool:
     return type(x).__module__.startswith("torch")
 
 
-_NP = {"int64": np.int64, "int32": np.int32, "uint8": np.uint8}
+_NP = {"int64": np.int64, "int32": np.int32, "uint8": np.uint8, "float32": np.float32}
 
 
 def _marshal(arrays: Sequence[Tuple[Any, str]]):
@@ -204,8 +219,80 @@ def best_allocation(batch: Batch, best_idx, best_bound, search: int = SEARCH_EXH
     """dagbound_best_allocation: per-DAG argmin candidate and its bound."""
     lib = load_library()
     (p_i, p_b), kind, keep = _marshal([(best_idx, "int32"), (best_bound, "int64")])
+    mh = ctypes.c_void_p(model.handle) if model is not None else None
     _check(lib.dagbound_best_allocation(ctypes.c_void_p(batch.handle), int(search), int(top_k),
-                                        model, p_i, p_b, kind, _stream_ptr(stream)))
+                                        mh, p_i, p_b, kind, _stream_ptr(stream)))
+
+
+class Model:
+    """Owning handle of a dagbound_model (learned candidate proposal)."""
+
+    def __init__(self, seed: int = 0):
+        out = ctypes.c_void_p()
+        _check(load_library().dagbound_model_create(ctypes.c_uint64(seed & (2**64 - 1)), ctypes.byref(out)))
+        self.handle = out.value
+
+    def close(self) -> None:
+        if self.handle:
+            load_library().dagbound_model_destroy(ctypes.c_void_p(self.handle))
+            self.handle = 0
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def params(self) -> np.ndarray:
+        out = np.empty(MODEL_PARAMS, np.float32)
+        _check(load_library().dagbound_model_params(ctypes.c_void_p(self.handle), out.ctypes.data,
+                                                    None, None, None))
+        return out
+
+    def set_params(self, p) -> None:
+        arr = np.ascontiguousarray(np.asarray(p, np.float32))
+        assert arr.size == MODEL_PARAMS
+        _check(load_library().dagbound_model_params(ctypes.c_void_p(self.handle), None, arr.ctypes.data,
+                                                    None, None))
+
+    def grad(self) -> np.ndarray:
+        out = np.empty(MODEL_PARAMS, np.float32)
+        _check(load_library().dagbound_model_params(ctypes.c_void_p(self.handle), None, None,
+                                                    out.ctypes.data, None))
+        return out
+
+    def step(self) -> int:
+        st = ctypes.c_int64(0)
+        _check(load_library().dagbound_model_params(ctypes.c_void_p(self.handle), None, None, None,
+                                                    ctypes.byref(st)))
+        return int(st.value)
+
+
+def model_forward(model: Model, batch: Batch, node_out, stream=None) -> None:
+    """dagbound_model_forward: per-node head coefficients [T_N][3]."""
+    (p_o,), kind, keep = _marshal([(node_out, "float32")])
+    _check(load_library().dagbound_model_forward(ctypes.c_void_p(model.handle), ctypes.c_void_p(batch.handle),
+                                                 p_o, kind, _stream_ptr(stream)))
+
+
+def model_train_step(model: Model, batch: Batch, K: int, seed: int, bounds, lr: float, stream=None) -> float:
+    """dagbound_model_train_step: one Adam step; returns the loss before it."""
+    (p_b,), kind, keep = _marshal([(bounds, "int64")])
+    loss = ctypes.c_float(0)
+    _check(load_library().dagbound_model_train_step(ctypes.c_void_p(model.handle), ctypes.c_void_p(batch.handle),
+                                                    int(K), ctypes.c_uint64(seed & (2**64 - 1)), p_b,
+                                                    ctypes.c_float(lr), ctypes.byref(loss), kind,
+                                                    _stream_ptr(stream)))
+    return float(loss.value)
+
+
+def model_select(model: Model, batch: Batch, K: int, seed: int, top_k: int, nodes: int, cand, scores=None,
+                 stream=None) -> None:
+    """dagbound_model_select: candidate lists [D][top_k+1] (device tensors)."""
+    (p_c, p_s), kind, keep = _marshal([(cand, "int32"), (scores, "float32")])
+    _check(load_library().dagbound_model_select(ctypes.c_void_p(model.handle), ctypes.c_void_p(batch.handle),
+                                                int(K), ctypes.c_uint64(seed & (2**64 - 1)), int(top_k),
+                                                int(nodes), p_c, p_s, kind, _stream_ptr(stream)))
 
 
 def get_division(batch: Batch, d: int):

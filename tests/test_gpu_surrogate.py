@@ -1,0 +1,194 @@
+"""Learned candidate proposal on the GPU against its float64 reference
+(oracle/surrogate_ref.py): features and forward pass, the gradient of one
+training step, determinism, training progress, and the surrogate-guided
+search against exhaustive search (bounds from the CPU oracle)."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from oracle import surrogate_ref as S
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2602_20826_amd as db
+
+    db.load_library()
+    return torch, db
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def rand_params(seed, scale=1.0):
+    rng = np.random.default_rng(seed)
+    p = {}
+    for name, shp in S.param_shapes():
+        if name.startswith("b"):
+            p[name] = rng.normal(0, 0.05, shp)
+        else:
+            fan = shp[0]
+            p[name] = rng.uniform(-1, 1, shp) * scale * np.sqrt(3.0 / fan)
+    return p
+
+
+def small_batch():
+    a = W.generate_workload(1, count=12)
+    b = W.generate_workload(2, count=4)
+    return W.from_dags([a.dag(d) for d in range(a.num_dags)] + [b.dag(d) for d in range(b.num_dags)])
+
+
+def reference_inputs(batch, M):
+    out = []
+    for d in range(batch.num_dags):
+        n, s, t, w, p = batch.dag(d)
+        div = oracle.division(n, s, t, w, p, M)
+        X = S.features(n, s, t, w, p, M, div.wanc, div.groups)
+        out.append((n, s, t, w, p, X, S.neighbours(n, s, t)))
+    return out
+
+
+def test_forward_matches_reference(env):
+    torch, db = env
+    M = 64
+    batch = small_batch()
+    params = rand_params(1)
+    model = db.Model(0)
+    model.set_params(S.flatten(params).astype(np.float32))
+    b = db.create_batch(batch.node_off, batch.edge_off, batch.src, batch.dst, batch.wcet, batch.par, M)
+    out = np.zeros((int(batch.node_off[-1]), 3), np.float32)
+    say("surrogate forward on", batch.num_dags, "DAGs")
+    db.model_forward(model, b, out)
+    p32 = S.unflatten(S.flatten(params).astype(np.float32))
+    errs, scale = [], 0.0
+    for d, (n, s, t, w, p, X, nb) in enumerate(reference_inputs(batch, M)):
+        ref = S.forward(p32, X, nb).A[:, :3]
+        n0 = int(batch.node_off[d])
+        got = out[n0:n0 + n]
+        errs.append(np.abs(got - ref).max())
+        scale = max(scale, np.abs(ref).max())
+        c = np.corrcoef(got.ravel(), ref.ravel())[0, 1] if n > 1 else 1.0
+        assert c > 0.999, (d, c)
+    # BF16 activations and weights through four layers: a few per cent of
+    # the output scale
+    assert max(errs) <= 0.03 * scale + 1e-3, (max(errs), scale)
+    b.close()
+    model.close()
+
+
+def test_gradient_matches_reference(env):
+    torch, db = env
+    M, K, seed = 64, 24, 77
+    batch = small_batch()
+    alloc = W.alloc_bytes(batch, M, K, seed=seed)
+    bounds, _, _ = oracle.bounds_batch(batch, M, K, alloc)
+    params = rand_params(2)
+    flat32 = S.flatten(params).astype(np.float32)
+    model = db.Model(0)
+    model.set_params(flat32)
+    b = db.create_batch(batch.node_off, batch.edge_off, batch.src, batch.dst, batch.wcet, batch.par, M)
+    db.set_allocations(b, K, db.ALLOC_SEEDED, None, seed)
+    say("surrogate gradient, lr = 0")
+    loss_gpu = db.model_train_step(model, b, K, seed, bounds.reshape(-1).copy(), 0.0)
+    g_gpu = model.grad()
+    assert model.step() == 0
+    p32 = S.unflatten(flat32)
+    scale = 1.0 / (batch.num_dags * (K - 1))
+    g_ref = {k: np.zeros_like(v) for k, v in p32.items()}
+    loss_ref = 0.0
+    for d, (n, s, t, w, p, X, nb) in enumerate(reference_inputs(batch, M)):
+        n0 = int(batch.node_off[d])
+        rb = alloc[K * n0: K * n0 + K * n].reshape(K, n)[1:].astype(np.float64)
+        rng_v = np.minimum(np.minimum(p, M), 255)
+        y = np.log(bounds[d, 1:].astype(np.float64)) - np.log(float(bounds[d, 0]))
+        l, g, _ = S.loss_and_grad(p32, X, nb, rb, rng_v, y, scale)
+        loss_ref += l
+        for k in g:
+            g_ref[k] += g[k]
+    assert abs(loss_gpu - loss_ref) <= 0.02 * abs(loss_ref) + 1e-6, (loss_gpu, loss_ref)
+    gr = S.flatten(g_ref)
+    gg = g_gpu.astype(np.float64)
+    cos = gr @ gg / (np.linalg.norm(gr) * np.linalg.norm(gg))
+    rel = np.linalg.norm(gg - gr) / np.linalg.norm(gr)
+    say(f"gradient cosine {cos:.6f} relative error {rel:.4f}")
+    assert cos >= 0.999 and rel <= 0.05
+    o = 0
+    for name, shp in S.param_shapes():
+        k = int(np.prod(shp))
+        a, r = gg[o:o + k], gr[o:o + k]
+        o += k
+        if np.linalg.norm(r) > 1e-6 * np.linalg.norm(gr):
+            c = a @ r / (np.linalg.norm(a) * np.linalg.norm(r))
+            assert c >= 0.99, (name, c)
+    b.close()
+    model.close()
+
+
+def test_training_is_deterministic_and_learns(env):
+    torch, db = env
+    wl = W.WORKLOADS[4]
+    M, K, seed = wl.num_cus, 64, 5
+    batch = W.generate_workload(4, count=300)
+    dev = torch.device("cuda:0")
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    b = db.create_batch(t(batch.node_off), t(batch.edge_off), t(batch.src), t(batch.dst), t(batch.wcet),
+                        t(batch.par), M)
+    db.set_allocations(b, K, db.ALLOC_SEEDED, None, seed)
+    bounds = torch.empty(batch.num_dags * K, dtype=torch.int64, device=dev)
+    db.eval_bounds(b, bounds)
+    say("training twice from the same seed")
+    runs = []
+    for rep in range(2):
+        model = db.Model(9)
+        losses = [db.model_train_step(model, b, K, seed, bounds, 3e-3) for _ in range(40)]
+        runs.append((losses, model.params()))
+        model.close()
+    assert runs[0][0] == runs[1][0]
+    assert np.array_equal(runs[0][1], runs[1][1])
+    losses = runs[0][0]
+    assert losses[-1] < 0.7 * losses[0], losses[::8]
+    b.close()
+
+
+def test_surrogate_search_is_exact_on_its_candidates(env):
+    torch, db = env
+    wl = W.WORKLOADS[4]
+    M, K, seed, top_k = wl.num_cus, 256, 3, 8
+    batch = W.generate_workload(4, count=40, first=1000)
+    alloc = W.alloc_bytes(batch, M, K, seed=seed)
+    want, _, _ = oracle.bounds_batch(batch, M, K, alloc, threads=8)
+    dev = torch.device("cuda:0")
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    b = db.create_batch(t(batch.node_off), t(batch.edge_off), t(batch.src), t(batch.dst), t(batch.wcet),
+                        t(batch.par), M)
+    db.set_allocations(b, K, db.ALLOC_SEEDED, None, seed)
+    model = db.Model(4)
+    cand = torch.empty(batch.num_dags * (top_k + 1), dtype=torch.int32, device=dev)
+    scores = torch.empty(batch.num_dags * K, dtype=torch.float32, device=dev)
+    say("surrogate selection and search")
+    db.model_select(model, b, K, seed, top_k, 32, cand, scores)
+    idx = np.empty(batch.num_dags, np.int32)
+    bb = np.empty(batch.num_dags, np.int64)
+    db.best_allocation(b, idx, bb, search=db.SEARCH_SURROGATE, top_k=top_k, model=model)
+    cand = cand.cpu().numpy().reshape(batch.num_dags, top_k + 1)
+    sc = scores.cpu().numpy().reshape(batch.num_dags, K)
+    for d in range(batch.num_dags):
+        lst = cand[d]
+        assert lst[0] == 0 and len(set(lst[1:].tolist())) == top_k and all(1 <= c < K for c in lst[1:])
+        # the listed candidates are the smallest scores (ties: smaller index)
+        order = sorted(range(1, K), key=lambda c: (sc[d, c], c))
+        assert lst[1:].tolist() == order[:top_k]
+        # the search returns the exact minimum over its list (ties: the
+        # candidate listed first)
+        pos = min(range(len(lst)), key=lambda i: (want[d, lst[i]], i))
+        assert bb[d] == want[d, lst[pos]] and idx[d] == lst[pos]
+        assert bb[d] <= want[d, 0]
+    b.close()
+    model.close()
