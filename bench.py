@@ -49,7 +49,7 @@ def algorithmic_bytes(batch, K: int) -> int:
     return int(np.sum(K * n + 8 * K + 17 * n + 4 * e))
 
 
-def measured_traffic(K_launch_bytes_key: str):
+def measured_traffic(workload_key: str):
     """HBM bytes per evaluation launch from the committed rocprofv3 counter
     summary, if it was taken on the current kernel source."""
     try:
@@ -57,9 +57,93 @@ def measured_traffic(K_launch_bytes_key: str):
             p = json.load(f)
     except (OSError, ValueError):
         return None
-    if p.get("source_hash") != sweep_source_hash() or p.get("workload") != K_launch_bytes_key:
+    if p.get("source_hash") != sweep_source_hash() or p.get("workload") != workload_key:
         return None
     return p.get("bytes_per_launch")
+
+
+COPY_PROBE_BYTES = 1 << 30
+
+
+def traffic_probe() -> int:
+    """Run under `rocprofv3 --pmc FETCH_SIZE` (then WRITE_SIZE): one plain
+    elementwise copy of COPY_PROBE_BYTES (read once, written once) to scale the
+    counters, then one evaluation launch of the benchmark workload."""
+    import torch
+
+    import paper_2602_20826_amd as db
+    import workloads as W
+
+    db.load_library()
+    dev = torch.device("cuda:0")
+    src = torch.ones(COPY_PROBE_BYTES // 4, dtype=torch.int32, device=dev)
+    dst = torch.empty_like(src)
+    torch.neg(src, out=dst)
+    torch.cuda.synchronize()
+    del src, dst
+    wl = W.WORKLOADS[2]
+    M, K = wl.num_cus, wl.K
+    batch = W.generate_workload(2)
+    alloc = W.alloc_bytes(batch, M, K, seed=wl.seed)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    b = db.create_batch(t(batch.node_off), t(batch.edge_off), t(batch.src), t(batch.dst), t(batch.wcet),
+                        t(batch.par), M)
+    db.set_allocations(b, K, db.ALLOC_EXPLICIT, t(alloc))
+    bounds = torch.empty(batch.num_dags * K, dtype=torch.int64, device=dev)
+    db.eval_bounds(b, bounds)
+    torch.cuda.synchronize()
+    b.close()
+    print(json.dumps({"traffic_probe": f"batched-layered/{batch.num_dags}x{K}",
+                      "copy_bytes": COPY_PROBE_BYTES,
+                      "algorithmic_bytes": algorithmic_bytes(batch, K)}), flush=True)
+    return 0
+
+
+def _counter_rows(path: str):
+    import csv
+
+    with open(path, newline="") as f:
+        for row in csv.DictReader(f):
+            yield row
+
+
+def write_traffic(fetch_csv: str, write_csv: str) -> int:
+    """Turn the two counter passes of `traffic_probe` into the traffic summary
+    read by `measured_traffic`: FETCH_SIZE and WRITE_SIZE (KiB per dispatch)
+    of the evaluation kernels, each scaled by what the same counter reads for
+    the copy of known size."""
+    out = {}
+    for name, path, copy_side in (("FETCH_SIZE", fetch_csv, "read"), ("WRITE_SIZE", write_csv, "written")):
+        per_kernel = {}
+        copy_kib = None
+        for row in _counter_rows(path):
+            if row.get("Counter_Name") != name:
+                continue
+            k = row["Kernel_Name"]
+            v = float(row["Counter_Value"])
+            if "neg_kernel" in k:
+                copy_kib = v
+            elif "dagbound" in k and ("k_eval" in k):
+                short = k.split("(")[0].replace("void dagbound::(anonymous namespace)::", "")
+                per_kernel[short] = per_kernel.get(short, 0.0) + v
+        if copy_kib is None:
+            raise SystemExit(f"{path}: no copy kernel row for {name}")
+        factor = COPY_PROBE_BYTES / (copy_kib * 1024.0)
+        out[name] = {"copy_kib": copy_kib, "bytes_per_kib": factor,
+                     "kernels_kib": per_kernel,
+                     "bytes": sum(per_kernel.values()) * 1024.0 * factor}
+    rec = {
+        "source_hash": sweep_source_hash(),
+        "workload": "batched-layered/100000x64",
+        "fetch_bytes": out["FETCH_SIZE"]["bytes"],
+        "write_bytes": out["WRITE_SIZE"]["bytes"],
+        "bytes_per_launch": out["FETCH_SIZE"]["bytes"] + out["WRITE_SIZE"]["bytes"],
+        "counters": out,
+    }
+    with open(PROFILE_TRAFFIC, "w") as f:
+        json.dump(rec, f, indent=1)
+    print(json.dumps(rec))
+    return 0
 
 
 def cpu_baseline(batch, M, K, alloc, gpu_bounds, max_seconds: float = 30.0):
@@ -97,7 +181,15 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--traffic-probe", action="store_true",
+                    help="one copy of known size plus one evaluation launch, for counter passes")
+    ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write the traffic summary from the two counter passes")
     args = ap.parse_args()
+    if args.write_traffic:
+        return write_traffic(*args.write_traffic)
+    if args.traffic_probe:
+        return traffic_probe()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
               "(DAGs are independent: a multi-GPU run would shard the batch by DAG)", file=sys.stderr)

@@ -597,19 +597,22 @@ void model_init_params(uint64_t seed, std::vector<float>& h) {
     z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
     return z ^ (z >> 31);
   };
-  auto fill = [&](int64_t off, int fan_in, int fan_out) {
+  // count entries from offset off, scaled for a layer of fan_in inputs and
+  // fan_out outputs (the message-passing layers see 2 * HID inputs)
+  auto fill = [&](int64_t off, int64_t count, int fan_in, int fan_out) {
     const double a = std::sqrt(6.0 / (fan_in + fan_out));
-    for (int64_t i = 0; i < (int64_t)fan_in * fan_out; i++) {
+    for (int64_t i = 0; i < count; i++) {
       const double u = (double)(mix(seed ^ mix((uint64_t)(off + i))) >> 11) / 9007199254740992.0;
       h[(size_t)(off + i)] = (float)((2.0 * u - 1.0) * a);
     }
   };
-  fill(SUR_OFF_W0, SUR_FIN, SUR_HID);
+  fill(SUR_OFF_W0, SUR_FIN * SUR_HID, SUR_FIN, SUR_HID);
   for (int l = 0; l < SUR_LAYERS; l++) {
-    fill(SUR_OFF_L1 + l * SUR_LAYER_STRIDE, 2 * SUR_HID, SUR_HID);
-    fill(SUR_OFF_L1 + l * SUR_LAYER_STRIDE + SUR_HID * SUR_HID, 2 * SUR_HID, SUR_HID);
+    const int64_t o = SUR_OFF_L1 + l * SUR_LAYER_STRIDE;
+    fill(o, SUR_HID * SUR_HID, 2 * SUR_HID, SUR_HID);
+    fill(o + SUR_HID * SUR_HID, SUR_HID * SUR_HID, 2 * SUR_HID, SUR_HID);
   }
-  fill(SUR_OFF_WA, SUR_HID, SUR_OUT);
+  fill(SUR_OFF_WA, SUR_HID * SUR_OUT, SUR_HID, SUR_OUT);
 }
 
 // Activation workspace of a batch; returns the argument block.

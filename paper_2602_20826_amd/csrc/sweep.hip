@@ -29,11 +29,15 @@ namespace {
 
 constexpr int WAVE = 64;
 
+// Word v / 64 of a bitset held in registers; a masked OR rather than an
+// indexed read keeps the array in registers.
 template <int NW>
 __device__ inline uint64_t word_of(const uint64_t (&b)[NW], int v) {
-  uint64_t w = b[0];
+  if constexpr (NW == 1) return b[0];
+  uint64_t w = 0;
+  const int q = v >> 6;
 #pragma unroll
-  for (int k = 1; k < NW; k++) w = (v >> 6) == k ? b[k] : w;
+  for (int k = 0; k < NW; k++) w |= b[k] & (0ull - (uint64_t)(q == k));
   return w;
 }
 template <int NW>
@@ -71,6 +75,14 @@ __device__ inline int pop_first(uint64_t (&b)[NW]) {
     }
     done = done || take;
   }
+  return r;
+}
+// Index of the highest set bit, or -1.
+template <int NW>
+__device__ inline int bit_last(const uint64_t (&b)[NW]) {
+  int r = -1;
+#pragma unroll
+  for (int k = 0; k < NW; k++) r = b[k] ? k * 64 + 63 - __builtin_clzll(b[k]) : r;
   return r;
 }
 template <int NW>
@@ -151,39 +163,76 @@ __device__ inline uint64_t wave_or64(uint64_t x) {
   return ((uint64_t)wave_or32((uint32_t)(x >> 32)) << 32) | wave_or32((uint32_t)x);
 }
 
-// Unfinished-predecessor counters, packed into dwords laid out [node / P][lane]
-// so a lane always hits its own bank: P = 4 byte counters while every
-// in-degree fits (N <= 256), P = 2 half-word counters above.  A decrement is
-// one LDS atomic subtract on the node's field (it never borrows: a counter is
-// positive until its last predecessor finishes).
-template <int NW> struct Cnt { static constexpr int PER = 4, BITS = 8; };
-template <> struct Cnt<8> { static constexpr int PER = 2, BITS = 16; };
+// Predecessor and successor bitsets of the DAG's nodes live in registers
+// (lane x holds the rows of nodes x, 64 + x, ...) while they are small, and
+// in LDS above that.
+template <int NW> struct RowsInRegs { static constexpr bool value = NW <= 2; };
 
 // LDS layout of one wavefront (bytes), for the batch's largest DAG.
 struct Lds {
-  size_t mem, node, soff, succ, ppv, res, r, npr, total;
+  size_t mem, node, ppv, inv, pb, sb, res, r, map, total;
 };
-__host__ __device__ inline Lds lds_layout(int maxn, int maxe, int nw, bool big) {
+__host__ __device__ inline Lds lds_layout(int maxn, int nw, bool big) {
+  const bool regs = nw <= 2;
   Lds l;
   size_t o = 0;
   l.mem = o;  o += (size_t)maxn * 16;           // members in group order
   l.node = o; o += (size_t)maxn * 8;            // node info by sigma rank
-  l.soff = o; o += (size_t)(maxn + 1) * 4;      // successor offsets by sigma rank
-  l.succ = o; o += ((size_t)maxe * 2 + 15) & ~(size_t)15;  // successor sigma ranks
   l.ppv = o;  o += ((size_t)maxn * 2 + 15) & ~(size_t)15;  // min(p, M) by local id
-  l.res = o;  o += big ? 0 : (size_t)RES_SLOTS * WAVE * 4;  // residual table
-  l.r = o;    o += (size_t)maxn * WAVE;         // candidate bytes [local id][lane]
-  l.npr = o;  o += (size_t)((maxn + 3) / 4 + 1) * WAVE * 4 * (nw == 8 ? 2 : 1);  // packed counters
+  l.inv = o;  o += ((size_t)maxn * 2 + 15) & ~(size_t)15;  // sigma rank by local id
+  l.res = o;  o += big ? 0 : (size_t)RES_SLOTS * WAVE * 4;  // residual table [slot][lane]
+  l.r = o;    o += (size_t)maxn * WAVE;         // candidate bytes [sigma][lane]
+  l.map = o;  o += big ? 0 : (size_t)((maxn + 7) / 8) * WAVE * 4;  // residual slot of a node, 4 bits
+  if (regs) {
+    // built in the candidate-byte region before the bytes are loaded
+    l.pb = l.r;
+    l.sb = l.r + (size_t)maxn * nw * 8;
+  } else {
+    l.pb = o; o += (size_t)maxn * nw * 8;       // predecessor bitsets by sigma rank
+    l.sb = o; o += (size_t)maxn * nw * 8;       // successor bitsets by sigma rank
+  }
   l.total = (o + 15) & ~(size_t)15;
   return l;
 }
 
-// One (DAG, 64-candidate tile).  Returns true if the lane tables overflowed
-// (nothing was written; the tile must be redone by the global-table pass).
+template <int NW>
+__device__ inline void load_row(uint64_t (&b)[NW], const uint64_t* row) {
+  if constexpr (NW == 1) {
+    b[0] = row[0];
+  } else {
+#pragma unroll
+    for (int k = 0; k < NW; k += 2) {
+      const ulonglong2 q = *(const ulonglong2*)(row + k);
+      b[k] = q.x;
+      b[k + 1] = q.y;
+    }
+  }
+}
+
+__device__ inline uint64_t readlane64(uint64_t x, int l) {
+  return ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(x >> 32), l) << 32) |
+         (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, l);
+}
+
+// Eq. 5's half-up share for loads below 2^22: W < 2^31 then, and a float
+// estimate from the slot's reciprocal of 2W is within one of the quotient;
+// one exact integer step corrects it.
+__device__ inline uint32_t round_share_small(uint32_t cv, uint32_t M, uint32_t W, float rw2) {
+  const uint64_t num = 2ull * cv * M + W;
+  const uint64_t den = 2ull * W;
+  uint32_t q = (uint32_t)(__builtin_fmaf(2.0f * (float)cv, (float)M, (float)W) * rw2);
+  const uint64_t pq = (uint64_t)q * den;
+  if (pq > num) q--;
+  else if (pq + den <= num) q++;
+  return q;
+}
+
+// One (DAG, 64-candidate tile).  Returns true if a lane's residual table
+// overflowed (nothing was written; the tile must be redone by the
+// global-table pass).
 template <int NW, bool BIG, bool SMALL>
 __device__ bool eval_tile(const SweepArgs& a, int item, unsigned char* smem, uint32_t* gres) {
-  constexpr int CP = Cnt<NW>::PER, CB = Cnt<NW>::BITS;
-  constexpr uint32_t CMASK = (1u << CB) - 1u;
+  constexpr bool REG = RowsInRegs<NW>::value;
   const int ntile = (a.K + WAVE - 1) / WAVE;
   const int d = item / ntile;
   const int tile = item - d * ntile;
@@ -192,57 +241,78 @@ __device__ bool eval_tile(const SweepArgs& a, int item, unsigned char* smem, uin
   const bool active = slot < a.K;
   const int c = a.cand_list ? (active ? a.cand_list[(int64_t)d * a.K + slot] : 0) : slot;  // candidate id
   const int64_t n0 = a.t.node_off[d];
-  const int N = (int)(a.t.node_off[d + 1] - n0);
+  const int N = (int)uni((uint32_t)(a.t.node_off[d + 1] - n0));
   const int64_t e0 = a.t.edge_off[d];
-  const int E = (int)(a.t.edge_off[d + 1] - e0);
   const uint32_t M = (uint32_t)a.M;
-  const Lds L = lds_layout(a.max_n, a.max_e, NW, BIG);
-  uint4* s_mem = (uint4*)(smem + L.mem);       // {C_hat, pp | v << 16, s | last << 31, 0}
-  uint2* s_node = (uint2*)(smem + L.node);     // {C_hat, pp | v << 16} by sigma rank
-  uint32_t* s_soff = (uint32_t*)(smem + L.soff);
-  uint16_t* s_succ = (uint16_t*)(smem + L.succ);
+  const Lds L = lds_layout(a.max_n, NW, BIG);
+  uint4* s_mem = (uint4*)(smem + L.mem);       // {C_hat, pp, s | last << 31, 0}
+  uint2* s_node = (uint2*)(smem + L.node);     // {C_hat, pp} by sigma rank
   uint16_t* s_ppv = (uint16_t*)(smem + L.ppv); // [local id]
-  uint32_t* res = BIG ? gres : (uint32_t*)(smem + L.res);  // [slot][lane]
-  uint8_t* s_r = smem + L.r;                   // [local id][lane]
-  uint32_t* s_cnt = (uint32_t*)(smem + L.npr); // [sigma / CP][lane]
-  const int qcap = BIG ? a.max_n : a.res_slots;
+  uint16_t* s_inv = (uint16_t*)(smem + L.inv); // [local id]
+  uint64_t* s_pb = (uint64_t*)(smem + L.pb);   // [sigma][NW]
+  uint64_t* s_sb = (uint64_t*)(smem + L.sb);   // [sigma][NW]
+  uint32_t* res = BIG ? gres : (uint32_t*)(smem + L.res);  // [slot][lane], or [sigma][lane] when BIG
+  uint8_t* s_r = smem + L.r;                   // [sigma][lane]
+  uint32_t* s_map = (uint32_t*)(smem + L.map); // [sigma / 8][lane], 4 bits per node: slot + 1
 
   // ---- DAG tables (shared by the 64 candidates)
   for (int s = lane; s < N; s += WAVE) s_node[s] = make_uint2(a.t.wc[n0 + s], a.t.pp[n0 + s]);
-  for (int s = lane; s <= N; s += WAVE) s_soff[s] = a.t.soff[n0 + d + s];
-  for (int e = lane; e < E; e += WAVE) s_succ[e] = a.t.succ[e0 + e];
+  for (int v = lane; v < N; v += WAVE) s_inv[v] = a.t.inv[n0 + v];
+  for (int i = lane; i < N * NW; i += WAVE) { s_pb[i] = 0; s_sb[i] = 0; }
   __syncthreads();
-  for (int v = lane; v < N; v += WAVE) {
-    const int s = a.t.inv[n0 + v];
-    const uint32_t y = s_node[s].y;
-    s_node[s].y = y | ((uint32_t)v << 16);
-    s_ppv[v] = (uint16_t)y;
+  for (int v = lane; v < N; v += WAVE) s_ppv[v] = (uint16_t)s_node[s_inv[v]].y;
+  // successor bitset of x (this lane's row) and predecessor bits of its successors
+  for (int x = lane; x < N; x += WAVE) {
+    uint64_t row[NW];
+#pragma unroll
+    for (int w = 0; w < NW; w++) row[w] = 0;
+    const uint32_t ea = a.t.soff[n0 + d + x], eb = a.t.soff[n0 + d + x + 1];
+    for (uint32_t e = ea; e < eb; e++) {
+      const int u = a.t.succ[e0 + e];
+      bit_set<NW>(row, u);
+      atomicOr((unsigned long long*)&s_pb[u * NW + (x >> 6)], 1ull << (x & 63));
+    }
+#pragma unroll
+    for (int w = 0; w < NW; w++) s_sb[x * NW + w] = row[w];
   }
-  __syncthreads();
   for (int k = lane; k < N; k += WAVE) {
     const uint32_t g = a.t.gl[n0 + k];
     const int s = g & 0x7FFF;
     const uint2 nd = s_node[s];
     s_mem[k] = make_uint4(nd.x, nd.y, (uint32_t)s | ((g & 0x8000u) << 16), 0u);
   }
-  // per-candidate unfinished-predecessor counters; sources are released
-  uint64_t rel[NW], seg[NW];
+  __syncthreads();
+  // released: the sources; finished: none.  With REG, lane x keeps the rows
+  // of nodes w * 64 + x.
+  uint64_t rel[NW], fin[NW], seg[NW];
+  uint64_t PB[REG ? NW : 1][REG ? NW : 1], SB[REG ? NW : 1][REG ? NW : 1];
 #pragma unroll
-  for (int w = 0; w < NW; w++) { rel[w] = 0; seg[w] = 0; }
-  for (int s0 = 0; s0 < N; s0 += CP) {
-    uint32_t packed = 0;
+  for (int w = 0; w < NW; w++) {
+    const int u = w * WAVE + lane;
+    uint64_t pr[NW], sr[NW];
 #pragma unroll
-    for (int i = 0; i < CP; i++) {
-      const int s = s0 + i;
-      if (s < N) {
-        const uint32_t np = a.t.indeg[n0 + s];
-        packed |= np << (CB * i);
-        if (np == 0) bit_set<NW>(rel, s);
-      }
+    for (int k = 0; k < NW; k++) { pr[k] = 0; sr[k] = 0; }
+    if (u < N) {
+      load_row<NW>(pr, s_pb + u * NW);
+      if (REG) load_row<NW>(sr, s_sb + u * NW);
     }
-    s_cnt[(s0 / CP) * WAVE + lane] = packed;
+    uint64_t any = 0;
+#pragma unroll
+    for (int k = 0; k < NW; k++) any |= pr[k];
+    rel[w] = __ballot(u < N && any == 0);
+    fin[w] = 0;
+    seg[w] = 0;
+    if constexpr (REG) {
+#pragma unroll
+      for (int k = 0; k < NW; k++) { PB[w][k] = pr[k]; SB[w][k] = sr[k]; }
+    }
   }
-  // ---- candidate bytes of this lane, by local id.  Candidate 0 is the
+  if (REG) __syncthreads();  // the rows' LDS becomes the candidate bytes
+  if (!BIG) {
+    for (int i = 0; i < (N + 7) / 8; i++) s_map[i * WAVE + lane] = 0;
+  }
+  uint32_t freem = (1u << a.res_slots) - 1u;  // free residual slots
+  // ---- candidate bytes of this lane, by sigma rank.  Candidate 0 is the
   // paper's own rule (all zero); lanes past K run zeros and store nothing.
   if (a.alloc) {
     if (c > 0 && active) {
@@ -258,7 +328,7 @@ __device__ bool eval_tile(const SweepArgs& a, int item, unsigned char* smem, uin
 #pragma unroll
         for (int j = 0; j < 16; j++) {
           const int64_t idx = (int64_t)(p + j) - (int64_t)rb;
-          if (idx >= 0 && idx < N) s_r[idx * WAVE + lane] = (uint8_t)(w4[j >> 2] >> (8 * (j & 3)));
+          if (idx >= 0 && idx < N) s_r[s_inv[idx] * WAVE + lane] = (uint8_t)(w4[j >> 2] >> (8 * (j & 3)));
         }
       }
     } else {
@@ -272,105 +342,161 @@ __device__ bool eval_tile(const SweepArgs& a, int item, unsigned char* smem, uin
       const uint32_t range = min((uint32_t)s_ppv[v], 255u);
       const uint32_t h16 = (uint32_t)(word >> (16 * (v & 3))) & 0xFFFFu;
       const uint32_t r = 1u + ((h16 * range) >> 16);
-      s_r[v * WAVE + lane] = (c > 0 && active) ? (uint8_t)r : (uint8_t)0;
+      s_r[s_inv[v] * WAVE + lane] = (c > 0 && active) ? (uint8_t)r : (uint8_t)0;
     }
   }
   __syncthreads();
 
+  // Remaining load of a segmented node.
+  auto res_at = [&](int s) -> uint32_t* {
+    if (BIG) return &res[s * WAVE + lane];
+    const uint32_t sl = ((s_map[(s >> 3) * WAVE + lane] >> (4 * (s & 7))) & 15u) - 1u;
+    return &res[sl * WAVE + lane];
+  };
+
   // ---- per-candidate sweep (Algorithm 2 and Theorem 1).  rel: released
-  // and unfinished (Algorithm 2's Released_nodes); seg: segmented nodes
-  // whose remaining load sits in the residual table.
+  // and unfinished (Algorithm 2's Released_nodes); fin: finished; seg:
+  // segmented and unfinished, remaining load in the residual table.
   uint64_t bound = 0, cp = 0;
   bool ovf = false;
   int k = 0;
   while (k < N) {
-    // Pass 1 over the group: its extent, member set, and W(pi_j), the
-    // remaining load of the members unfinished in this lane (Eq. 5).
+    // The group's extent from the members' end marks, 64 records at a time;
+    // the first 64 records stay in registers (lane i holds member k + i).
+    uint4 rec0 = make_uint4(0u, 0u, 0u, 0u);
+    if (k + lane < N) rec0 = s_mem[k + lane];
+    int kend;
+    {
+      const uint64_t ends = __ballot(k + lane < N && (rec0.z >> 31));
+      if (ends) {
+        kend = k + 1 + __builtin_ctzll(ends);
+      } else {
+        kend = k + WAVE;
+        while (kend < N) {
+          const bool e = kend + lane < N && (s_mem[kend + lane].z >> 31);
+          const uint64_t m = __ballot(e);
+          if (m) { kend += 1 + __builtin_ctzll(m); break; }
+          kend += WAVE;
+        }
+        kend = min(kend, N);
+      }
+    }
+    // Pass 1: member set and W(pi_j), the remaining load of the members
+    // unfinished in this lane (Eq. 5).
     uint64_t gm[NW];
 #pragma unroll
     for (int w = 0; w < NW; w++) gm[w] = 0;
     uint64_t W = 0;
-    int kend = k;
-    for (;;) {
-      const uint4 mm = s_mem[kend];
-      const int s = (int)(uni(mm.z) & 0x7FFFu);
-      bit_set<NW>(gm, s);
-      if (bit_get<NW>(rel, s)) {
-        uint32_t cv = uni(mm.x);
-        if (bit_get<NW>(seg, s)) cv = res[bit_rank<NW>(seg, s) * WAVE + lane];
-        W += cv;
+    for (int base = k; base < kend; base += WAVE) {
+      uint4 rec = rec0;
+      if (base != k && base + lane < kend) rec = s_mem[base + lane];
+      const int cnt = min(WAVE, kend - base);
+      for (int i = 0; i < cnt; i++) {
+        const int s = __builtin_amdgcn_readlane((int)rec.z, i) & 0x7FFF;
+        bit_set<NW>(gm, s);
+        if (bit_get<NW>(rel, s)) {
+          uint32_t cv = (uint32_t)__builtin_amdgcn_readlane((int)rec.x, i);
+          if (bit_get<NW>(seg, s)) cv = *res_at(s);
+          W += cv;
+        }
       }
-      kend++;
-      if ((uni(mm.z) >> 31) || kend >= N) break;
     }
     if (!__ballot(W != 0)) { k = kend; continue; }  // every member finished earlier
     // Pass 2: parallelism of each unfinished member (Eq. 5, or the candidate
-    // byte) and its execution time (Eq. 1, t_min = 1, m <= M).
+    // byte) and its execution time (Eq. 1, t_min = 1, m <= M).  The byte of
+    // the next member is read one step ahead.
+    const float rw2 = SMALL ? __builtin_amdgcn_rcpf((float)(2ull * W)) : 0.0f;
     uint32_t maxC = 0, sm = 0;
     uint64_t A = 0;
-    for (int q = k; q < kend; q++) {
-      const uint4 mm = s_mem[q];
-      const int s = (int)(uni(mm.z) & 0x7FFFu);
-      if (!bit_get<NW>(rel, s)) continue;
-      uint32_t cv = uni(mm.x);
-      if (bit_get<NW>(seg, s)) cv = res[bit_rank<NW>(seg, s) * WAVE + lane];
-      const uint32_t rv = s_r[(uni(mm.y) >> 16) * WAVE + lane];
-      const uint32_t mx = min(uni(mm.y) & 0xFFFFu, cv);
-      uint32_t m;
-      if (rv) m = min(rv, mx);
-      else m = max(1u, min(mx, round_share(cv, M, W)));
-      const uint32_t C = ceil_div<SMALL>(cv, m);
-      maxC = max(maxC, C);
-      sm += m;
-      A += (uint64_t)m * C;
+    for (int base = k; base < kend; base += WAVE) {
+      uint4 rec = rec0;
+      if (base != k && base + lane < kend) rec = s_mem[base + lane];
+      const int cnt = min(WAVE, kend - base);
+      uint32_t rnext = s_r[(__builtin_amdgcn_readlane((int)rec.z, 0) & 0x7FFF) * WAVE + lane];
+      for (int i = 0; i < cnt; i++) {
+        const int s = __builtin_amdgcn_readlane((int)rec.z, i) & 0x7FFF;
+        const uint32_t rv = rnext;
+        if (i + 1 < cnt) rnext = s_r[(__builtin_amdgcn_readlane((int)rec.z, i + 1) & 0x7FFF) * WAVE + lane];
+        if (!bit_get<NW>(rel, s)) continue;
+        uint32_t cv = (uint32_t)__builtin_amdgcn_readlane((int)rec.x, i);
+        if (bit_get<NW>(seg, s)) cv = *res_at(s);
+        const uint32_t mx = min((uint32_t)__builtin_amdgcn_readlane((int)rec.y, i), cv);
+        uint32_t m;
+        if (rv) m = min(rv, mx);
+        else m = max(1u, min(mx, SMALL ? round_share_small(cv, M, (uint32_t)W, rw2) : round_share(cv, M, W)));
+        const uint32_t C = ceil_div<SMALL>(cv, m);
+        maxC = max(maxC, C);
+        sm += m;
+        A += (uint64_t)m * C;
+      }
     }
     // Eqs. 6-7: parallel nodes (released, outside the group) take the S spare
     // compute units, largest W^anc first; a node that does not fit in
-    // maxC * m is segmented there and the launching stops.  The nodes taken
-    // from Q and not segmented are the ones launched whole.
+    // maxC * m is segmented there and the launching stops.  Each lane walks
+    // its own parallel set; the next node's data are read one step ahead.
+    // The nodes taken from Q and not segmented are the ones launched whole.
     uint32_t S = (W != 0 && sm < M) ? M - sm : 0u;
     uint64_t Q[NW], Lw[NW];
 #pragma unroll
     for (int w = 0; w < NW; w++) { Q[w] = rel[w] & ~gm[w]; Lw[w] = Q[w]; }
     int cseg = -1;
-    while (S) {
-      const int cn = pop_first<NW>(Q);
-      if (cn < 0) break;
-      const uint2 nd = s_node[cn];
-      const bool sg = bit_get<NW>(seg, cn);
-      int rk = 0;
-      uint32_t cc = nd.x;
-      if (sg) {
-        rk = bit_rank<NW>(seg, cn);
-        cc = res[rk * WAVE + lane];
-      }
-      const uint32_t rc = s_r[(nd.y >> 16) * WAVE + lane];
-      const uint32_t mx = min(nd.y & 0xFFFFu, cc);
-      const uint32_t mc = min(rc ? min(rc, mx) : mx, S);
+    bool csg = false;
+    uint32_t cleft = 0;
+    int cn = S ? pop_first<NW>(Q) : -1;
+    int ci = max(cn, 0);
+    uint2 nd = s_node[ci];
+    uint32_t rc = s_r[ci * WAVE + lane];
+    uint32_t mw = BIG ? 0u : s_map[(ci >> 3) * WAVE + lane];
+    bool go = cn >= 0;
+    while (go) {
+      const int cur = cn;
+      const uint2 ndc = nd;
+      const uint32_t rcc = rc, mwc = mw;
+      cn = pop_first<NW>(Q);
+      ci = max(cn, 0);
+      nd = s_node[ci];
+      rc = s_r[ci * WAVE + lane];
+      if (!BIG) mw = s_map[(ci >> 3) * WAVE + lane];
+      uint32_t nib = 0;
+      bool sg;
+      if (BIG) sg = bit_get<NW>(seg, cur);
+      else { nib = (mwc >> (4 * (cur & 7))) & 15u; sg = nib != 0; }
+      uint32_t cc = ndc.x;
+      if (sg) cc = BIG ? res[cur * WAVE + lane] : res[(nib - 1u) * WAVE + lane];
+      const uint32_t mx = min(ndc.y, cc);
+      const uint32_t mc = min(rcc ? min(rcc, mx) : mx, S);
       const uint64_t cap = (uint64_t)maxC * mc;
-      if ((uint64_t)cc > cap) {
-        const uint32_t left = cc - (uint32_t)cap;
-        cseg = cn;
-        if (sg) {
-          res[rk * WAVE + lane] = left;
-        } else {
-          rk = bit_rank<NW>(seg, cn);
-          const int cnt = bit_count<NW>(seg);
-          if (cnt >= qcap) {
-            ovf = true;
-          } else {
-            for (int i = cnt; i > rk; i--) res[i * WAVE + lane] = res[(i - 1) * WAVE + lane];
-            res[rk * WAVE + lane] = left;
-            bit_set<NW>(seg, cn);
-          }
-        }
-        break;
+      const bool fits = (uint64_t)cc <= cap;
+      if (!fits) {
+        cseg = cur;
+        csg = sg;
+        cleft = cc - (uint32_t)cap;
       }
-      S -= mc;
+      S -= fits ? mc : 0u;
+      go = fits && S != 0 && cn >= 0;
     }
+    if (cn >= 0) bit_set<NW>(Q, cn);  // read ahead, not launched
 #pragma unroll
     for (int w = 0; w < NW; w++) Lw[w] &= ~Q[w];
     if (cseg >= 0) bit_clear<NW>(Lw, cseg);
+    if (cseg >= 0) {
+      if (csg) {
+        *res_at(cseg) = cleft;
+      } else if (BIG) {
+        res[cseg * WAVE + lane] = cleft;
+        bit_set<NW>(seg, cseg);
+      } else if (freem == 0) {
+        ovf = true;
+      } else {
+        const uint32_t sl = (uint32_t)__builtin_ctz(freem);
+        freem &= freem - 1u;
+        res[sl * WAVE + lane] = cleft;
+        uint32_t* mp = &s_map[(cseg >> 3) * WAVE + lane];
+        const int sh = 4 * (cseg & 7);
+        *mp = (*mp & ~(15u << sh)) | ((sl + 1u) << sh);
+        bit_set<NW>(seg, cseg);
+      }
+    }
     // Lemma 1, plus the list-scheduling term if the members oversubscribe.
     if (W != 0) {
       uint64_t R = maxC;
@@ -384,32 +510,81 @@ __device__ bool eval_tile(const SweepArgs& a, int item, unsigned char* smem, uin
     for (int w = 0; w < NW; w++) {
       Dn[w] = (rel[w] & gm[w]) | Lw[w];
       gone[w] = seg[w] & Dn[w];
+      seg[w] &= ~Dn[w];
       rel[w] &= ~Dn[w];
+      fin[w] |= Dn[w];
       Fu[w] = gm[w] | wave_or64(Lw[w]);  // finished now in some lane
     }
-    while (bits_any<NW>(gone)) {  // drop finished nodes from the residual table
-      const int x = pop_first<NW>(gone);
-      const int rk = bit_rank<NW>(seg, x);
-      const int cnt = bit_count<NW>(seg);
-      for (int i = rk; i + 1 < cnt; i++) res[i * WAVE + lane] = res[(i + 1) * WAVE + lane];
-      bit_clear<NW>(seg, x);
+    if (!BIG) {  // free the residual slots of finished segmented nodes
+      while (bits_any<NW>(gone)) {
+        const int x = pop_first<NW>(gone);
+        const uint32_t sl = (s_map[(x >> 3) * WAVE + lane] >> (4 * (x & 7))) & 15u;
+        freem |= 1u << (sl - 1u);
+      }
     }
-    // Releases: every node finished now decrements its successors' counters
-    // in the lanes where it finished; a counter reaching zero releases its
-    // node.  The walk is wave-uniform over the nodes finished in some lane.
-    while (bits_any<NW>(Fu)) {
-      const int x = pop_first<NW>(Fu);
-      const bool mine = bit_get<NW>(Dn, x);
-      const uint32_t e1 = uni(s_soff[x + 1]);
-      for (uint32_t e = uni(s_soff[x]); e < e1; e++) {
-        const int u = (int)uni(s_succ[e]);
-        if (mine) {
-          const int sh = CB * (u % CP);
-          const uint32_t old = atomicSub(&s_cnt[(u / CP) * WAVE + lane], 1u << sh);
-          if (((old >> sh) & CMASK) == 1u) bit_set<NW>(rel, u);
+    // Releases: a successor of a node finished now (in some lane) is
+    // released in the lanes where all its predecessors have finished.
+    // Successor rows are OR-ed lane-parallel (lane x takes node w * 64 + x).
+    uint64_t cand[NW];
+    {
+      uint64_t acc[NW];
+#pragma unroll
+      for (int k2 = 0; k2 < NW; k2++) acc[k2] = 0;
+#pragma unroll
+      for (int w = 0; w < NW; w++) {
+        if ((Fu[w] >> lane) & 1) {
+          uint64_t sr[NW];
+          if constexpr (REG) {
+#pragma unroll
+            for (int k2 = 0; k2 < NW; k2++) sr[k2] = SB[w][k2];
+          } else {
+            load_row<NW>(sr, s_sb + (w * WAVE + lane) * NW);
+          }
+#pragma unroll
+          for (int k2 = 0; k2 < NW; k2++) acc[k2] |= sr[k2];
+        }
+      }
+#pragma unroll
+      for (int k2 = 0; k2 < NW; k2++) cand[k2] = wave_or64(acc[k2]);
+    }
+    // A node found ready is added to rel even where it has finished already;
+    // rel is cut back to the unfinished nodes after the walk.
+    if constexpr (REG) {
+#pragma unroll
+      for (int w = 0; w < NW; w++) {
+        uint64_t cw = cand[w];
+        while (cw) {
+          const int ul = __builtin_ctzll(cw);
+          cw &= cw - 1;
+          uint64_t open = 0;
+#pragma unroll
+          for (int k2 = 0; k2 < NW; k2++) open |= readlane64(PB[w][k2], ul) & ~fin[k2];
+          if (open == 0) rel[w] |= 1ull << ul;
+        }
+      }
+    } else {
+      while (bits_any<NW>(cand)) {  // four rows in flight
+        int u[4];
+        uint64_t pr[4][NW];
+#pragma unroll
+        for (int t = 0; t < 4; t++) u[t] = pop_first<NW>(cand);
+#pragma unroll
+        for (int t = 0; t < 4; t++) {
+          if (u[t] >= 0) load_row<NW>(pr[t], s_pb + u[t] * NW);
+        }
+#pragma unroll
+        for (int t = 0; t < 4; t++) {
+          if (u[t] >= 0) {
+            uint64_t open = 0;
+#pragma unroll
+            for (int k2 = 0; k2 < NW; k2++) open |= pr[t][k2] & ~fin[k2];
+            if (open == 0) bit_set<NW>(rel, u[t]);
+          }
         }
       }
     }
+#pragma unroll
+    for (int w = 0; w < NW; w++) rel[w] &= ~fin[w];
     if (__ballot(ovf)) return true;
     k = kend;
   }
@@ -482,14 +657,14 @@ hipError_t launch_nw(const SweepArgs& a, hipStream_t stream) {
                      a.ovf_count);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if (a.path != EVAL_PATH_GLOBAL) {
-    const size_t lds = lds_layout(a.max_n, a.max_e, NW, false).total;
+    const size_t lds = lds_layout(a.max_n, NW, false).total;
     e = hipFuncSetAttribute((const void*)k_eval<NW, SMALL>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_eval<NW, SMALL>), dim3(total), dim3(WAVE), lds, stream, a);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
-  const size_t lds = lds_layout(a.max_n, a.max_e, NW, true).total;
+  const size_t lds = lds_layout(a.max_n, NW, true).total;
   e = hipFuncSetAttribute((const void*)k_eval_global<NW, SMALL>,
                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
@@ -506,7 +681,8 @@ hipError_t launch_nw(const SweepArgs& a, hipStream_t stream) {
 
 size_t sweep_lds_need(int max_n, int max_e) {
   const int nw = (max_n + 63) / 64;
-  return lds_layout(max_n, max_e, nw <= 1 ? 1 : nw <= 2 ? 2 : nw <= 4 ? 4 : 8, false).total;
+  (void)max_e;
+  return lds_layout(max_n, nw <= 1 ? 1 : nw <= 2 ? 2 : nw <= 4 ? 4 : 8, false).total;
 }
 
 hipError_t launch_sweep(const SweepArgs& a, hipStream_t stream) {
