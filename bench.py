@@ -20,6 +20,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -124,7 +125,8 @@ def write_traffic(fetch_csv: str, write_csv: str) -> int:
             if "neg_kernel" in k:
                 copy_kib = v
             elif "dagbound" in k and ("k_eval" in k):
-                short = k.split("(")[0].replace("void dagbound::(anonymous namespace)::", "")
+                m = re.search(r"(k_eval\w*(<[^>]*>)?)", k)
+                short = m.group(1) if m else k
                 per_kernel[short] = per_kernel.get(short, 0.0) + v
         if copy_kib is None:
             raise SystemExit(f"{path}: no copy kernel row for {name}")
@@ -133,6 +135,11 @@ def write_traffic(fetch_csv: str, write_csv: str) -> int:
                      "kernels_kib": per_kernel,
                      "bytes": sum(per_kernel.values()) * 1024.0 * factor}
     rec = {
+        "commands": [
+            "rocprofv3 --pmc FETCH_SIZE --output-format csv -d fetch -o fetch -- python3 bench.py --traffic-probe",
+            "rocprofv3 --pmc WRITE_SIZE --output-format csv -d write -o write -- python3 bench.py --traffic-probe",
+            "python3 bench.py --write-traffic fetch/fetch_counter_collection.csv write/write_counter_collection.csv",
+        ],
         "source_hash": sweep_source_hash(),
         "workload": "batched-layered/100000x64",
         "fetch_bytes": out["FETCH_SIZE"]["bytes"],
@@ -275,7 +282,7 @@ def main() -> int:
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": measured_traffic(key),
-            "kernel": "k_sweep",
+            "kernel": "k_eval (one eval_bounds launch: k_eval_init, k_eval, k_eval_global)",
             "kernel_ms": sweep_ms,
             "algorithmic_bytes_per_launch": alg,
         },
