@@ -185,13 +185,16 @@ dagbound_status dagbound_get_division(dagbound_batch* batch, int32_t d, int64_t*
 /*
  * dagbound_set_tuning -- launch-plan options of the evaluation kernels; they
  * never change results.
- *   "residual_slots"  1..12 (default 12): per-candidate table slots for the
- *                     remaining loads of segmented nodes in the first
- *                     evaluation pass; a 64-candidate tile that needs more is
- *                     re-evaluated by the second pass, whose tables live in
- *                     global memory and hold every node.
- *   "eval_path"       0 (default): first pass, then the second pass for the
- *                     tiles it hands over; 1: the second pass for every tile.
+ *   "residual_slots"  1..12 (default 12): per-candidate LDS table slots for
+ *                     the remaining loads of segmented nodes; a 64-candidate
+ *                     tile that needs more restarts with a table in global
+ *                     memory that holds every node (256 such tables per
+ *                     batch; further tiles wait for a second pass).
+ *   "eval_path"       0 (default): LDS tables first, as above; 1: global
+ *                     tables for every tile.
+ *   "size_classes"    1 (default): one launch per DAG size class (up to 64,
+ *                     128, 256, 512 nodes); 0: one launch over all DAGs,
+ *                     sized for the largest.
  * Errors: E_ARG (unknown key or value).
  */
 dagbound_status dagbound_set_tuning(dagbound_batch* batch, const char* key, int64_t value);

@@ -134,7 +134,7 @@ struct Carve {
 size_t table_bytes(int64_t D, int64_t tn, int64_t te, int64_t max_n) {
   return 18 * 256 + (size_t)(D + 1) * 8 * 2 + (size_t)tn * 8 + (size_t)D * 8 + 16 +
          (size_t)tn * 4 + (size_t)(tn + D) * 4 + (size_t)D * 4 + (size_t)tn * 2 * 4 +
-         (size_t)te * 2 + (size_t)GLOBAL_PASS_GRID * (size_t)max_n * 64 * 4;
+         (size_t)te * 2 + (size_t)GLOBAL_PASS_GRID * (size_t)max_n * 64 * 4 + (size_t)D * 4;
 }
 
 }  // namespace
@@ -152,6 +152,12 @@ struct dagbound_batch {
   unsigned long long* err = nullptr;   // [2] first failing DAG, largest load
   uint32_t* gres = nullptr;            // residual tables of the global evaluation pass
   bool small_loads = false;            // every load < 2^22
+  // DAG ids grouped by size class (the evaluation launches one kernel per class)
+  int32_t* order = nullptr;
+  std::vector<int32_t> order_host;
+  int32_t class_off[NUM_CLASSES + 1] = {0, 0, 0, 0, 0};
+  int32_t class_max_n[NUM_CLASSES] = {0, 0, 0, 0};
+  bool size_classes = true;
   // per-allocation-set scratch: tiles handed to the global pass
   void* ovf_block = nullptr;
   size_t ovf_block_size = 0;
@@ -196,6 +202,9 @@ SweepArgs sweep_args(const dagbound_batch* b) {
   a.seed = b->seed;
   a.max_n = b->max_n;
   a.max_e = b->max_e;
+  a.order = b->size_classes ? b->order : nullptr;
+  for (int c = 0; c <= NUM_CLASSES; c++) a.class_off[c] = b->class_off[c];
+  for (int c = 0; c < NUM_CLASSES; c++) a.class_max_n[c] = b->class_max_n[c];
   a.ovf_list = b->ovf_list;
   a.ovf_count = b->ovf_count;
   a.gres = b->gres;
@@ -295,6 +304,19 @@ dagbound_status dagbound_create_batch(int32_t num_dags, const int64_t* node_off,
   b->t.indeg = cv.take<uint16_t>(tn);
   b->t.inv = cv.take<uint16_t>(tn);
   b->t.succ = cv.take<uint16_t>(te);
+  b->order = cv.take<int32_t>(D);
+  {
+    std::vector<int32_t> cnt(NUM_CLASSES + 1, 0);
+    for (int64_t d = 0; d < D; d++) {
+      const int cls = class_of((int)(no[d + 1] - no[d]));
+      cnt[cls + 1]++;
+      b->class_max_n[cls] = std::max<int32_t>(b->class_max_n[cls], (int32_t)(no[d + 1] - no[d]));
+    }
+    for (int c = 0; c < NUM_CLASSES; c++) cnt[c + 1] += cnt[c];
+    for (int c = 0; c <= NUM_CLASSES; c++) b->class_off[c] = cnt[c];
+    b->order_host.resize((size_t)D);
+    for (int64_t d = 0; d < D; d++) b->order_host[(size_t)cnt[class_of((int)(no[d + 1] - no[d]))]++] = (int32_t)d;
+  }
 
   // Inputs: device pointers are read in place; host arrays go through a
   // staging block that is released when this call returns.
@@ -303,6 +325,8 @@ dagbound_status dagbound_create_batch(int32_t num_dags, const int64_t* node_off,
   size_t stage_size = 0;
   e = hipMemcpyAsync(d_no, no.data(), (D + 1) * 8, hipMemcpyHostToDevice, st);
   if (e == hipSuccess) e = hipMemcpyAsync(d_eo, eo.data(), (D + 1) * 8, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess && D > 0)
+    e = hipMemcpyAsync(b->order, b->order_host.data(), (size_t)D * 4, hipMemcpyHostToDevice, st);
   if (e == hipSuccess && ptr_kind == DAGBOUND_PTR_HOST && (tn + te) > 0) {
     stage_size = 4 * 256 + (size_t)te * 8 + (size_t)tn * 12;
     e = dev_alloc(&stage, &stage_size, device);
@@ -393,7 +417,7 @@ dagbound_status dagbound_set_allocations(dagbound_batch* b, int32_t K, uint32_t 
     b->seed = seed;
   }
   const size_t tiles = (size_t)b->D * (size_t)((K + 63) / 64);
-  const size_t need = 512 + tiles * 4;
+  const size_t need = 512 + 2 * NUM_CLASSES * 4 + tiles * 4;
   if (b->ovf_block_size < need) {
     dev_release(b->ovf_block, b->ovf_block_size, b->device);
     b->ovf_block = nullptr;
@@ -407,7 +431,7 @@ dagbound_status dagbound_set_allocations(dagbound_batch* b, int32_t K, uint32_t 
     }
   }
   Carve oc(b->ovf_block);
-  b->ovf_count = oc.take<uint32_t>(1);
+  b->ovf_count = oc.take<uint32_t>(2 * NUM_CLASSES);
   b->ovf_list = oc.take<uint32_t>(tiles);
   b->K = K;
   b->mode = mode;
@@ -561,6 +585,9 @@ dagbound_status dagbound_set_tuning(dagbound_batch* b, const char* key, int64_t 
   } else if (!strcmp(key, "eval_path")) {
     if (value != EVAL_PATH_AUTO && value != EVAL_PATH_GLOBAL) return fail(DAGBOUND_E_ARG, "eval_path must be 0 or 1");
     b->eval_path = (int32_t)value;
+  } else if (!strcmp(key, "size_classes")) {
+    if (value != 0 && value != 1) return fail(DAGBOUND_E_ARG, "size_classes must be 0 or 1");
+    b->size_classes = value != 0;
   } else {
     return fail(DAGBOUND_E_ARG, "unknown tuning key '%s'", key);
   }

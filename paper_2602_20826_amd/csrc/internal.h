@@ -44,13 +44,26 @@ hipError_t launch_prep(const Tables& t, const PrepInputs& in, int32_t D, int32_t
 // Slots of the per-lane table of segmented residuals in the first
 // evaluation pass; a tile that needs more goes to the global-memory pass.
 constexpr int RES_SLOTS = 12;
-// Workgroups of the global-memory pass (each owns max_n * 64 residual words).
+// Global-memory residual tables (max_n * 64 words each): a first-pass tile
+// that overflows its LDS table takes one and finishes at once; the second
+// pass (one workgroup per table) takes the tiles left when all are taken.
 constexpr int GLOBAL_PASS_GRID = 256;
 enum : int32_t { EVAL_PATH_AUTO = 0, EVAL_PATH_GLOBAL = 1 };
+
+// DAGs are evaluated in size classes (up to 64, 128, 256, 512 nodes), one
+// launch per class, so that a small DAG never pays for a large one's
+// bitsets and LDS.
+constexpr int NUM_CLASSES = 4;
+__host__ __device__ constexpr int class_of(int n) { return n <= 64 ? 0 : n <= 128 ? 1 : n <= 256 ? 2 : 3; }
 
 struct SweepArgs {
   Tables t;
   int32_t D, M, K;
+  const int32_t* order;         // [D] DAG ids grouped by size class, or nullptr (one class: all DAGs)
+  int32_t class_off[NUM_CLASSES + 1];  // host: class c holds order[class_off[c] .. class_off[c + 1])
+  int32_t class_max_n[NUM_CLASSES];    // host: largest DAG of each class
+  const int32_t* dag_list;      // device: the DAGs of the launch (set per class), or nullptr
+  int32_t list_len;             // DAGs in the launch
   const uint8_t* alloc;         // explicit bytes, or nullptr when seeded
   uint64_t seed;
   int64_t* bounds;              // [D*K] or nullptr
@@ -58,7 +71,7 @@ struct SweepArgs {
   int64_t* intf;                // [D*K] or nullptr
   unsigned long long* best;     // [D] packed (bound << 22 | c), atomicMin
   uint32_t* ovf_list;           // [D * ceil(K/64)] tiles handed to the global pass
-  uint32_t* ovf_count;          // [1]
+  uint32_t* ovf_count;          // [2 * NUM_CLASSES]: per class, tiles listed and global tables taken
   uint32_t* gres;               // [GLOBAL_PASS_GRID][max_n][64] residual tables
   int32_t max_n, max_e;
   const int32_t* cand_list;     // [D][K] candidate ids to evaluate, or nullptr (ids 0..K-1)

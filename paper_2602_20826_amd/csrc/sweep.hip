@@ -234,8 +234,9 @@ template <int NW, bool BIG, bool SMALL>
 __device__ bool eval_tile(const SweepArgs& a, int item, unsigned char* smem, uint32_t* gres) {
   constexpr bool REG = RowsInRegs<NW>::value;
   const int ntile = (a.K + WAVE - 1) / WAVE;
-  const int d = item / ntile;
-  const int tile = item - d * ntile;
+  const int li = item / ntile;
+  const int tile = item - li * ntile;
+  const int d = a.dag_list ? a.dag_list[li] : li;
   const int lane = threadIdx.x;
   const int slot = tile * WAVE + lane;  // output position
   const bool active = slot < a.K;
@@ -607,34 +608,45 @@ __device__ bool eval_tile(const SweepArgs& a, int item, unsigned char* smem, uin
   return false;
 }
 
-// First pass: one tile per workgroup, residual tables in LDS.
+// First pass: one tile per workgroup, residual table in LDS.  A tile that
+// overflows it restarts at once with one of the global-memory tables, or,
+// when all are taken, is listed for the second pass.
 template <int NW, bool SMALL>
-__global__ __launch_bounds__(64) void k_eval(SweepArgs a) {
+__global__ __launch_bounds__(64) void k_eval(SweepArgs a, uint32_t* counters, uint32_t* list) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int item = blockIdx.x;
   if (eval_tile<NW, false, SMALL>(a, item, smem, nullptr)) {
-    if (threadIdx.x == 0) a.ovf_list[atomicAdd(a.ovf_count, 1u)] = (uint32_t)item;
+    uint32_t g = 0;
+    if (threadIdx.x == 0) g = atomicAdd(&counters[1], 1u);
+    g = __shfl(g, 0);
+    __syncthreads();
+    if (g < (uint32_t)GLOBAL_PASS_GRID) {
+      eval_tile<NW, true, SMALL>(a, item, smem, a.gres + (size_t)g * (size_t)a.max_n * WAVE);
+    } else if (threadIdx.x == 0) {
+      list[atomicAdd(&counters[0], 1u)] = (uint32_t)item;
+    }
   }
 }
 
-// Second pass: the tiles the first pass handed over (or every tile when
+// Second pass: the tiles the first pass listed (or every tile when
 // `direct`), residual tables in global memory sized to hold every node.
 template <int NW, bool SMALL>
-__global__ __launch_bounds__(64) void k_eval_global(SweepArgs a, int direct, int total) {
+__global__ __launch_bounds__(64) void k_eval_global(SweepArgs a, const uint32_t* counters, const uint32_t* list,
+                                                    int direct, int total) {
   extern __shared__ __align__(16) unsigned char smem[];
-  const int count = direct ? total : (int)*a.ovf_count;
+  const int count = direct ? total : (int)counters[0];
   uint32_t* gres = a.gres + (size_t)blockIdx.x * (size_t)a.max_n * WAVE;
   for (int q = blockIdx.x; q < count; q += gridDim.x) {
-    const int item = direct ? q : (int)a.ovf_list[q];
+    const int item = direct ? q : (int)list[q];
     eval_tile<NW, true, SMALL>(a, item, smem, gres);
     __syncthreads();
   }
 }
 
-__global__ void k_eval_init(unsigned long long* best, int32_t D, uint32_t* ovf_count) {
+__global__ void k_eval_init(unsigned long long* best, int32_t D, uint32_t* counters) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < D) best[i] = ~0ull;
-  if (i == 0) *ovf_count = 0;
+  if (i < 2 * NUM_CLASSES) counters[i] = 0;
 }
 
 __global__ void k_best_final(const unsigned long long* best, int32_t D, int32_t* idx, int64_t* bnd,
@@ -649,19 +661,17 @@ __global__ void k_best_final(const unsigned long long* best, int32_t D, int32_t*
 }
 
 template <int NW, bool SMALL>
-hipError_t launch_nw(const SweepArgs& a, hipStream_t stream) {
+hipError_t launch_nw(const SweepArgs& a, uint32_t* counters, uint32_t* list, hipStream_t stream) {
   const int ntile = (a.K + WAVE - 1) / WAVE;
-  const int total = a.D * ntile;
+  const int total = a.list_len * ntile;
   hipError_t e = hipSuccess;
-  hipLaunchKernelGGL(k_eval_init, dim3((a.D + 255) / 256), dim3(256), 0, stream, a.best, a.D,
-                     a.ovf_count);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if (total <= 0) return e;
   if (a.path != EVAL_PATH_GLOBAL) {
     const size_t lds = lds_layout(a.max_n, NW, false).total;
     e = hipFuncSetAttribute((const void*)k_eval<NW, SMALL>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_eval<NW, SMALL>), dim3(total), dim3(WAVE), lds, stream, a);
+    hipLaunchKernelGGL((k_eval<NW, SMALL>), dim3(total), dim3(WAVE), lds, stream, a, counters, list);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   const size_t lds = lds_layout(a.max_n, NW, true).total;
@@ -669,30 +679,54 @@ hipError_t launch_nw(const SweepArgs& a, hipStream_t stream) {
                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   const int grid = a.path == EVAL_PATH_GLOBAL ? min(total, GLOBAL_PASS_GRID) : GLOBAL_PASS_GRID;
-  if (grid > 0) {
-    hipLaunchKernelGGL((k_eval_global<NW, SMALL>), dim3(grid), dim3(WAVE), lds, stream, a,
-                       a.path == EVAL_PATH_GLOBAL ? 1 : 0, total);
-    e = hipGetLastError();
+  hipLaunchKernelGGL((k_eval_global<NW, SMALL>), dim3(grid), dim3(WAVE), lds, stream, a, counters, list,
+                     a.path == EVAL_PATH_GLOBAL ? 1 : 0, total);
+  return hipGetLastError();
+}
+
+template <bool SMALL>
+hipError_t launch_class(int cls, const SweepArgs& a, uint32_t* counters, uint32_t* list, hipStream_t stream) {
+  switch (cls) {
+    case 0: return launch_nw<1, SMALL>(a, counters, list, stream);
+    case 1: return launch_nw<2, SMALL>(a, counters, list, stream);
+    case 2: return launch_nw<4, SMALL>(a, counters, list, stream);
+    default: return launch_nw<8, SMALL>(a, counters, list, stream);
   }
-  return e;
 }
 
 }  // namespace
 
 size_t sweep_lds_need(int max_n, int max_e) {
-  const int nw = (max_n + 63) / 64;
   (void)max_e;
-  return lds_layout(max_n, nw <= 1 ? 1 : nw <= 2 ? 2 : nw <= 4 ? 4 : 8, false).total;
+  const int nw = 1 << class_of(max_n);
+  return lds_layout(max_n, nw, false).total;
 }
 
 hipError_t launch_sweep(const SweepArgs& a, hipStream_t stream) {
   if (a.D <= 0) return hipSuccess;
-  const bool small = a.small_loads != 0;
-  if (a.max_n <= 64) return small ? launch_nw<1, true>(a, stream) : launch_nw<1, false>(a, stream);
-  if (a.max_n <= 128) return small ? launch_nw<2, true>(a, stream) : launch_nw<2, false>(a, stream);
-  if (a.max_n <= 256) return small ? launch_nw<4, true>(a, stream) : launch_nw<4, false>(a, stream);
-  if (a.max_n <= 512) return small ? launch_nw<8, true>(a, stream) : launch_nw<8, false>(a, stream);
-  return hipErrorInvalidValue;
+  if (a.max_n > 512) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_eval_init, dim3((a.D + 255) / 256), dim3(256), 0, stream, a.best, a.D, a.ovf_count);
+  hipError_t e = hipGetLastError();
+  const int ntile = (a.K + WAVE - 1) / WAVE;
+  for (int c = 0; c < NUM_CLASSES && e == hipSuccess; c++) {
+    SweepArgs ac = a;
+    if (a.order) {
+      ac.dag_list = a.order + a.class_off[c];
+      ac.list_len = a.class_off[c + 1] - a.class_off[c];
+      ac.max_n = a.class_max_n[c];
+    } else {
+      // one launch over all DAGs, sized by the largest
+      if (c != class_of(a.max_n)) continue;
+      ac.dag_list = nullptr;
+      ac.list_len = a.D;
+    }
+    if (ac.list_len <= 0) continue;
+    uint32_t* counters = a.ovf_count + 2 * c;
+    uint32_t* list = a.ovf_list + (size_t)(a.order ? a.class_off[c] : 0) * ntile;
+    e = a.small_loads ? launch_class<true>(c, ac, counters, list, stream)
+                      : launch_class<false>(c, ac, counters, list, stream);
+  }
+  return e;
 }
 
 hipError_t launch_best_final(const unsigned long long* best, int32_t D, int32_t* idx, int64_t* bound,

@@ -214,8 +214,9 @@ def test_seeded_mode_matches_explicit_bytes(torch_dev):
     check_against_oracle(batch, wl.num_cus, K, alloc, got)
 
 
-@pytest.mark.parametrize("tuning", [{"eval_path": 1}, {"residual_slots": 1}, {"residual_slots": 2}],
-                         ids=["global-pass-only", "one-slot", "two-slots"])
+@pytest.mark.parametrize("tuning", [{"eval_path": 1}, {"residual_slots": 1}, {"residual_slots": 2},
+                                    {"size_classes": 0}, {"size_classes": 0, "residual_slots": 1}],
+                         ids=["global-pass-only", "one-slot", "two-slots", "one-launch", "one-launch-one-slot"])
 def test_second_pass_paths(torch_dev, tuning):
     # The global-memory pass alone, and the first pass with tiny residual
     # tables so that many tiles overflow and are handed over.
@@ -231,12 +232,54 @@ def test_second_pass_paths(torch_dev, tuning):
                          W.alloc_bytes(W.generate_workload(1, count=200), 8, 16, seed=2), got)
 
 
+def test_overflow_beyond_global_tables(torch_dev):
+    # One residual slot: far more than 256 tiles overflow, so the tiles left
+    # after the global tables are taken go through the second pass.
+    wl = W.WORKLOADS[2]
+    batch = W.generate_workload(2, count=3000, first=9000)
+    alloc = W.alloc_bytes(batch, wl.num_cus, wl.K, seed=8, first=9000)
+    say("overflow beyond the global tables: 3000 DAGs, one slot")
+    got = gpu_eval(torch_dev, batch, wl.num_cus, wl.K, alloc, tuning={"residual_slots": 1})
+    check_against_oracle(batch, wl.num_cus, wl.K, alloc, got)
+
+
+def mixed_size_batch():
+    """DAGs of all four size classes (<= 64, 128, 256, 512 nodes), interleaved."""
+    a = W.generate_workload(1, count=40)
+    b = W.generate_workload(2, count=40, first=300)
+    full = W.generate_workload(3, count=300, first=77)
+    mid = [d for d in range(full.num_dags) if 128 < full.dag(d)[0] <= 256][:12]
+    big = [d for d in range(full.num_dags) if 256 < full.dag(d)[0] <= 400 and len(full.dag(d)[1]) <= 4000][:3]
+    dags = []
+    for i in range(40):
+        dags.append(a.dag(i))
+        dags.append(b.dag(i))
+        if i < len(mid):
+            dags.append(full.dag(mid[i]))
+        if i < len(big):
+            dags.append(full.dag(big[i]))
+    return W.from_dags(dags)
+
+
+@pytest.mark.parametrize("classes", [1, 0])
+def test_mixed_size_classes(torch_dev, classes):
+    batch = mixed_size_batch()
+    sizes = np.diff(batch.node_off)
+    assert sizes.max() > 256 and (sizes <= 64).any() and ((sizes > 64) & (sizes <= 128)).any()
+    K, M = 70, 256
+    alloc = W.alloc_bytes(batch, M, K, seed=5)
+    say("mixed size classes:", batch.num_dags, "DAGs, size_classes", classes)
+    got = gpu_eval(torch_dev, batch, M, K, alloc, tuning={"size_classes": classes})
+    check_against_oracle(batch, M, K, alloc, got)
+
+
 def test_tuning_rejects_bad_keys(torch_dev):
     import paper_2602_20826_amd as db
 
     batch = W.generate_workload(1, count=2)
     b = db.create_batch(batch.node_off, batch.edge_off, batch.src, batch.dst, batch.wcet, batch.par, 8)
-    for key, val in [("residual_slots", 0), ("residual_slots", 13), ("eval_path", 2), ("nope", 1)]:
+    for key, val in [("residual_slots", 0), ("residual_slots", 13), ("eval_path", 2), ("size_classes", 2),
+                     ("nope", 1)]:
         with pytest.raises(db.DagboundError):
             db.set_tuning(b, key, val)
     b.close()
