@@ -151,7 +151,7 @@ struct dagbound_batch {
   unsigned long long* best = nullptr;  // [D] packed per-DAG minimum
   unsigned long long* err = nullptr;   // [2] first failing DAG, largest load
   uint32_t* gres = nullptr;            // residual tables of the global evaluation pass
-  bool small_loads = false;            // every load < 2^22
+  bool small_loads = false;            // every load < 2^20
   // DAG ids grouped by size class (the evaluation launches one kernel per class)
   int32_t* order = nullptr;
   std::vector<int32_t> order_host;
@@ -355,7 +355,7 @@ dagbound_status dagbound_create_batch(int32_t num_dags, const int64_t* node_off,
     return hip_fail(e, "preprocessing");
   }
   const unsigned long long err = errw[0];
-  b->small_loads = errw[1] < (1ull << 22);
+  b->small_loads = errw[1] < (1ull << 20);
   if (err != ~0ull) {
     const long long d = (long long)(err >> 8);
     const unsigned code = (unsigned)(err & 0xFF);

@@ -77,7 +77,7 @@ struct SweepArgs {
   const int32_t* cand_list;     // [D][K] candidate ids to evaluate, or nullptr (ids 0..K-1)
   int32_t res_slots;            // <= RES_SLOTS
   int32_t path;                 // EVAL_PATH_*
-  int32_t small_loads;          // every C_hat < 2^22
+  int32_t small_loads;          // every C_hat < 2^20
 };
 
 // Packing of the per-DAG minimum: bound < 2^42 (the summed load is < 2^40)

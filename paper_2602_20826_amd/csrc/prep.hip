@@ -17,28 +17,31 @@ namespace {
 
 constexpr int WAVE = 64;
 
-__device__ inline int wave_min_i32(int x) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) x = min(x, __shfl_xor(x, o));
+// Wave reductions and the inclusive scan through DPP: row shifts build the
+// prefix within each row of 16 lanes, two row broadcasts carry it across
+// rows; lane 63 ends with the total.  Lanes without a source take the
+// operation's identity.
+template <class Op>
+__device__ inline uint32_t wave_scan_dpp(uint32_t x, uint32_t id, Op op) {
+  x = op(x, (uint32_t)__builtin_amdgcn_update_dpp((int)id, (int)x, 0x111, 0xf, 0xf, false));  // row_shr:1
+  x = op(x, (uint32_t)__builtin_amdgcn_update_dpp((int)id, (int)x, 0x112, 0xf, 0xf, false));  // row_shr:2
+  x = op(x, (uint32_t)__builtin_amdgcn_update_dpp((int)id, (int)x, 0x114, 0xf, 0xf, false));  // row_shr:4
+  x = op(x, (uint32_t)__builtin_amdgcn_update_dpp((int)id, (int)x, 0x118, 0xf, 0xf, false));  // row_shr:8
+  x = op(x, (uint32_t)__builtin_amdgcn_update_dpp((int)id, (int)x, 0x142, 0xa, 0xf, false));  // row_bcast:15
+  x = op(x, (uint32_t)__builtin_amdgcn_update_dpp((int)id, (int)x, 0x143, 0xc, 0xf, false));  // row_bcast:31
   return x;
+}
+__device__ inline int wave_min_i32(int x) {
+  const uint32_t b = (uint32_t)x ^ 0x80000000u;  // order-preserving map to unsigned
+  const uint32_t r = wave_scan_dpp(b, 0xffffffffu, [](uint32_t p, uint32_t q) { return p < q ? p : q; });
+  return (int)((uint32_t)__builtin_amdgcn_readlane((int)r, 63) ^ 0x80000000u);
 }
 __device__ inline uint32_t wave_max_u32(uint32_t x) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) x = max(x, (uint32_t)__shfl_xor((int)x, o));
-  return x;
+  const uint32_t r = wave_scan_dpp(x, 0u, [](uint32_t p, uint32_t q) { return p > q ? p : q; });
+  return (uint32_t)__builtin_amdgcn_readlane((int)r, 63);
 }
-__device__ inline uint32_t wave_sum_u32(uint32_t x) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) x += (uint32_t)__shfl_xor((int)x, o);
-  return x;
-}
-__device__ inline uint32_t wave_incl_scan_u32(uint32_t x, int lane) {
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    uint32_t y = (uint32_t)__shfl_up((int)x, o);
-    if (lane >= o) x += y;
-  }
-  return x;
+__device__ inline uint32_t wave_incl_scan_u32(uint32_t x) {
+  return wave_scan_dpp(x, 0u, [](uint32_t p, uint32_t q) { return p + q; });
 }
 __device__ inline uint64_t lanes_below(int lane) { return lane ? (~0ull >> (64 - lane)) : 0ull; }
 
@@ -50,7 +53,7 @@ __host__ __device__ constexpr size_t prep_lds_bytes(int NW) {
          + (size_t)NW * 64 * 4 * 6      // wcet, par, indeg, outdeg/cursor, block, parent
          + 8 * 4                        // misc scalars
          + (size_t)NW * 64 * 2 * 3      // sig, perm, theta
-         + (size_t)NW * 64 * 2;         // state, removed bytes
+         + (size_t)NW * 64;             // closure state bytes
 }
 
 template <int NW>
@@ -74,7 +77,6 @@ __global__ __launch_bounds__(64) void k_prep(Tables t, PrepInputs in, int32_t M,
   uint16_t* s_perm = s_sig + NMAX;                   // local id of sigma rank
   uint16_t* s_theta = s_perm + NMAX;                 // join nodes in Theta order
   uint8_t* s_state = (uint8_t*)(s_theta + NMAX);     // closure state: 0 open, 1 done, 2 new
-  uint8_t* s_removed = s_state + NMAX;               // grouped already (by local id)
 
   const int d = blockIdx.x;
   const int lane = threadIdx.x;
@@ -87,7 +89,7 @@ __global__ __launch_bounds__(64) void k_prep(Tables t, PrepInputs in, int32_t M,
   for (int i = lane; i < N * NW; i += WAVE) { s_pred[i] = 0; s_anc[i] = 0; }
   for (int w = lane; w < NW; w += WAVE) s_done[w] = 0;
   for (int v = lane; v < N; v += WAVE) {
-    s_indeg[v] = 0; s_cursor[v] = 0; s_state[v] = 0; s_removed[v] = 0;
+    s_indeg[v] = 0; s_cursor[v] = 0; s_state[v] = 0;
   }
   __syncthreads();
 
@@ -152,22 +154,22 @@ __global__ __launch_bounds__(64) void k_prep(Tables t, PrepInputs in, int32_t M,
       s_state[v] = 2;
     }
     __syncthreads();
-    uint32_t fresh = 0;
+    bool fresh = false;
     for (int v = lane; v < N; v += WAVE)
       if (s_state[v] == 2) {
         s_state[v] = 1;
         atomicOr((unsigned long long*)&s_done[v >> 6], 1ull << (v & 63));
-        fresh++;
+        fresh = true;
       }
-    fresh = wave_sum_u32(fresh);
+    const bool any_fresh = __ballot(fresh) != 0;
     __syncthreads();
-    if (!fresh) break;
+    if (!any_fresh) break;
   }
   {
-    uint32_t closed = 0;
-    for (int w = lane; w < NW; w += WAVE) closed += __popcll(s_done[w]);
-    closed = wave_sum_u32(closed);
-    if ((int)closed != N) {  // some node never became ready: a cycle
+    int closed = 0;
+#pragma unroll
+    for (int w = 0; w < NW; w++) closed += __popcll(s_done[w]);
+    if (closed != N) {  // some node never became ready: a cycle
       if (lane == 0) atomicMin(err, ((unsigned long long)d << 8) | PREP_E_CYCLE);
       return;
     }
@@ -241,21 +243,36 @@ __global__ __launch_bounds__(64) void k_prep(Tables t, PrepInputs in, int32_t M,
   // Algorithm 1, balanced groups.  Blocks are taken in order; within the
   // current block the heads of the local complete paths are the ungrouped
   // nodes whose in-block parent is grouped (or absent).  Lane l holds sigma
-  // ranks l, l+64, ...; heads are picked in sigma order (Top_M, Rule 1) and
-  // Rule 2 keeps only the first node of largest m^max = min(p, C_hat) when
-  // that reaches M.
+  // ranks l, l+64, ... with their block, parent (as a sigma rank) and
+  // m^max = min(p, C_hat) in registers; G is the set of grouped sigma ranks.
+  // Heads are picked in sigma order (Top_M, Rule 1) and Rule 2 keeps only
+  // the first node of largest m^max when that reaches M.
+  int blk[NW], psig[NW];
+  uint32_t mmax[NW];
   bool grouped[NW];
+  uint64_t G[NW];
 #pragma unroll
-  for (int k = 0; k < NW; k++) grouped[k] = false;
+  for (int k = 0; k < NW; k++) {
+    const int s = k * 64 + lane;
+    grouped[k] = s >= N;
+    blk[k] = INT_MAX;
+    psig[k] = -1;
+    mmax[k] = 0;
+    if (s < N) {
+      const int v = s_perm[s];
+      blk[k] = s_block[v];
+      psig[k] = s_parent[v] < 0 ? -1 : (int)s_sig[s_parent[v]];
+      mmax[k] = min(s_par[v], s_wcet[v]);
+    }
+    G[k] = 0;
+  }
   uint16_t* gl = t.gl + n0;
   int gpos = 0, ng = 0;
   for (;;) {
     int bmin = INT_MAX;
 #pragma unroll
-    for (int k = 0; k < NW; k++) {
-      const int s = k * 64 + lane;
-      if (s < N && !grouped[k]) bmin = min(bmin, s_block[s_perm[s]]);
-    }
+    for (int k = 0; k < NW; k++)
+      if (!grouped[k]) bmin = min(bmin, blk[k]);
     bmin = wave_min_i32(bmin);
     if (bmin == INT_MAX) break;
     bool head[NW];
@@ -263,15 +280,14 @@ __global__ __launch_bounds__(64) void k_prep(Tables t, PrepInputs in, int32_t M,
     int nh = 0;
 #pragma unroll
     for (int k = 0; k < NW; k++) {
-      const int s = k * 64 + lane;
-      head[k] = false;
-      if (s < N && !grouped[k]) {
-        const int v = s_perm[s];
-        if (s_block[v] == bmin) {
-          const int p = s_parent[v];
-          head[k] = (p < 0) || s_removed[p];
-        }
+      bool pg = psig[k] < 0;
+      if (!pg) {
+        uint64_t gw = 0;
+#pragma unroll
+        for (int w = 0; w < NW; w++) gw |= (psig[k] >> 6) == w ? G[w] : 0ull;
+        pg = (gw >> (psig[k] & 63)) & 1;
       }
+      head[k] = !grouped[k] && blk[k] == bmin && pg;
       hb[k] = __ballot(head[k]);
       nh += __popcll(hb[k]);
     }
@@ -289,21 +305,13 @@ __global__ __launch_bounds__(64) void k_prep(Tables t, PrepInputs in, int32_t M,
       uint32_t mx = 0;
 #pragma unroll
       for (int k = 0; k < NW; k++)
-        if (sel[k]) {
-          const int v = s_perm[k * 64 + lane];
-          mx = max(mx, min(s_par[v], s_wcet[v]));
-        }
+        if (sel[k]) mx = max(mx, mmax[k]);
       mx = wave_max_u32(mx);
       if (mx >= (uint32_t)M) {
         bool found = false;
 #pragma unroll
         for (int k = 0; k < NW; k++) {
-          bool hit = false;
-          if (sel[k]) {
-            const int v = s_perm[k * 64 + lane];
-            hit = min(s_par[v], s_wcet[v]) == mx;
-          }
-          uint64_t hbits = __ballot(hit);
+          const uint64_t hbits = __ballot(sel[k] && mmax[k] == mx);
           uint64_t keep = 0;
           if (!found && hbits) { keep = hbits & (~hbits + 1); found = true; }
           sb[k] = keep;
@@ -322,13 +330,12 @@ __global__ __launch_bounds__(64) void k_prep(Tables t, PrepInputs in, int32_t M,
         const int pos = gpos + base + __popcll(sb[k] & lanes_below(lane));
         gl[pos] = (uint16_t)(s | (pos == gpos + cnt - 1 ? 0x8000 : 0));
         grouped[k] = true;
-        s_removed[s_perm[s]] = 1;
       }
       base += __popcll(sb[k]);
+      G[k] |= sb[k];
     }
     gpos += cnt;
     ng++;
-    __syncthreads();
   }
   if (lane == 0) t.ngroups[d] = ng;
 
@@ -351,9 +358,9 @@ __global__ __launch_bounds__(64) void k_prep(Tables t, PrepInputs in, int32_t M,
   for (int b = 0; b < N; b += WAVE) {
     const int s = b + lane;
     const uint32_t x = s < N ? s_cursor[s_perm[s]] : 0u;
-    const uint32_t incl = wave_incl_scan_u32(x, lane);
+    const uint32_t incl = wave_incl_scan_u32(x);
     if (s < N) soff[s] = carry + incl - x;
-    carry += (uint32_t)__shfl((int)incl, 63);
+    carry += (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
   }
   if (lane == 0) soff[N] = carry;
   __syncthreads();

@@ -114,14 +114,12 @@ __device__ inline int bit_count(const uint64_t (&b)[NW]) {
 
 __device__ inline uint32_t uni(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
 
-// ceil(a / b) for a < 2^22, b >= 1: a single-precision estimate is within one
-// of the quotient; one integer step corrects it.
+// ceil(a / b) for 1 <= a < 2^20 and 1 <= b < 2^16, exactly: with a - 1 =
+// q b + r, (a - 1/2) / b lies in [q + 1/(2b), q + 1 - 1/(2b)], and the
+// single-precision product (a - 1/2) * rcp(b) (reciprocal within one ulp) is
+// off by less than a * 2^-22.4 / b < 1/(5b), so it truncates to q.
 __device__ inline uint32_t ceil_div_small(uint32_t a, uint32_t b) {
-  uint32_t q = (uint32_t)((float)a * __builtin_amdgcn_rcpf((float)b));
-  int32_t r = (int32_t)(a - q * b);
-  if (r < 0) { q--; r += (int32_t)b; }
-  else if (r >= (int32_t)b) { q++; r -= (int32_t)b; }
-  return q + (r != 0);
+  return (uint32_t)(((float)a - 0.5f) * __builtin_amdgcn_rcpf((float)b)) + 1u;
 }
 template <bool SMALL>
 __device__ inline uint32_t ceil_div(uint32_t a, uint32_t b) {
@@ -214,7 +212,7 @@ __device__ inline uint64_t readlane64(uint64_t x, int l) {
          (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, l);
 }
 
-// Eq. 5's half-up share for loads below 2^22: W < 2^31 then, and a float
+// Eq. 5's half-up share for loads below 2^20: W < 2^29 then, and a float
 // estimate from the slot's reciprocal of 2W is within one of the quotient;
 // one exact integer step corrects it.
 __device__ inline uint32_t round_share_small(uint32_t cv, uint32_t M, uint32_t W, float rw2) {

@@ -243,6 +243,28 @@ def test_overflow_beyond_global_tables(torch_dev):
     check_against_oracle(batch, wl.num_cus, wl.K, alloc, got)
 
 
+@pytest.mark.parametrize("top", [(1 << 20) - 1, 1 << 20, 1 << 28])
+def test_load_ranges(torch_dev, top):
+    # Loads drawn up to `top`: below 2^20 the kernels divide in single
+    # precision (exact there), from 2^20 on in integer arithmetic.
+    rng = np.random.default_rng(top & 0xFFFF)
+    base = W.generate_workload(2, count=300, first=4000)
+    dags = []
+    for d in range(base.num_dags):
+        n, src, dst, _, par = base.dag(d)
+        w = rng.integers(top // 2, top + 1, n)
+        small = rng.random(n) < 0.3
+        w[small] = rng.integers(1, 1000, int(small.sum()))
+        dags.append((n, src, dst, w, par))
+    batch = W.from_dags(dags)
+    assert int(batch.wcet.max()) <= top and int(batch.wcet.max()) > top // 2
+    M, K = 256, 64
+    alloc = W.alloc_bytes(batch, M, K, seed=4)
+    say("load ranges up to", top)
+    got = gpu_eval(torch_dev, batch, M, K, alloc)
+    check_against_oracle(batch, M, K, alloc, got)
+
+
 def mixed_size_batch():
     """DAGs of all four size classes (<= 64, 128, 256, 512 nodes), interleaved."""
     a = W.generate_workload(1, count=40)
