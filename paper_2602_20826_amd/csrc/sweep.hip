@@ -64,6 +64,18 @@ __device__ inline int bit_first(const uint64_t (&b)[NW]) {
 // Index of the lowest set bit (or -1), cleared in place.
 template <int NW>
 __device__ inline int pop_first(uint64_t (&b)[NW]) {
+  if constexpr (NW == 1) {
+    const uint64_t w = b[0];
+    b[0] = w & (w - 1);
+    return w ? (int)__builtin_ctzll(w) : -1;
+  } else if constexpr (NW == 2) {
+    const bool lo = b[0] != 0;
+    const uint64_t w = lo ? b[0] : b[1];
+    const uint64_t w2 = w & (w - 1);
+    if (lo) b[0] = w2;
+    else b[1] = w2;
+    return w ? (lo ? 0 : 64) + (int)__builtin_ctzll(w) : -1;
+  }
   int r = -1;
   bool done = false;
 #pragma unroll
@@ -358,6 +370,9 @@ __device__ bool eval_tile(const SweepArgs& a, int item, unsigned char* smem, uin
   // segmented and unfinished, remaining load in the residual table.
   uint64_t bound = 0, cp = 0;
   bool ovf = false;
+  uint64_t FO[NW];  // nodes finished in some lane (wave-uniform)
+#pragma unroll
+  for (int w = 0; w < NW; w++) FO[w] = 0;
   int k = 0;
   while (k < N) {
     // The group's extent from the members' end marks, 64 records at a time;
@@ -451,17 +466,24 @@ __device__ bool eval_tile(const SweepArgs& a, int item, unsigned char* smem, uin
       const int cur = cn;
       const uint2 ndc = nd;
       const uint32_t rcc = rc, mwc = mw;
+      // remaining load of cur: read before the next node's data, so that
+      // waiting for it leaves those reads in flight
+      bool sg;
+      uint32_t cc = ndc.x;
+      if (BIG) {
+        sg = bit_get<NW>(seg, cur);
+        if (sg) cc = res[cur * WAVE + lane];
+      } else {
+        const uint32_t nib = (mwc >> (4 * (cur & 7))) & 15u;
+        sg = nib != 0;
+        const uint32_t rv = res[(sg ? nib - 1u : 0u) * WAVE + lane];
+        cc = sg ? rv : cc;
+      }
       cn = pop_first<NW>(Q);
       ci = max(cn, 0);
       nd = s_node[ci];
       rc = s_r[ci * WAVE + lane];
       if (!BIG) mw = s_map[(ci >> 3) * WAVE + lane];
-      uint32_t nib = 0;
-      bool sg;
-      if (BIG) sg = bit_get<NW>(seg, cur);
-      else { nib = (mwc >> (4 * (cur & 7))) & 15u; sg = nib != 0; }
-      uint32_t cc = ndc.x;
-      if (sg) cc = BIG ? res[cur * WAVE + lane] : res[(nib - 1u) * WAVE + lane];
       const uint32_t mx = min(ndc.y, cc);
       const uint32_t mc = min(rcc ? min(rcc, mx) : mx, S);
       const uint64_t cap = (uint64_t)maxC * mc;
@@ -523,28 +545,43 @@ __device__ bool eval_tile(const SweepArgs& a, int item, unsigned char* smem, uin
     }
     // Releases: a successor of a node finished now (in some lane) is
     // released in the lanes where all its predecessors have finished.
-    // Successor rows are OR-ed lane-parallel (lane x takes node w * 64 + x).
+    // Lane-parallel over nodes (lane x takes node w * 64 + x): successor rows
+    // of the nodes finished now are OR-ed into the candidates, and nodes with
+    // a predecessor unfinished in every lane (outside FO, the nodes finished
+    // in some lane) are dropped from them.
     uint64_t cand[NW];
     {
-      uint64_t acc[NW];
+      uint64_t acc[NW], blocked[NW];
 #pragma unroll
-      for (int k2 = 0; k2 < NW; k2++) acc[k2] = 0;
+      for (int k2 = 0; k2 < NW; k2++) {
+        acc[k2] = 0;
+        FO[k2] |= Fu[k2];
+      }
 #pragma unroll
       for (int w = 0; w < NW; w++) {
-        if ((Fu[w] >> lane) & 1) {
-          uint64_t sr[NW];
-          if constexpr (REG) {
+        uint64_t sr[NW], pr[NW];
+        if constexpr (REG) {
 #pragma unroll
-            for (int k2 = 0; k2 < NW; k2++) sr[k2] = SB[w][k2];
-          } else {
+          for (int k2 = 0; k2 < NW; k2++) { sr[k2] = SB[w][k2]; pr[k2] = PB[w][k2]; }
+        } else {
+#pragma unroll
+          for (int k2 = 0; k2 < NW; k2++) { sr[k2] = 0; pr[k2] = 0; }
+          if (w * WAVE + lane < N) {
             load_row<NW>(sr, s_sb + (w * WAVE + lane) * NW);
+            load_row<NW>(pr, s_pb + (w * WAVE + lane) * NW);
           }
+        }
+        uint64_t open = 0;
+#pragma unroll
+        for (int k2 = 0; k2 < NW; k2++) open |= pr[k2] & ~FO[k2];
+        blocked[w] = __ballot(open != 0);
+        if ((Fu[w] >> lane) & 1) {
 #pragma unroll
           for (int k2 = 0; k2 < NW; k2++) acc[k2] |= sr[k2];
         }
       }
 #pragma unroll
-      for (int k2 = 0; k2 < NW; k2++) cand[k2] = wave_or64(acc[k2]);
+      for (int k2 = 0; k2 < NW; k2++) cand[k2] = wave_or64(acc[k2]) & ~blocked[k2];
     }
     // A node found ready is added to rel even where it has finished already;
     // rel is cut back to the unfinished nodes after the walk.
