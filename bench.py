@@ -182,12 +182,46 @@ def cpu_baseline(batch, M, K, alloc, gpu_bounds, max_seconds: float = 30.0):
     }
 
 
+def search_block(torch, db, W, n_train: int, n_test: int) -> dict:
+    """Best-bound gap to exhaustive search on held-out learned-proposal DAGs
+    (4,096 seeded candidates each): the surrogate's top-16 plus the paper's
+    rule, the paper's rule alone, and 16 plain random candidates, with the
+    DAGs/s of surrogate-guided and exhaustive exact search.  The model is
+    trained here, deterministically, on separate DAGs of the same workload
+    (256 candidates each, labelled by the exact kernel)."""
+    from paper_2602_20826_amd import proposal as P
+
+    wl = W.WORKLOADS[4]
+    M = wl.num_cus
+    train = W.generate_workload(4, count=n_train, first=10**6)
+    test = W.generate_workload(4, count=n_test, first=0)
+    t0 = time.perf_counter()
+    shards = P.label_shards(torch, train, M, 256, seed=11, per_shard=2000)
+    model = db.Model(3)
+    epochs = 20
+    hist = P.train(model, shards, epochs, lr=2e-3, lr_end=2e-4)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    res = P.compare_search(torch, model, test, M, 4096, seed=5, top_k=16)
+    model.close()
+    for sh in shards:
+        sh.batch.close()
+    res["workload"] = (f"learned-proposal: {n_test} held-out DAGs x 4096 seeded candidates; model trained on "
+                       f"{n_train} other DAGs x 256 labelled candidates, {epochs} epochs")
+    res["train_seconds"] = train_s
+    res["final_train_loss"] = hist[-1]
+    return res
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-search", action="store_true", help="skip the learned-proposal comparison")
+    ap.add_argument("--search-train", type=int, default=5000, help="training DAGs (x 256 labelled candidates)")
+    ap.add_argument("--search-test", type=int, default=5000, help="held-out DAGs (x 4096 seeded candidates)")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="one copy of known size plus one evaluation launch, for counter passes")
     ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -288,6 +322,9 @@ def main() -> int:
         },
         "best_gap": None,
     }
+    if not args.no_search:
+        print("[bench] learned proposal: label, train, compare searches", file=sys.stderr, flush=True)
+        out["best_gap"] = search_block(torch, db, W, args.search_train, args.search_test)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         torch.cuda.synchronize()

@@ -195,6 +195,10 @@ dagbound_status dagbound_get_division(dagbound_batch* batch, int32_t d, int64_t*
  *   "size_classes"    1 (default): one launch per DAG size class (up to 64,
  *                     128, 256, 512 nodes); 0: one launch over all DAGs,
  *                     sized for the largest.
+ *   "class_streams"   1 (default): the class launches run concurrently on
+ *                     side streams of the device (forked from and joined back
+ *                     to the caller's stream with events); 0: in turn on the
+ *                     caller's stream.
  * Errors: E_ARG (unknown key or value).
  */
 dagbound_status dagbound_set_tuning(dagbound_batch* batch, const char* key, int64_t value);

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <climits>
 #include <cstdarg>
 #include <cstdio>
@@ -131,10 +132,31 @@ struct Carve {
   }
 };
 
-size_t table_bytes(int64_t D, int64_t tn, int64_t te, int64_t max_n) {
+size_t table_bytes(int64_t D, int64_t tn, int64_t te, size_t gres_words) {
   return 18 * 256 + (size_t)(D + 1) * 8 * 2 + (size_t)tn * 8 + (size_t)D * 8 + 16 +
          (size_t)tn * 4 + (size_t)(tn + D) * 4 + (size_t)D * 4 + (size_t)tn * 2 * 4 +
-         (size_t)te * 2 + (size_t)GLOBAL_PASS_GRID * (size_t)max_n * 64 * 4 + (size_t)D * 4;
+         (size_t)te * 2 + gres_words * 4 + (size_t)D * 4;
+}
+
+// Side streams of each device for the size-class launches (created once,
+// default priority, kept until the process ends).
+std::mutex g_stream_mu;
+std::vector<std::array<hipStream_t, NUM_CLASSES>> g_side;
+
+hipError_t side_streams(int device, hipStream_t out[NUM_CLASSES]) {
+  std::lock_guard<std::mutex> lk(g_stream_mu);
+  if ((int)g_side.size() <= device) g_side.resize(device + 1, {nullptr, nullptr, nullptr, nullptr});
+  for (int c = 0; c < NUM_CLASSES; c++) {
+    if (!g_side[device][c]) {
+      hipError_t e = hipStreamCreateWithFlags(&g_side[device][c], hipStreamNonBlocking);
+      if (e != hipSuccess) {
+        g_side[device][c] = nullptr;
+        return e;
+      }
+    }
+    out[c] = g_side[device][c];
+  }
+  return hipSuccess;
 }
 
 }  // namespace
@@ -158,6 +180,9 @@ struct dagbound_batch {
   int32_t class_off[NUM_CLASSES + 1] = {0, 0, 0, 0, 0};
   int32_t class_max_n[NUM_CLASSES] = {0, 0, 0, 0};
   bool size_classes = true;
+  bool class_streams = true;           // class launches on side streams
+  size_t gres_off[NUM_CLASSES] = {0, 0, 0, 0};
+  hipEvent_t ev[NUM_CLASSES + 1] = {nullptr, nullptr, nullptr, nullptr, nullptr};  // fork, joins
   // per-allocation-set scratch: tiles handed to the global pass
   void* ovf_block = nullptr;
   size_t ovf_block_size = 0;
@@ -189,6 +214,8 @@ void batch_free(dagbound_batch* b) {
   dev_release(b->block, b->block_size, b->device);
   dev_release(b->alloc_owned, b->alloc_owned_size, b->device);
   dev_release(b->ovf_block, b->ovf_block_size, b->device);
+  for (hipEvent_t ev : b->ev)
+    if (ev) (void)hipEventDestroy(ev);
   delete b;
 }
 
@@ -205,6 +232,7 @@ SweepArgs sweep_args(const dagbound_batch* b) {
   a.order = b->size_classes ? b->order : nullptr;
   for (int c = 0; c <= NUM_CLASSES; c++) a.class_off[c] = b->class_off[c];
   for (int c = 0; c < NUM_CLASSES; c++) a.class_max_n[c] = b->class_max_n[c];
+  for (int c = 0; c < NUM_CLASSES; c++) a.gres_off[c] = b->gres_off[c];
   a.ovf_list = b->ovf_list;
   a.ovf_count = b->ovf_count;
   a.gres = b->gres;
@@ -212,6 +240,22 @@ SweepArgs sweep_args(const dagbound_batch* b) {
   a.path = b->eval_path;
   a.small_loads = b->small_loads ? 1 : 0;
   return a;
+}
+
+// One evaluation launch of a batch: the size classes on the device's side
+// streams when there is more than one class to run.
+hipError_t run_sweep(dagbound_batch* b, const SweepArgs& a, hipStream_t st) {
+  int classes = 0;
+  for (int c = 0; c < NUM_CLASSES; c++) classes += b->class_off[c + 1] > b->class_off[c];
+  if (!a.order || !b->class_streams || classes < 2) return launch_sweep(a, st, nullptr);
+  SweepStreams ss;
+  hipError_t e = side_streams(b->device, ss.side);
+  for (int i = 0; i <= NUM_CLASSES && e == hipSuccess; i++)
+    if (!b->ev[i]) e = hipEventCreateWithFlags(&b->ev[i], hipEventDisableTiming);
+  if (e != hipSuccess) return e;
+  ss.fork = b->ev[0];
+  for (int c = 0; c < NUM_CLASSES; c++) ss.join[c] = b->ev[c + 1];
+  return launch_sweep(a, st, &ss);
 }
 
 }  // namespace
@@ -281,7 +325,25 @@ dagbound_status dagbound_create_batch(int32_t num_dags, const int64_t* node_off,
   b->max_e = (int32_t)std::min<int64_t>(max_e, INT32_MAX);
   b->node_off = no;
   b->edge_off = eo;
-  b->block_size = table_bytes(D, tn, te, max_n);
+  {
+    std::vector<int32_t> cnt(NUM_CLASSES + 1, 0);
+    for (int64_t d = 0; d < D; d++) {
+      const int cls = class_of((int)(no[d + 1] - no[d]));
+      cnt[cls + 1]++;
+      b->class_max_n[cls] = std::max<int32_t>(b->class_max_n[cls], (int32_t)(no[d + 1] - no[d]));
+    }
+    for (int c = 0; c < NUM_CLASSES; c++) cnt[c + 1] += cnt[c];
+    for (int c = 0; c <= NUM_CLASSES; c++) b->class_off[c] = cnt[c];
+    b->order_host.resize((size_t)D);
+    for (int64_t d = 0; d < D; d++) b->order_host[(size_t)cnt[class_of((int)(no[d + 1] - no[d]))]++] = (int32_t)d;
+    size_t off = (size_t)GLOBAL_PASS_GRID * (size_t)max_n * 64;  // the one-launch pool comes first
+    for (int c = 0; c < NUM_CLASSES; c++) {
+      b->gres_off[c] = off;
+      if (b->class_off[c + 1] > b->class_off[c]) off += (size_t)GLOBAL_PASS_GRID * (size_t)b->class_max_n[c] * 64;
+    }
+  }
+  const size_t gres_words = sweep_gres_words(b->class_max_n, b->class_off, (int32_t)max_n);
+  b->block_size = table_bytes(D, tn, te, gres_words);
   hipError_t e = dev_alloc(&b->block, &b->block_size, device);
   if (e != hipSuccess) {
     delete b;
@@ -295,7 +357,7 @@ dagbound_status dagbound_create_batch(int32_t num_dags, const int64_t* node_off,
   b->t.wanc = cv.take<int64_t>(tn);
   b->best = cv.take<unsigned long long>(D);
   b->err = cv.take<unsigned long long>(2);
-  b->gres = cv.take<uint32_t>((size_t)GLOBAL_PASS_GRID * (size_t)max_n * 64);
+  b->gres = cv.take<uint32_t>(gres_words);
   b->t.wc = cv.take<uint32_t>(tn);
   b->t.soff = cv.take<uint32_t>(tn + D);
   b->t.ngroups = cv.take<int32_t>(D);
@@ -305,18 +367,6 @@ dagbound_status dagbound_create_batch(int32_t num_dags, const int64_t* node_off,
   b->t.inv = cv.take<uint16_t>(tn);
   b->t.succ = cv.take<uint16_t>(te);
   b->order = cv.take<int32_t>(D);
-  {
-    std::vector<int32_t> cnt(NUM_CLASSES + 1, 0);
-    for (int64_t d = 0; d < D; d++) {
-      const int cls = class_of((int)(no[d + 1] - no[d]));
-      cnt[cls + 1]++;
-      b->class_max_n[cls] = std::max<int32_t>(b->class_max_n[cls], (int32_t)(no[d + 1] - no[d]));
-    }
-    for (int c = 0; c < NUM_CLASSES; c++) cnt[c + 1] += cnt[c];
-    for (int c = 0; c <= NUM_CLASSES; c++) b->class_off[c] = cnt[c];
-    b->order_host.resize((size_t)D);
-    for (int64_t d = 0; d < D; d++) b->order_host[(size_t)cnt[class_of((int)(no[d + 1] - no[d]))]++] = (int32_t)d;
-  }
 
   // Inputs: device pointers are read in place; host arrays go through a
   // staging block that is released when this call returns.
@@ -468,7 +518,7 @@ dagbound_status dagbound_eval_bounds(dagbound_batch* b, int64_t* bounds, int64_t
     a.intf = intf_term;
   }
   a.best = b->best;
-  e = launch_sweep(a, st);
+  e = run_sweep(b, a, st);
   if (e == hipSuccess && ptr_kind == DAGBOUND_PTR_HOST && n > 0) {
     e = hipMemcpyAsync(bounds, a.bounds, n * 8, hipMemcpyDeviceToHost, st);
     if (e == hipSuccess && cp_term) e = hipMemcpyAsync(cp_term, a.cp, n * 8, hipMemcpyDeviceToHost, st);
@@ -512,7 +562,7 @@ dagbound_status dagbound_best_allocation(dagbound_batch* b, uint32_t search, int
   if (b->best_gen != b->alloc_gen) {
     SweepArgs a = sweep_args(b);
     a.best = b->best;
-    e = launch_sweep(a, st);
+    e = run_sweep(b, a, st);
     if (e != hipSuccess) {
       b->best_gen = ~0ull;
       return hip_fail(e, "evaluating bounds");
@@ -588,6 +638,9 @@ dagbound_status dagbound_set_tuning(dagbound_batch* b, const char* key, int64_t 
   } else if (!strcmp(key, "size_classes")) {
     if (value != 0 && value != 1) return fail(DAGBOUND_E_ARG, "size_classes must be 0 or 1");
     b->size_classes = value != 0;
+  } else if (!strcmp(key, "class_streams")) {
+    if (value != 0 && value != 1) return fail(DAGBOUND_E_ARG, "class_streams must be 0 or 1");
+    b->class_streams = value != 0;
   } else {
     return fail(DAGBOUND_E_ARG, "unknown tuning key '%s'", key);
   }
@@ -900,7 +953,7 @@ dagbound_status surrogate_best(dagbound_batch* b, dagbound_model* m, int32_t top
     a.K = kk;
     a.cand_list = cand;
     a.best = b->best;
-    e = launch_sweep(a, st);
+    e = run_sweep(b, a, st);
     b->best_gen = ~0ull;  // the per-DAG minimum now holds list positions
   }
   if (e == hipSuccess) {

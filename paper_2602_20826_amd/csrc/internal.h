@@ -72,7 +72,9 @@ struct SweepArgs {
   unsigned long long* best;     // [D] packed (bound << 22 | c), atomicMin
   uint32_t* ovf_list;           // [D * ceil(K/64)] tiles handed to the global pass
   uint32_t* ovf_count;          // [2 * NUM_CLASSES]: per class, tiles listed and global tables taken
-  uint32_t* gres;               // [GLOBAL_PASS_GRID][max_n][64] residual tables
+  uint32_t* gres;               // residual tables: class c owns GLOBAL_PASS_GRID tables of
+                                // class_max_n[c] * 64 words from gres + gres_off[c]
+  size_t gres_off[NUM_CLASSES]; // host: word offset of each class's tables
   int32_t max_n, max_e;
   const int32_t* cand_list;     // [D][K] candidate ids to evaluate, or nullptr (ids 0..K-1)
   int32_t res_slots;            // <= RES_SLOTS
@@ -88,8 +90,22 @@ constexpr int BEST_SHIFT = 22;
 size_t sweep_lds_need(int max_n, int max_e);
 constexpr size_t LDS_LIMIT = 160 * 1024;
 
+// Side streams for the size classes: each class launch runs on its own
+// stream, forked from and joined back to the caller's stream by events, so
+// that one class's tail overlaps the others' work.
+struct SweepStreams {
+  hipStream_t side[NUM_CLASSES];
+  hipEvent_t fork;
+  hipEvent_t join[NUM_CLASSES];
+};
+
+// Words of residual tables a batch needs (all classes with DAGs).
+size_t sweep_gres_words(const int32_t class_max_n[NUM_CLASSES], const int32_t class_off[NUM_CLASSES + 1],
+                        int32_t max_n);
+
 // Evaluates every (DAG, candidate) pair; also resets `best` and fills it.
-hipError_t launch_sweep(const SweepArgs& a, hipStream_t stream);
+// With `ss`, the class launches run concurrently on its side streams.
+hipError_t launch_sweep(const SweepArgs& a, hipStream_t stream, const SweepStreams* ss = nullptr);
 // With `list` ([D][K] candidate ids), the packed index is a list position and
 // is translated to the candidate id.
 hipError_t launch_best_final(const unsigned long long* best, int32_t D, int32_t* idx, int64_t* bound,

@@ -176,17 +176,17 @@ __device__ inline uint64_t wave_or64(uint64_t x) {
 // Predecessor and successor bitsets of the DAG's nodes live in registers
 // (lane x holds the rows of nodes x, 64 + x, ...) while they are small, and
 // in LDS above that.
-template <int NW> struct RowsInRegs { static constexpr bool value = NW <= 2; };
+template <int NW> struct RowsInRegs { static constexpr bool value = NW <= 4; };
 
 // LDS layout of one wavefront (bytes), for the batch's largest DAG.
 struct Lds {
   size_t mem, node, ppv, inv, pb, sb, res, r, map, total;
 };
 __host__ __device__ inline Lds lds_layout(int maxn, int nw, bool big) {
-  const bool regs = nw <= 2;
+  const bool regs = nw <= 4;
   Lds l;
   size_t o = 0;
-  l.mem = o;  o += (size_t)maxn * 16;           // members in group order
+  l.mem = o;  o += (size_t)maxn * 8;            // members in group order
   l.node = o; o += (size_t)maxn * 8;            // node info by sigma rank
   l.ppv = o;  o += ((size_t)maxn * 2 + 15) & ~(size_t)15;  // min(p, M) by local id
   l.inv = o;  o += ((size_t)maxn * 2 + 15) & ~(size_t)15;  // sigma rank by local id
@@ -256,7 +256,7 @@ __device__ bool eval_tile(const SweepArgs& a, int item, unsigned char* smem, uin
   const int64_t e0 = a.t.edge_off[d];
   const uint32_t M = (uint32_t)a.M;
   const Lds L = lds_layout(a.max_n, NW, BIG);
-  uint4* s_mem = (uint4*)(smem + L.mem);       // {C_hat, pp, s | last << 31, 0}
+  uint2* s_mem = (uint2*)(smem + L.mem);       // {C_hat, pp | s << 16 | last << 31}
   uint2* s_node = (uint2*)(smem + L.node);     // {C_hat, pp} by sigma rank
   uint16_t* s_ppv = (uint16_t*)(smem + L.ppv); // [local id]
   uint16_t* s_inv = (uint16_t*)(smem + L.inv); // [local id]
@@ -290,7 +290,7 @@ __device__ bool eval_tile(const SweepArgs& a, int item, unsigned char* smem, uin
     const uint32_t g = a.t.gl[n0 + k];
     const int s = g & 0x7FFF;
     const uint2 nd = s_node[s];
-    s_mem[k] = make_uint4(nd.x, nd.y, (uint32_t)s | ((g & 0x8000u) << 16), 0u);
+    s_mem[k] = make_uint2(nd.x, nd.y | ((uint32_t)s << 16) | ((g & 0x8000u) << 16));
   }
   __syncthreads();
   // released: the sources; finished: none.  With REG, lane x keeps the rows
@@ -377,17 +377,17 @@ __device__ bool eval_tile(const SweepArgs& a, int item, unsigned char* smem, uin
   while (k < N) {
     // The group's extent from the members' end marks, 64 records at a time;
     // the first 64 records stay in registers (lane i holds member k + i).
-    uint4 rec0 = make_uint4(0u, 0u, 0u, 0u);
+    uint2 rec0 = make_uint2(0u, 0u);
     if (k + lane < N) rec0 = s_mem[k + lane];
     int kend;
     {
-      const uint64_t ends = __ballot(k + lane < N && (rec0.z >> 31));
+      const uint64_t ends = __ballot(k + lane < N && (rec0.y >> 31));
       if (ends) {
         kend = k + 1 + __builtin_ctzll(ends);
       } else {
         kend = k + WAVE;
         while (kend < N) {
-          const bool e = kend + lane < N && (s_mem[kend + lane].z >> 31);
+          const bool e = kend + lane < N && (s_mem[kend + lane].y >> 31);
           const uint64_t m = __ballot(e);
           if (m) { kend += 1 + __builtin_ctzll(m); break; }
           kend += WAVE;
@@ -402,11 +402,11 @@ __device__ bool eval_tile(const SweepArgs& a, int item, unsigned char* smem, uin
     for (int w = 0; w < NW; w++) gm[w] = 0;
     uint64_t W = 0;
     for (int base = k; base < kend; base += WAVE) {
-      uint4 rec = rec0;
+      uint2 rec = rec0;
       if (base != k && base + lane < kend) rec = s_mem[base + lane];
       const int cnt = min(WAVE, kend - base);
       for (int i = 0; i < cnt; i++) {
-        const int s = __builtin_amdgcn_readlane((int)rec.z, i) & 0x7FFF;
+        const int s = ((uint32_t)__builtin_amdgcn_readlane((int)rec.y, i) >> 16) & 0x7FFF;
         bit_set<NW>(gm, s);
         if (bit_get<NW>(rel, s)) {
           uint32_t cv = (uint32_t)__builtin_amdgcn_readlane((int)rec.x, i);
@@ -423,18 +423,18 @@ __device__ bool eval_tile(const SweepArgs& a, int item, unsigned char* smem, uin
     uint32_t maxC = 0, sm = 0;
     uint64_t A = 0;
     for (int base = k; base < kend; base += WAVE) {
-      uint4 rec = rec0;
+      uint2 rec = rec0;
       if (base != k && base + lane < kend) rec = s_mem[base + lane];
       const int cnt = min(WAVE, kend - base);
-      uint32_t rnext = s_r[(__builtin_amdgcn_readlane((int)rec.z, 0) & 0x7FFF) * WAVE + lane];
+      uint32_t rnext = s_r[(((uint32_t)__builtin_amdgcn_readlane((int)rec.y, 0) >> 16) & 0x7FFF) * WAVE + lane];
       for (int i = 0; i < cnt; i++) {
-        const int s = __builtin_amdgcn_readlane((int)rec.z, i) & 0x7FFF;
+        const int s = ((uint32_t)__builtin_amdgcn_readlane((int)rec.y, i) >> 16) & 0x7FFF;
         const uint32_t rv = rnext;
-        if (i + 1 < cnt) rnext = s_r[(__builtin_amdgcn_readlane((int)rec.z, i + 1) & 0x7FFF) * WAVE + lane];
+        if (i + 1 < cnt) rnext = s_r[(((uint32_t)__builtin_amdgcn_readlane((int)rec.y, i + 1) >> 16) & 0x7FFF) * WAVE + lane];
         if (!bit_get<NW>(rel, s)) continue;
         uint32_t cv = (uint32_t)__builtin_amdgcn_readlane((int)rec.x, i);
         if (bit_get<NW>(seg, s)) cv = *res_at(s);
-        const uint32_t mx = min((uint32_t)__builtin_amdgcn_readlane((int)rec.y, i), cv);
+        const uint32_t mx = min((uint32_t)__builtin_amdgcn_readlane((int)rec.y, i) & 0xFFFFu, cv);
         uint32_t m;
         if (rv) m = min(rv, mx);
         else m = max(1u, min(mx, SMALL ? round_share_small(cv, M, (uint32_t)W, rw2) : round_share(cv, M, W)));
@@ -737,29 +737,59 @@ size_t sweep_lds_need(int max_n, int max_e) {
   return lds_layout(max_n, nw, false).total;
 }
 
-hipError_t launch_sweep(const SweepArgs& a, hipStream_t stream) {
+size_t sweep_gres_words(const int32_t class_max_n[NUM_CLASSES], const int32_t class_off[NUM_CLASSES + 1],
+                        int32_t max_n) {
+  size_t w = (size_t)GLOBAL_PASS_GRID * (size_t)max_n * WAVE;  // one pool for the one-launch mode
+  for (int c = 0; c < NUM_CLASSES; c++)
+    if (class_off[c + 1] > class_off[c]) w += (size_t)GLOBAL_PASS_GRID * (size_t)class_max_n[c] * WAVE;
+  return w;
+}
+
+hipError_t launch_sweep(const SweepArgs& a, hipStream_t stream, const SweepStreams* ss) {
   if (a.D <= 0) return hipSuccess;
   if (a.max_n > 512) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_eval_init, dim3((a.D + 255) / 256), dim3(256), 0, stream, a.best, a.D, a.ovf_count);
   hipError_t e = hipGetLastError();
   const int ntile = (a.K + WAVE - 1) / WAVE;
-  for (int c = 0; c < NUM_CLASSES && e == hipSuccess; c++) {
+  int launched[NUM_CLASSES] = {0, 0, 0, 0};
+  const bool fork = ss != nullptr && a.order != nullptr;
+  if (e == hipSuccess && fork) e = hipEventRecord(ss->fork, stream);
+  // largest DAGs first: their tiles are the longest
+  for (int c = NUM_CLASSES - 1; c >= 0 && e == hipSuccess; c--) {
     SweepArgs ac = a;
     if (a.order) {
       ac.dag_list = a.order + a.class_off[c];
       ac.list_len = a.class_off[c + 1] - a.class_off[c];
       ac.max_n = a.class_max_n[c];
+      ac.gres = a.gres + a.gres_off[c];
     } else {
-      // one launch over all DAGs, sized by the largest
+      // one launch over all DAGs, sized by the largest, with the shared pool
       if (c != class_of(a.max_n)) continue;
       ac.dag_list = nullptr;
       ac.list_len = a.D;
     }
     if (ac.list_len <= 0) continue;
+    hipStream_t sc = stream;
+    if (fork) {
+      sc = ss->side[c];
+      e = hipStreamWaitEvent(sc, ss->fork, 0);
+      if (e != hipSuccess) break;
+    }
     uint32_t* counters = a.ovf_count + 2 * c;
     uint32_t* list = a.ovf_list + (size_t)(a.order ? a.class_off[c] : 0) * ntile;
-    e = a.small_loads ? launch_class<true>(c, ac, counters, list, stream)
-                      : launch_class<false>(c, ac, counters, list, stream);
+    e = a.small_loads ? launch_class<true>(c, ac, counters, list, sc)
+                      : launch_class<false>(c, ac, counters, list, sc);
+    if (e == hipSuccess && fork) {
+      e = hipEventRecord(ss->join[c], sc);
+      launched[c] = 1;
+    }
+  }
+  if (fork) {  // join every side stream that was forked, even after an error
+    for (int c = 0; c < NUM_CLASSES; c++) {
+      if (!launched[c]) continue;
+      const hipError_t w = hipStreamWaitEvent(stream, ss->join[c], 0);
+      if (e == hipSuccess) e = w;
+    }
   }
   return e;
 }

@@ -283,15 +283,15 @@ def mixed_size_batch():
     return W.from_dags(dags)
 
 
-@pytest.mark.parametrize("classes", [1, 0])
-def test_mixed_size_classes(torch_dev, classes):
+@pytest.mark.parametrize("classes,streams", [(1, 1), (1, 0), (0, 1)])
+def test_mixed_size_classes(torch_dev, classes, streams):
     batch = mixed_size_batch()
     sizes = np.diff(batch.node_off)
     assert sizes.max() > 256 and (sizes <= 64).any() and ((sizes > 64) & (sizes <= 128)).any()
     K, M = 70, 256
     alloc = W.alloc_bytes(batch, M, K, seed=5)
-    say("mixed size classes:", batch.num_dags, "DAGs, size_classes", classes)
-    got = gpu_eval(torch_dev, batch, M, K, alloc, tuning={"size_classes": classes})
+    say("mixed size classes:", batch.num_dags, "DAGs, size_classes", classes, "class_streams", streams)
+    got = gpu_eval(torch_dev, batch, M, K, alloc, tuning={"size_classes": classes, "class_streams": streams})
     check_against_oracle(batch, M, K, alloc, got)
 
 
@@ -300,7 +300,7 @@ def test_tuning_rejects_bad_keys(torch_dev):
 
     batch = W.generate_workload(1, count=2)
     b = db.create_batch(batch.node_off, batch.edge_off, batch.src, batch.dst, batch.wcet, batch.par, 8)
-    for key, val in [("residual_slots", 0), ("residual_slots", 13), ("eval_path", 2), ("size_classes", 2),
+    for key, val in [("residual_slots", 0), ("residual_slots", 13), ("eval_path", 2), ("size_classes", 2), ("class_streams", 3),
                      ("nope", 1)]:
         with pytest.raises(db.DagboundError):
             db.set_tuning(b, key, val)
@@ -468,4 +468,46 @@ def test_state_errors(torch_dev):
     with pytest.raises(db.DagboundError) as e:
         db.set_allocations(b, 0, B.ALLOC_EXPLICIT, np.zeros(0, np.uint8))
     assert e.value.code == B.E_ARG
+    b.close()
+
+
+def test_eval_bounds_in_a_captured_graph(torch_dev):
+    # eval_bounds on device pointers records only kernels and events, so a
+    # caller can capture it (here with the class launches on side streams)
+    # and replay it; every replay must equal the eager result.
+    import paper_2602_20826_amd as db
+
+    torch, dev = torch_dev
+    batch = mixed_size_batch()
+    M, K = 256, 64
+    alloc = W.alloc_bytes(batch, M, K, seed=12)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    b = db.create_batch(t(batch.node_off), t(batch.edge_off), t(batch.src), t(batch.dst), t(batch.wcet),
+                        t(batch.par), M, stream=torch.cuda.current_stream(dev))
+    a_dev = t(alloc)
+    db.set_allocations(b, K, db.ALLOC_EXPLICIT, a_dev)
+    D = batch.num_dags
+    eager = torch.empty(D * K, dtype=torch.int64, device=dev)
+    db.eval_bounds(b, eager, stream=torch.cuda.current_stream(dev))
+    torch.cuda.synchronize()
+    out = torch.zeros(D * K, dtype=torch.int64, device=dev)
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream(dev))
+    say("capturing eval_bounds")
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            db.eval_bounds(b, out, stream=s)
+    torch.cuda.synchronize()
+    ref = eager.cpu().numpy()
+    for rep in range(3):
+        out.fill_(-1)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        say("replay", rep)
+        assert np.array_equal(out.cpu().numpy(), ref), rep
+    want, _, _ = oracle.bounds_batch(batch, M, K, alloc, threads=8)
+    assert np.array_equal(ref.reshape(D, K), want)
+    del g
     b.close()
