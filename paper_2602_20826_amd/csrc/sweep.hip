@@ -61,6 +61,20 @@ __device__ inline int bit_first(const uint64_t (&b)[NW]) {
   for (int k = NW - 1; k >= 0; k--) r = b[k] ? k * 64 + __builtin_ctzll(b[k]) : r;
   return r;
 }
+// The same with a wave-uniform index: the word is addressed directly (GPR
+// indexing) instead of through a select over every word.
+template <int NW>
+__device__ inline bool bit_get_u(const uint64_t (&b)[NW], int v) {
+  const int u = __builtin_amdgcn_readfirstlane(v);
+  if constexpr (NW == 1) return (b[0] >> (u & 63)) & 1;
+  return (b[u >> 6] >> (u & 63)) & 1;
+}
+template <int NW>
+__device__ inline void bit_set_u(uint64_t (&b)[NW], int v) {
+  const int u = __builtin_amdgcn_readfirstlane(v);
+  if constexpr (NW == 1) b[0] |= 1ull << (u & 63);
+  else b[u >> 6] |= 1ull << (u & 63);
+}
 // Index of the lowest set bit (or -1), cleared in place.
 template <int NW>
 __device__ inline int pop_first(uint64_t (&b)[NW]) {
@@ -89,6 +103,28 @@ __device__ inline int pop_first(uint64_t (&b)[NW]) {
   }
   return r;
 }
+// Pops the set bits of a bitset in increasing order through a cursor word,
+// so a pop touches one word; the bitset itself is updated by rest().
+template <int NW>
+struct Popper {
+  uint64_t cw;
+  int kw;
+  __device__ void init(const uint64_t (&b)[NW]) { kw = 0; cw = b[0]; }
+  __device__ int pop(const uint64_t (&b)[NW]) {
+    while (cw == 0) {
+      if (++kw >= NW) { kw = NW; return -1; }
+      cw = word_of<NW>(b, kw * 64);
+    }
+    const int r = kw * 64 + (int)__builtin_ctzll(cw);
+    cw &= cw - 1;
+    return r;
+  }
+  // leaves in b the bits not popped yet
+  __device__ void rest(uint64_t (&b)[NW]) const {
+#pragma unroll
+    for (int k = 0; k < NW; k++) b[k] = k < kw ? 0ull : (k == kw ? cw : b[k]);
+  }
+};
 // Index of the highest set bit, or -1.
 template <int NW>
 __device__ inline int bit_last(const uint64_t (&b)[NW]) {
@@ -407,10 +443,10 @@ __device__ bool eval_tile(const SweepArgs& a, int item, unsigned char* smem, uin
       const int cnt = min(WAVE, kend - base);
       for (int i = 0; i < cnt; i++) {
         const int s = ((uint32_t)__builtin_amdgcn_readlane((int)rec.y, i) >> 16) & 0x7FFF;
-        bit_set<NW>(gm, s);
-        if (bit_get<NW>(rel, s)) {
+        bit_set_u<NW>(gm, s);
+        if (bit_get_u<NW>(rel, s)) {
           uint32_t cv = (uint32_t)__builtin_amdgcn_readlane((int)rec.x, i);
-          if (bit_get<NW>(seg, s)) cv = *res_at(s);
+          if (bit_get_u<NW>(seg, s)) cv = *res_at(s);
           W += cv;
         }
       }
@@ -431,9 +467,9 @@ __device__ bool eval_tile(const SweepArgs& a, int item, unsigned char* smem, uin
         const int s = ((uint32_t)__builtin_amdgcn_readlane((int)rec.y, i) >> 16) & 0x7FFF;
         const uint32_t rv = rnext;
         if (i + 1 < cnt) rnext = s_r[(((uint32_t)__builtin_amdgcn_readlane((int)rec.y, i + 1) >> 16) & 0x7FFF) * WAVE + lane];
-        if (!bit_get<NW>(rel, s)) continue;
+        if (!bit_get_u<NW>(rel, s)) continue;
         uint32_t cv = (uint32_t)__builtin_amdgcn_readlane((int)rec.x, i);
-        if (bit_get<NW>(seg, s)) cv = *res_at(s);
+        if (bit_get_u<NW>(seg, s)) cv = *res_at(s);
         const uint32_t mx = min((uint32_t)__builtin_amdgcn_readlane((int)rec.y, i) & 0xFFFFu, cv);
         uint32_t m;
         if (rv) m = min(rv, mx);
@@ -456,7 +492,10 @@ __device__ bool eval_tile(const SweepArgs& a, int item, unsigned char* smem, uin
     int cseg = -1;
     bool csg = false;
     uint32_t cleft = 0;
-    int cn = S ? pop_first<NW>(Q) : -1;
+    constexpr bool CURSOR = NW >= 4;
+    Popper<NW> pq;
+    pq.init(Q);
+    int cn = S ? (CURSOR ? pq.pop(Q) : pop_first<NW>(Q)) : -1;
     int ci = max(cn, 0);
     uint2 nd = s_node[ci];
     uint32_t rc = s_r[ci * WAVE + lane];
@@ -479,7 +518,7 @@ __device__ bool eval_tile(const SweepArgs& a, int item, unsigned char* smem, uin
         const uint32_t rv = res[(sg ? nib - 1u : 0u) * WAVE + lane];
         cc = sg ? rv : cc;
       }
-      cn = pop_first<NW>(Q);
+      cn = CURSOR ? pq.pop(Q) : pop_first<NW>(Q);
       ci = max(cn, 0);
       nd = s_node[ci];
       rc = s_r[ci * WAVE + lane];
@@ -496,6 +535,7 @@ __device__ bool eval_tile(const SweepArgs& a, int item, unsigned char* smem, uin
       S -= fits ? mc : 0u;
       go = fits && S != 0 && cn >= 0;
     }
+    if (CURSOR) pq.rest(Q);
     if (cn >= 0) bit_set<NW>(Q, cn);  // read ahead, not launched
 #pragma unroll
     for (int w = 0; w < NW; w++) Lw[w] &= ~Q[w];
@@ -534,7 +574,7 @@ __device__ bool eval_tile(const SweepArgs& a, int item, unsigned char* smem, uin
       seg[w] &= ~Dn[w];
       rel[w] &= ~Dn[w];
       fin[w] |= Dn[w];
-      Fu[w] = gm[w] | wave_or64(Lw[w]);  // finished now in some lane
+      Fu[w] = gm[w] | (__ballot(Lw[w] != 0) ? wave_or64(Lw[w]) : 0ull);  // finished now in some lane
     }
     if (!BIG) {  // free the residual slots of finished segmented nodes
       while (bits_any<NW>(gone)) {
@@ -557,31 +597,48 @@ __device__ bool eval_tile(const SweepArgs& a, int item, unsigned char* smem, uin
         acc[k2] = 0;
         FO[k2] |= Fu[k2];
       }
+      if constexpr (REG) {
 #pragma unroll
-      for (int w = 0; w < NW; w++) {
-        uint64_t sr[NW], pr[NW];
-        if constexpr (REG) {
+        for (int w = 0; w < NW; w++) {
+          uint64_t open = 0;
 #pragma unroll
-          for (int k2 = 0; k2 < NW; k2++) { sr[k2] = SB[w][k2]; pr[k2] = PB[w][k2]; }
-        } else {
+          for (int k2 = 0; k2 < NW; k2++) open |= PB[w][k2] & ~FO[k2];
+          blocked[w] = __ballot(open != 0);
+          if ((Fu[w] >> lane) & 1) {
 #pragma unroll
-          for (int k2 = 0; k2 < NW; k2++) { sr[k2] = 0; pr[k2] = 0; }
-          if (w * WAVE + lane < N) {
-            load_row<NW>(sr, s_sb + (w * WAVE + lane) * NW);
-            load_row<NW>(pr, s_pb + (w * WAVE + lane) * NW);
+            for (int k2 = 0; k2 < NW; k2++) acc[k2] |= SB[w][k2];
           }
         }
-        uint64_t open = 0;
 #pragma unroll
-        for (int k2 = 0; k2 < NW; k2++) open |= pr[k2] & ~FO[k2];
-        blocked[w] = __ballot(open != 0);
-        if ((Fu[w] >> lane) & 1) {
+        for (int k2 = 0; k2 < NW; k2++) cand[k2] = (__ballot(acc[k2] != 0) ? wave_or64(acc[k2]) : 0ull) & ~blocked[k2];
+      } else {
+        // rows from LDS: successor rows of the finished nodes, then
+        // predecessor rows of the candidates only
 #pragma unroll
-          for (int k2 = 0; k2 < NW; k2++) acc[k2] |= sr[k2];
+        for (int w = 0; w < NW; w++) {
+          if ((Fu[w] >> lane) & 1) {
+            uint64_t sr[NW];
+            load_row<NW>(sr, s_sb + (w * WAVE + lane) * NW);
+#pragma unroll
+            for (int k2 = 0; k2 < NW; k2++) acc[k2] |= sr[k2];
+          }
         }
-      }
 #pragma unroll
-      for (int k2 = 0; k2 < NW; k2++) cand[k2] = wave_or64(acc[k2]) & ~blocked[k2];
+        for (int k2 = 0; k2 < NW; k2++) cand[k2] = __ballot(acc[k2] != 0) ? wave_or64(acc[k2]) : 0ull;
+#pragma unroll
+        for (int w = 0; w < NW; w++) {
+          uint64_t open = 0;
+          if ((cand[w] >> lane) & 1) {
+            uint64_t pr[NW];
+            load_row<NW>(pr, s_pb + (w * WAVE + lane) * NW);
+#pragma unroll
+            for (int k2 = 0; k2 < NW; k2++) open |= pr[k2] & ~FO[k2];
+          }
+          blocked[w] = __ballot(open != 0);
+        }
+#pragma unroll
+        for (int k2 = 0; k2 < NW; k2++) cand[k2] &= ~blocked[k2];
+      }
     }
     // A node found ready is added to rel even where it has finished already;
     // rel is cut back to the unfinished nodes after the walk.
@@ -614,7 +671,7 @@ __device__ bool eval_tile(const SweepArgs& a, int item, unsigned char* smem, uin
             uint64_t open = 0;
 #pragma unroll
             for (int k2 = 0; k2 < NW; k2++) open |= pr[t][k2] & ~fin[k2];
-            if (open == 0) bit_set<NW>(rel, u[t]);
+            if (open == 0) bit_set_u<NW>(rel, u[t]);
           }
         }
       }
