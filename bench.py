@@ -41,13 +41,13 @@ def sweep_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def algorithmic_bytes(batch, K: int) -> int:
+def algorithmic_bytes(batch, K: int, explicit: bool = True) -> int:
     """Bytes the method must move for one evaluation launch: each candidate's
-    bytes (N_d per candidate), its 8-byte bound, and the DAG's own data once
-    (17 bytes per node, 4 per edge)."""
-    n = np.diff(batch.node_off)
-    e = np.diff(batch.edge_off)
-    return int(np.sum(K * n + 8 * K + 17 * n + 4 * e))
+    bytes (N_d per candidate, explicit mode only), its 8-byte bound, and the
+    DAG's own data once (17 bytes per node, 4 per edge)."""
+    n = np.diff(batch.node_off).astype(np.int64)
+    e = np.diff(batch.edge_off).astype(np.int64)
+    return int(np.sum((K * n if explicit else 0) + 8 * K + 17 * n + 4 * e))
 
 
 def measured_traffic(workload_key: str):
@@ -153,24 +153,29 @@ def write_traffic(fetch_csv: str, write_csv: str) -> int:
     return 0
 
 
-def cpu_baseline(batch, M, K, alloc, gpu_bounds, max_seconds: float = 30.0):
+def cpu_baseline(batch, M, K, seed, gpu_bounds, max_seconds: float = 30.0):
     """Time the CPU oracle (as it stands) on the host cores over the same
-    workload, DAG by DAG across a thread pool, and count mismatches."""
+    workload (the first DAGs of the batch with the same candidate bytes), DAG
+    by DAG across a thread pool, and count mismatches."""
     import oracle
+    import workloads as W
 
     threads = max(1, min(16, os.cpu_count() or 1))
     D = batch.num_dags
     # size the sample from a short probe so the leg stays near its budget
-    probe = list(range(min(D, 2000)))
+    probe_n = min(D, 500)
+    probe = batch.subset(range(probe_n))
+    pa = W.alloc_bytes(probe, M, K, seed=seed)
     t0 = time.perf_counter()
-    oracle.bounds_batch(batch, M, K, alloc, dags=probe, threads=threads)
-    per_dag = (time.perf_counter() - t0) / len(probe)
-    count = int(min(D, max(len(probe), max_seconds * 0.8 / max(per_dag, 1e-9))))
-    idx = np.arange(count)
+    oracle.bounds_batch(probe, M, K, pa, threads=threads)
+    per_dag = (time.perf_counter() - t0) / probe_n
+    count = int(min(D, max(probe_n, max_seconds * 0.8 / max(per_dag, 1e-9))))
+    sample = batch if count == D else batch.subset(range(count))
+    alloc = W.alloc_bytes(sample, M, K, seed=seed)
     t0 = time.perf_counter()
-    wb, _, _ = oracle.bounds_batch(batch, M, K, alloc, dags=idx, threads=threads)
+    wb, _, _ = oracle.bounds_batch(sample, M, K, alloc, threads=threads)
     dt = time.perf_counter() - t0
-    mism = int(np.count_nonzero(wb != gpu_bounds[:count]))
+    mism = int(np.count_nonzero(wb != gpu_bounds[:count].cpu().numpy()))
     return {
         "value": count * K / dt,
         "unit": "evals/s",
@@ -218,6 +223,12 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", choices=["batched-layered", "persistent-mixed"], default="batched-layered",
+                    help="batched-layered (default; 100,000 DAGs x 64 explicit candidates) or persistent-mixed "
+                         "(DAGs of 50-500 nodes x 256 candidates)")
+    ap.add_argument("--dags", type=int, default=None, help="number of DAGs (default: the workload's)")
+    ap.add_argument("--seeded", action="store_true", help="seeded candidates drawn on the GPU instead of "
+                    "explicit bytes (same values)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-search", action="store_true", help="skip the learned-proposal comparison")
     ap.add_argument("--search-train", type=int, default=5000, help="training DAGs (x 256 labelled candidates)")
@@ -243,17 +254,22 @@ def main() -> int:
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     db.load_library()
-    wl = W.WORKLOADS[2]
+    wk = 2 if args.workload == "batched-layered" else 3
+    wl = W.WORKLOADS[wk]
     M, K = wl.num_cus, wl.K
     print(f"[bench] generating {wl.name}", file=sys.stderr, flush=True)
-    batch = W.generate_workload(2)
-    alloc = W.alloc_bytes(batch, M, K, seed=wl.seed)
+    batch = W.generate_workload(wk, count=args.dags)
     D = batch.num_dags
     dev = torch.device("cuda:0")
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
     inputs = [t(batch.node_off), t(batch.edge_off), t(batch.src), t(batch.dst), t(batch.wcet),
               t(batch.par)]
-    a_dev = t(alloc)
+    if args.seeded:
+        alloc, a_dev = None, None
+    else:
+        alloc = W.alloc_bytes(batch, M, K, seed=wl.seed)
+        a_dev = t(alloc)
+        del alloc
     bounds = torch.empty(D * K, dtype=torch.int64, device=dev)
     bidx = torch.empty(D, dtype=torch.int32, device=dev)
     bbound = torch.empty(D, dtype=torch.int64, device=dev)
@@ -262,7 +278,10 @@ def main() -> int:
 
     def step(record: bool):
         b = db.create_batch(*inputs, M, stream=stream)
-        db.set_allocations(b, K, db.ALLOC_EXPLICIT, a_dev)
+        if args.seeded:
+            db.set_allocations(b, K, db.ALLOC_SEEDED, None, wl.seed)
+        else:
+            db.set_allocations(b, K, db.ALLOC_EXPLICIT, a_dev)
         if record:
             e0 = torch.cuda.Event(enable_timing=True)
             e1 = torch.cuda.Event(enable_timing=True)
@@ -287,9 +306,16 @@ def main() -> int:
     sweep_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
     evals = D * K
     value = evals * args.steps / elapsed
-    alg = algorithmic_bytes(batch, K)
+    alg = algorithmic_bytes(batch, K, explicit=not args.seeded)
     achieved = alg / (sweep_ms * 1e-3) / 1e9
-    key = f"batched-layered/{D}x{K}"
+    key = f"{args.workload}/{D}x{K}" + ("/seeded" if args.seeded else "")
+    if args.workload == "batched-layered":
+        desc = (f"batched-layered: {D} DAGs, 20-100 internal nodes (+source/sink), layered width 1-16 p=0.3, "
+                f"WCET 1-1000, parallelism 1-32, M=256, {K} {'seeded' if args.seeded else 'explicit'} candidates")
+    else:
+        desc = (f"persistent-mixed: {D} DAGs, log-uniform 50-500 internal nodes (+source/sink), half ER p=0.05, "
+                f"half layered width 1-32 p=0.3, WCET log-uniform 1-1e5, parallelism 1-64, M=256, "
+                f"{K} {'seeded' if args.seeded else 'explicit'} candidates")
     out = {
         "metric": "exact DAG-bound evals/sec + best-bound gap vs exhaustive, surrogate vs plain",
         "value": value,
@@ -304,8 +330,7 @@ def main() -> int:
         "dtype": "int64",
         "data": "synthetic (seeded generator)",
         "config": {
-            "workload": "batched-layered: 100000 DAGs, 20-100 internal nodes (+source/sink), layered "
-                        "width 1-16 p=0.3, WCET 1-1000, parallelism 1-32, M=256, 64 explicit candidates",
+            "workload": desc,
             "num_dags": D, "candidates": K, "num_cus": M,
             "total_nodes": int(batch.node_off[-1]), "total_edges": int(batch.edge_off[-1]),
         },
@@ -328,7 +353,7 @@ def main() -> int:
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         torch.cuda.synchronize()
-        out["cpu_baseline"] = cpu_baseline(batch, M, K, alloc, bounds.cpu().numpy().reshape(D, K))
+        out["cpu_baseline"] = cpu_baseline(batch, M, K, wl.seed, bounds.view(D, K))
     print(json.dumps(out), flush=True)
     return 0
 

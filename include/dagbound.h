@@ -199,6 +199,14 @@ dagbound_status dagbound_get_division(dagbound_batch* batch, int32_t d, int64_t*
  *                     side streams of the device (forked from and joined back
  *                     to the caller's stream with events); 0: in turn on the
  *                     caller's stream.
+ *   "persistent"      0 (default): one workgroup per 64-candidate tile;
+ *                     1: as many workgroups as fit on the device, each taking
+ *                     tiles from a work counter.
+ *   "autotune"        1: the next evaluation (eval_bounds, or the sweep of an
+ *                     exhaustive best_allocation) runs each combination of
+ *                     "persistent" and "class_streams" once, timed with
+ *                     events on its stream (so that call synchronizes and must
+ *                     not be captured in a graph), and keeps the fastest.
  * Errors: E_ARG (unknown key or value).
  */
 dagbound_status dagbound_set_tuning(dagbound_batch* batch, const char* key, int64_t value);

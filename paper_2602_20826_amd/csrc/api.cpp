@@ -181,6 +181,9 @@ struct dagbound_batch {
   int32_t class_max_n[NUM_CLASSES] = {0, 0, 0, 0};
   bool size_classes = true;
   bool class_streams = true;           // class launches on side streams
+  bool persistent = false;             // first pass as a persistent kernel
+  bool autotune_pending = false;       // time the launch plans on the next evaluation
+  float plan_ms[4] = {0, 0, 0, 0};     // last autotune: (persistent, class_streams) = (p, s) at 2p + s
   size_t gres_off[NUM_CLASSES] = {0, 0, 0, 0};
   hipEvent_t ev[NUM_CLASSES + 1] = {nullptr, nullptr, nullptr, nullptr, nullptr};  // fork, joins
   // per-allocation-set scratch: tiles handed to the global pass
@@ -239,12 +242,49 @@ SweepArgs sweep_args(const dagbound_batch* b) {
   a.res_slots = b->res_slots;
   a.path = b->eval_path;
   a.small_loads = b->small_loads ? 1 : 0;
+  a.persistent = b->persistent ? 1 : 0;
   return a;
+}
+
+hipError_t run_sweep_plan(dagbound_batch* b, const SweepArgs& a, hipStream_t st);
+
+// One evaluation launch of a batch.  After set_tuning("autotune", 1) the
+// next call runs every launch plan (persistent first pass or not, class
+// launches concurrent or not) once, timed with events on `st`, and keeps the
+// fastest; the results of every plan are identical.
+hipError_t run_sweep(dagbound_batch* b, const SweepArgs& a, hipStream_t st) {
+  if (!b->autotune_pending) return run_sweep_plan(b, a, st);
+  b->autotune_pending = false;
+  hipEvent_t t0 = nullptr, t1 = nullptr;
+  hipError_t e = hipEventCreate(&t0);
+  if (e == hipSuccess) e = hipEventCreate(&t1);
+  float best = -1.f;
+  int best_plan = (b->persistent ? 2 : 0) + (b->class_streams ? 1 : 0);
+  for (int plan = 0; plan < 4 && e == hipSuccess; plan++) {
+    b->persistent = plan >= 2;
+    b->class_streams = plan & 1;
+    SweepArgs ap = a;
+    ap.persistent = b->persistent ? 1 : 0;
+    e = hipEventRecord(t0, st);
+    if (e == hipSuccess) e = run_sweep_plan(b, ap, st);
+    if (e == hipSuccess) e = hipEventRecord(t1, st);
+    if (e == hipSuccess) e = hipEventSynchronize(t1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
+    if (e != hipSuccess) break;
+    b->plan_ms[plan] = ms;
+    if (best < 0.f || ms < best) { best = ms; best_plan = plan; }
+  }
+  b->persistent = best_plan >= 2;
+  b->class_streams = best_plan & 1;
+  if (t0) (void)hipEventDestroy(t0);
+  if (t1) (void)hipEventDestroy(t1);
+  return e;
 }
 
 // One evaluation launch of a batch: the size classes on the device's side
 // streams when there is more than one class to run.
-hipError_t run_sweep(dagbound_batch* b, const SweepArgs& a, hipStream_t st) {
+hipError_t run_sweep_plan(dagbound_batch* b, const SweepArgs& a, hipStream_t st) {
   int classes = 0;
   for (int c = 0; c < NUM_CLASSES; c++) classes += b->class_off[c + 1] > b->class_off[c];
   if (!a.order || !b->class_streams || classes < 2) return launch_sweep(a, st, nullptr);
@@ -467,7 +507,7 @@ dagbound_status dagbound_set_allocations(dagbound_batch* b, int32_t K, uint32_t 
     b->seed = seed;
   }
   const size_t tiles = (size_t)b->D * (size_t)((K + 63) / 64);
-  const size_t need = 512 + 2 * NUM_CLASSES * 4 + tiles * 4;
+  const size_t need = 512 + COUNTERS_PER_CLASS * NUM_CLASSES * 4 + tiles * 4;
   if (b->ovf_block_size < need) {
     dev_release(b->ovf_block, b->ovf_block_size, b->device);
     b->ovf_block = nullptr;
@@ -481,7 +521,7 @@ dagbound_status dagbound_set_allocations(dagbound_batch* b, int32_t K, uint32_t 
     }
   }
   Carve oc(b->ovf_block);
-  b->ovf_count = oc.take<uint32_t>(2 * NUM_CLASSES);
+  b->ovf_count = oc.take<uint32_t>(COUNTERS_PER_CLASS * NUM_CLASSES);
   b->ovf_list = oc.take<uint32_t>(tiles);
   b->K = K;
   b->mode = mode;
@@ -641,6 +681,12 @@ dagbound_status dagbound_set_tuning(dagbound_batch* b, const char* key, int64_t 
   } else if (!strcmp(key, "class_streams")) {
     if (value != 0 && value != 1) return fail(DAGBOUND_E_ARG, "class_streams must be 0 or 1");
     b->class_streams = value != 0;
+  } else if (!strcmp(key, "persistent")) {
+    if (value != 0 && value != 1) return fail(DAGBOUND_E_ARG, "persistent must be 0 or 1");
+    b->persistent = value != 0;
+  } else if (!strcmp(key, "autotune")) {
+    if (value != 0 && value != 1) return fail(DAGBOUND_E_ARG, "autotune must be 0 or 1");
+    b->autotune_pending = value != 0;
   } else {
     return fail(DAGBOUND_E_ARG, "unknown tuning key '%s'", key);
   }

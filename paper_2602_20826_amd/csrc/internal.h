@@ -54,6 +54,7 @@ enum : int32_t { EVAL_PATH_AUTO = 0, EVAL_PATH_GLOBAL = 1 };
 // launch per class, so that a small DAG never pays for a large one's
 // bitsets and LDS.
 constexpr int NUM_CLASSES = 4;
+constexpr int COUNTERS_PER_CLASS = 3;
 __host__ __device__ constexpr int class_of(int n) { return n <= 64 ? 0 : n <= 128 ? 1 : n <= 256 ? 2 : 3; }
 
 struct SweepArgs {
@@ -71,7 +72,8 @@ struct SweepArgs {
   int64_t* intf;                // [D*K] or nullptr
   unsigned long long* best;     // [D] packed (bound << 22 | c), atomicMin
   uint32_t* ovf_list;           // [D * ceil(K/64)] tiles handed to the global pass
-  uint32_t* ovf_count;          // [2 * NUM_CLASSES]: per class, tiles listed and global tables taken
+  uint32_t* ovf_count;          // [COUNTERS_PER_CLASS * NUM_CLASSES]: per class, tiles listed,
+                                // global tables taken, tiles taken by the persistent pass
   uint32_t* gres;               // residual tables: class c owns GLOBAL_PASS_GRID tables of
                                 // class_max_n[c] * 64 words from gres + gres_off[c]
   size_t gres_off[NUM_CLASSES]; // host: word offset of each class's tables
@@ -80,6 +82,7 @@ struct SweepArgs {
   int32_t res_slots;            // <= RES_SLOTS
   int32_t path;                 // EVAL_PATH_*
   int32_t small_loads;          // every C_hat < 2^20
+  int32_t persistent;           // first pass as a persistent kernel over a work counter
 };
 
 // Packing of the per-DAG minimum: bound < 2^42 (the summed load is < 2^40)

@@ -704,9 +704,8 @@ __device__ bool eval_tile(const SweepArgs& a, int item, unsigned char* smem, uin
 // overflows it restarts at once with one of the global-memory tables, or,
 // when all are taken, is listed for the second pass.
 template <int NW, bool SMALL>
-__global__ __launch_bounds__(64) void k_eval(SweepArgs a, uint32_t* counters, uint32_t* list) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  const int item = blockIdx.x;
+__device__ void first_pass_tile(const SweepArgs& a, int item, unsigned char* smem, uint32_t* counters,
+                                uint32_t* list) {
   if (eval_tile<NW, false, SMALL>(a, item, smem, nullptr)) {
     uint32_t g = 0;
     if (threadIdx.x == 0) g = atomicAdd(&counters[1], 1u);
@@ -717,6 +716,29 @@ __global__ __launch_bounds__(64) void k_eval(SweepArgs a, uint32_t* counters, ui
     } else if (threadIdx.x == 0) {
       list[atomicAdd(&counters[0], 1u)] = (uint32_t)item;
     }
+  }
+}
+
+template <int NW, bool SMALL>
+__global__ __launch_bounds__(64) void k_eval(SweepArgs a, uint32_t* counters, uint32_t* list) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  first_pass_tile<NW, SMALL>(a, blockIdx.x, smem, counters, list);
+}
+
+// Persistent form of the first pass: as many workgroups as fit on the device
+// at once, each taking tiles from a work counter until all `total` are taken.
+// Every workgroup leaves the loop when the counter passes `total`.
+template <int NW, bool SMALL>
+__global__ __launch_bounds__(64) void k_eval_persistent(SweepArgs a, uint32_t* counters, uint32_t* list,
+                                                        int total) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  for (;;) {
+    uint32_t item = 0;
+    if (threadIdx.x == 0) item = atomicAdd(&counters[2], 1u);
+    item = __shfl(item, 0);
+    if (item >= (uint32_t)total) break;
+    first_pass_tile<NW, SMALL>(a, (int)item, smem, counters, list);
+    __syncthreads();
   }
 }
 
@@ -738,7 +760,7 @@ __global__ __launch_bounds__(64) void k_eval_global(SweepArgs a, const uint32_t*
 __global__ void k_eval_init(unsigned long long* best, int32_t D, uint32_t* counters) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < D) best[i] = ~0ull;
-  if (i < 2 * NUM_CLASSES) counters[i] = 0;
+  if (i < COUNTERS_PER_CLASS * NUM_CLASSES) counters[i] = 0;
 }
 
 __global__ void k_best_final(const unsigned long long* best, int32_t D, int32_t* idx, int64_t* bnd,
@@ -758,7 +780,21 @@ hipError_t launch_nw(const SweepArgs& a, uint32_t* counters, uint32_t* list, hip
   const int total = a.list_len * ntile;
   hipError_t e = hipSuccess;
   if (total <= 0) return e;
-  if (a.path != EVAL_PATH_GLOBAL) {
+  if (a.path != EVAL_PATH_GLOBAL && a.persistent) {
+    const size_t lds = lds_layout(a.max_n, NW, false).total;
+    const void* fn = (const void*)k_eval_persistent<NW, SMALL>;
+    e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    int per_cu = 0, dev = 0, cus = 0;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, WAVE, lds);
+    if (e == hipSuccess) e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
+    const int grid = max(1, min(total, max(1, per_cu) * max(1, cus)));
+    hipLaunchKernelGGL((k_eval_persistent<NW, SMALL>), dim3(grid), dim3(WAVE), lds, stream, a, counters, list,
+                       total);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  } else if (a.path != EVAL_PATH_GLOBAL) {
     const size_t lds = lds_layout(a.max_n, NW, false).total;
     e = hipFuncSetAttribute((const void*)k_eval<NW, SMALL>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -832,7 +868,7 @@ hipError_t launch_sweep(const SweepArgs& a, hipStream_t stream, const SweepStrea
       e = hipStreamWaitEvent(sc, ss->fork, 0);
       if (e != hipSuccess) break;
     }
-    uint32_t* counters = a.ovf_count + 2 * c;
+    uint32_t* counters = a.ovf_count + COUNTERS_PER_CLASS * c;
     uint32_t* list = a.ovf_list + (size_t)(a.order ? a.class_off[c] : 0) * ntile;
     e = a.small_loads ? launch_class<true>(c, ac, counters, list, sc)
                       : launch_class<false>(c, ac, counters, list, sc);

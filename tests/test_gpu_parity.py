@@ -283,16 +283,44 @@ def mixed_size_batch():
     return W.from_dags(dags)
 
 
-@pytest.mark.parametrize("classes,streams", [(1, 1), (1, 0), (0, 1)])
-def test_mixed_size_classes(torch_dev, classes, streams):
+@pytest.mark.parametrize("classes,streams,persistent", [(1, 1, 0), (1, 0, 0), (0, 1, 0), (1, 1, 1), (0, 0, 1)])
+def test_mixed_size_classes(torch_dev, classes, streams, persistent):
     batch = mixed_size_batch()
     sizes = np.diff(batch.node_off)
     assert sizes.max() > 256 and (sizes <= 64).any() and ((sizes > 64) & (sizes <= 128)).any()
     K, M = 70, 256
     alloc = W.alloc_bytes(batch, M, K, seed=5)
-    say("mixed size classes:", batch.num_dags, "DAGs, size_classes", classes, "class_streams", streams)
-    got = gpu_eval(torch_dev, batch, M, K, alloc, tuning={"size_classes": classes, "class_streams": streams})
+    say("mixed size classes:", batch.num_dags, "DAGs, size_classes", classes, "class_streams", streams,
+        "persistent", persistent)
+    got = gpu_eval(torch_dev, batch, M, K, alloc,
+                   tuning={"size_classes": classes, "class_streams": streams, "persistent": persistent})
     check_against_oracle(batch, M, K, alloc, got)
+
+
+def test_autotune_keeps_results(torch_dev):
+    # The autotuning evaluation runs every launch plan; its results and the
+    # next evaluation's (with the chosen plan) both match the oracle.
+    import paper_2602_20826_amd as db
+
+    torch, dev = torch_dev
+    batch = mixed_size_batch()
+    M, K = 256, 64
+    alloc = W.alloc_bytes(batch, M, K, seed=13)
+    want, _, _ = oracle.bounds_batch(batch, M, K, alloc, threads=8)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    st = torch.cuda.current_stream(dev)
+    b = db.create_batch(t(batch.node_off), t(batch.edge_off), t(batch.src), t(batch.dst), t(batch.wcet),
+                        t(batch.par), M, stream=st)
+    a_dev = t(alloc)
+    db.set_allocations(b, K, db.ALLOC_EXPLICIT, a_dev)
+    db.set_tuning(b, "autotune", 1)
+    for rep in range(2):
+        out = torch.full((batch.num_dags * K,), -1, dtype=torch.int64, device=dev)
+        say("autotune evaluation", rep)
+        db.eval_bounds(b, out, stream=st)
+        torch.cuda.synchronize()
+        assert np.array_equal(out.cpu().numpy().reshape(batch.num_dags, K), want), rep
+    b.close()
 
 
 def test_tuning_rejects_bad_keys(torch_dev):
@@ -300,7 +328,7 @@ def test_tuning_rejects_bad_keys(torch_dev):
 
     batch = W.generate_workload(1, count=2)
     b = db.create_batch(batch.node_off, batch.edge_off, batch.src, batch.dst, batch.wcet, batch.par, 8)
-    for key, val in [("residual_slots", 0), ("residual_slots", 13), ("eval_path", 2), ("size_classes", 2), ("class_streams", 3),
+    for key, val in [("residual_slots", 0), ("residual_slots", 13), ("eval_path", 2), ("size_classes", 2), ("class_streams", 3), ("persistent", 2), ("autotune", -1),
                      ("nope", 1)]:
         with pytest.raises(db.DagboundError):
             db.set_tuning(b, key, val)
