@@ -185,6 +185,7 @@ struct dagbound_batch {
   bool autotune_pending = false;       // time the launch plans on the next evaluation
   float plan_ms[4] = {0, 0, 0, 0};     // last autotune: (persistent, class_streams) = (p, s) at 2p + s
   size_t gres_off[NUM_CLASSES] = {0, 0, 0, 0};
+  uint64_t* grows = nullptr;           // row regions for DAGs above 256 nodes
   hipEvent_t ev[NUM_CLASSES + 1] = {nullptr, nullptr, nullptr, nullptr, nullptr};  // fork, joins
   // per-allocation-set scratch: tiles handed to the global pass
   void* ovf_block = nullptr;
@@ -236,6 +237,7 @@ SweepArgs sweep_args(const dagbound_batch* b) {
   for (int c = 0; c <= NUM_CLASSES; c++) a.class_off[c] = b->class_off[c];
   for (int c = 0; c < NUM_CLASSES; c++) a.class_max_n[c] = b->class_max_n[c];
   for (int c = 0; c < NUM_CLASSES; c++) a.gres_off[c] = b->gres_off[c];
+  a.grows = b->grows;
   a.ovf_list = b->ovf_list;
   a.ovf_count = b->ovf_count;
   a.gres = b->gres;
@@ -383,7 +385,8 @@ dagbound_status dagbound_create_batch(int32_t num_dags, const int64_t* node_off,
     }
   }
   const size_t gres_words = sweep_gres_words(b->class_max_n, b->class_off, (int32_t)max_n);
-  b->block_size = table_bytes(D, tn, te, gres_words);
+  const size_t rows_words = max_n > 256 ? (size_t)ROW_REGIONS * 2 * (size_t)max_n * 8 : 0;
+  b->block_size = table_bytes(D, tn, te, gres_words) + rows_words * 8 + 256;
   hipError_t e = dev_alloc(&b->block, &b->block_size, device);
   if (e != hipSuccess) {
     delete b;
@@ -398,6 +401,7 @@ dagbound_status dagbound_create_batch(int32_t num_dags, const int64_t* node_off,
   b->best = cv.take<unsigned long long>(D);
   b->err = cv.take<unsigned long long>(2);
   b->gres = cv.take<uint32_t>(gres_words);
+  if (rows_words) b->grows = cv.take<uint64_t>(rows_words);
   b->t.wc = cv.take<uint32_t>(tn);
   b->t.soff = cv.take<uint32_t>(tn + D);
   b->t.ngroups = cv.take<int32_t>(D);

@@ -48,6 +48,9 @@ constexpr int RES_SLOTS = 12;
 // that overflows its LDS table takes one and finishes at once; the second
 // pass (one workgroup per table) takes the tiles left when all are taken.
 constexpr int GLOBAL_PASS_GRID = 256;
+// Global row regions for eight-word bitsets: one per workgroup of the
+// persistent first pass (at most this many) and of the second pass.
+constexpr int ROW_REGIONS = 2048;
 enum : int32_t { EVAL_PATH_AUTO = 0, EVAL_PATH_GLOBAL = 1 };
 
 // DAGs are evaluated in size classes (up to 64, 128, 256, 512 nodes), one
@@ -77,6 +80,8 @@ struct SweepArgs {
   uint32_t* gres;               // residual tables: class c owns GLOBAL_PASS_GRID tables of
                                 // class_max_n[c] * 64 words from gres + gres_off[c]
   size_t gres_off[NUM_CLASSES]; // host: word offset of each class's tables
+  uint64_t* grows;              // ROW_REGIONS regions of 2 * max_n * 8 words (predecessor and successor
+                                // rows of DAGs above 256 nodes), or nullptr when no DAG needs them
   int32_t max_n, max_e;
   const int32_t* cand_list;     // [D][K] candidate ids to evaluate, or nullptr (ids 0..K-1)
   int32_t res_slots;            // <= RES_SLOTS

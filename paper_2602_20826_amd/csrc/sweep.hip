@@ -213,6 +213,10 @@ __device__ inline uint64_t wave_or64(uint64_t x) {
 // (lane x holds the rows of nodes x, 64 + x, ...) while they are small, and
 // in LDS above that.
 template <int NW> struct RowsInRegs { static constexpr bool value = NW <= 4; };
+// Eight-word rows (DAGs of 257-512 nodes) live in a global-memory region of
+// the workgroup instead of LDS, which keeps the workgroup's LDS small
+// enough for several waves per compute unit.
+template <int NW> struct RowsInGlobal { static constexpr bool value = NW == 8; };
 
 // LDS layout of one wavefront (bytes), for the batch's largest DAG.
 struct Lds {
@@ -233,6 +237,8 @@ __host__ __device__ inline Lds lds_layout(int maxn, int nw, bool big) {
     // built in the candidate-byte region before the bytes are loaded
     l.pb = l.r;
     l.sb = l.r + (size_t)maxn * nw * 8;
+  } else if (nw == 8) {
+    l.pb = l.sb = 0;  // in global memory
   } else {
     l.pb = o; o += (size_t)maxn * nw * 8;       // predecessor bitsets by sigma rank
     l.sb = o; o += (size_t)maxn * nw * 8;       // successor bitsets by sigma rank
@@ -277,8 +283,9 @@ __device__ inline uint32_t round_share_small(uint32_t cv, uint32_t M, uint32_t W
 // overflowed (nothing was written; the tile must be redone by the
 // global-table pass).
 template <int NW, bool BIG, bool SMALL>
-__device__ bool eval_tile(const SweepArgs& a, int item, unsigned char* smem, uint32_t* gres) {
+__device__ bool eval_tile(const SweepArgs& a, int item, unsigned char* smem, uint32_t* gres, uint64_t* grows) {
   constexpr bool REG = RowsInRegs<NW>::value;
+  constexpr bool GROWS = RowsInGlobal<NW>::value;
   const int ntile = (a.K + WAVE - 1) / WAVE;
   const int li = item / ntile;
   const int tile = item - li * ntile;
@@ -296,8 +303,8 @@ __device__ bool eval_tile(const SweepArgs& a, int item, unsigned char* smem, uin
   uint2* s_node = (uint2*)(smem + L.node);     // {C_hat, pp} by sigma rank
   uint16_t* s_ppv = (uint16_t*)(smem + L.ppv); // [local id]
   uint16_t* s_inv = (uint16_t*)(smem + L.inv); // [local id]
-  uint64_t* s_pb = (uint64_t*)(smem + L.pb);   // [sigma][NW]
-  uint64_t* s_sb = (uint64_t*)(smem + L.sb);   // [sigma][NW]
+  uint64_t* s_pb = GROWS ? grows : (uint64_t*)(smem + L.pb);  // [sigma][NW]
+  uint64_t* s_sb = GROWS ? grows + (size_t)a.max_n * NW : (uint64_t*)(smem + L.sb);  // [sigma][NW]
   uint32_t* res = BIG ? gres : (uint32_t*)(smem + L.res);  // [slot][lane], or [sigma][lane] when BIG
   uint8_t* s_r = smem + L.r;                   // [sigma][lane]
   uint32_t* s_map = (uint32_t*)(smem + L.map); // [sigma / 8][lane], 4 bits per node: slot + 1
@@ -306,6 +313,7 @@ __device__ bool eval_tile(const SweepArgs& a, int item, unsigned char* smem, uin
   for (int s = lane; s < N; s += WAVE) s_node[s] = make_uint2(a.t.wc[n0 + s], a.t.pp[n0 + s]);
   for (int v = lane; v < N; v += WAVE) s_inv[v] = a.t.inv[n0 + v];
   for (int i = lane; i < N * NW; i += WAVE) { s_pb[i] = 0; s_sb[i] = 0; }
+  if (GROWS) __threadfence_block();
   __syncthreads();
   for (int v = lane; v < N; v += WAVE) s_ppv[v] = (uint16_t)s_node[s_inv[v]].y;
   // successor bitset of x (this lane's row) and predecessor bits of its successors
@@ -322,6 +330,7 @@ __device__ bool eval_tile(const SweepArgs& a, int item, unsigned char* smem, uin
 #pragma unroll
     for (int w = 0; w < NW; w++) s_sb[x * NW + w] = row[w];
   }
+  if (GROWS) __threadfence_block();
   for (int k = lane; k < N; k += WAVE) {
     const uint32_t g = a.t.gl[n0 + k];
     const int s = g & 0x7FFF;
@@ -705,24 +714,31 @@ __device__ bool eval_tile(const SweepArgs& a, int item, unsigned char* smem, uin
 // when all are taken, is listed for the second pass.
 template <int NW, bool SMALL>
 __device__ void first_pass_tile(const SweepArgs& a, int item, unsigned char* smem, uint32_t* counters,
-                                uint32_t* list) {
-  if (eval_tile<NW, false, SMALL>(a, item, smem, nullptr)) {
+                                uint32_t* list, uint64_t* grows) {
+  if (eval_tile<NW, false, SMALL>(a, item, smem, nullptr, grows)) {
     uint32_t g = 0;
     if (threadIdx.x == 0) g = atomicAdd(&counters[1], 1u);
     g = __shfl(g, 0);
     __syncthreads();
     if (g < (uint32_t)GLOBAL_PASS_GRID) {
-      eval_tile<NW, true, SMALL>(a, item, smem, a.gres + (size_t)g * (size_t)a.max_n * WAVE);
+      eval_tile<NW, true, SMALL>(a, item, smem, a.gres + (size_t)g * (size_t)a.max_n * WAVE, grows);
     } else if (threadIdx.x == 0) {
       list[atomicAdd(&counters[0], 1u)] = (uint32_t)item;
     }
   }
 }
 
+// Row region of workgroup `slot` (eight-word bitsets only).
+__device__ inline uint64_t* rows_of(const SweepArgs& a, int slot) {
+  return a.grows ? a.grows + (size_t)slot * 2 * (size_t)a.max_n * 8 : nullptr;
+}
+
 template <int NW, bool SMALL>
 __global__ __launch_bounds__(64) void k_eval(SweepArgs a, uint32_t* counters, uint32_t* list) {
   extern __shared__ __align__(16) unsigned char smem[];
-  first_pass_tile<NW, SMALL>(a, blockIdx.x, smem, counters, list);
+  // eight-word bitsets run the persistent form only (their row regions are
+  // per running workgroup)
+  if constexpr (!RowsInGlobal<NW>::value) first_pass_tile<NW, SMALL>(a, blockIdx.x, smem, counters, list, nullptr);
 }
 
 // Persistent form of the first pass: as many workgroups as fit on the device
@@ -732,12 +748,13 @@ template <int NW, bool SMALL>
 __global__ __launch_bounds__(64) void k_eval_persistent(SweepArgs a, uint32_t* counters, uint32_t* list,
                                                         int total) {
   extern __shared__ __align__(16) unsigned char smem[];
+  uint64_t* grows = rows_of(a, blockIdx.x);
   for (;;) {
     uint32_t item = 0;
     if (threadIdx.x == 0) item = atomicAdd(&counters[2], 1u);
     item = __shfl(item, 0);
     if (item >= (uint32_t)total) break;
-    first_pass_tile<NW, SMALL>(a, (int)item, smem, counters, list);
+    first_pass_tile<NW, SMALL>(a, (int)item, smem, counters, list, grows);
     __syncthreads();
   }
 }
@@ -750,9 +767,10 @@ __global__ __launch_bounds__(64) void k_eval_global(SweepArgs a, const uint32_t*
   extern __shared__ __align__(16) unsigned char smem[];
   const int count = direct ? total : (int)counters[0];
   uint32_t* gres = a.gres + (size_t)blockIdx.x * (size_t)a.max_n * WAVE;
+  uint64_t* grows = rows_of(a, blockIdx.x);
   for (int q = blockIdx.x; q < count; q += gridDim.x) {
     const int item = direct ? q : (int)list[q];
-    eval_tile<NW, true, SMALL>(a, item, smem, gres);
+    eval_tile<NW, true, SMALL>(a, item, smem, gres, grows);
     __syncthreads();
   }
 }
@@ -780,7 +798,8 @@ hipError_t launch_nw(const SweepArgs& a, uint32_t* counters, uint32_t* list, hip
   const int total = a.list_len * ntile;
   hipError_t e = hipSuccess;
   if (total <= 0) return e;
-  if (a.path != EVAL_PATH_GLOBAL && a.persistent) {
+  // eight-word rows need a row region per running workgroup: persistent only
+  if (a.path != EVAL_PATH_GLOBAL && (a.persistent || RowsInGlobal<NW>::value)) {
     const size_t lds = lds_layout(a.max_n, NW, false).total;
     const void* fn = (const void*)k_eval_persistent<NW, SMALL>;
     e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -790,7 +809,8 @@ hipError_t launch_nw(const SweepArgs& a, uint32_t* counters, uint32_t* list, hip
     if (e == hipSuccess) e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess) return e;
-    const int grid = max(1, min(total, max(1, per_cu) * max(1, cus)));
+    int grid = max(1, min(total, max(1, per_cu) * max(1, cus)));
+    if (RowsInGlobal<NW>::value) grid = min(grid, ROW_REGIONS);
     hipLaunchKernelGGL((k_eval_persistent<NW, SMALL>), dim3(grid), dim3(WAVE), lds, stream, a, counters, list,
                        total);
     if ((e = hipGetLastError()) != hipSuccess) return e;
