@@ -185,7 +185,8 @@ struct dagbound_batch {
   bool autotune_pending = false;       // time the launch plans on the next evaluation
   float plan_ms[4] = {0, 0, 0, 0};     // last autotune: (persistent, class_streams) = (p, s) at 2p + s
   size_t gres_off[NUM_CLASSES] = {0, 0, 0, 0};
-  uint64_t* grows = nullptr;           // row regions for DAGs above 256 nodes
+  uint64_t* grows = nullptr;           // row regions for DAGs above 128 nodes
+  size_t rows_off[NUM_CLASSES + 1] = {0, 0, 0, 0, 0};
   hipEvent_t ev[NUM_CLASSES + 1] = {nullptr, nullptr, nullptr, nullptr, nullptr};  // fork, joins
   // per-allocation-set scratch: tiles handed to the global pass
   void* ovf_block = nullptr;
@@ -238,6 +239,7 @@ SweepArgs sweep_args(const dagbound_batch* b) {
   for (int c = 0; c < NUM_CLASSES; c++) a.class_max_n[c] = b->class_max_n[c];
   for (int c = 0; c < NUM_CLASSES; c++) a.gres_off[c] = b->gres_off[c];
   a.grows = b->grows;
+  for (int c = 0; c <= NUM_CLASSES; c++) a.rows_off[c] = b->rows_off[c];
   a.ovf_list = b->ovf_list;
   a.ovf_count = b->ovf_count;
   a.gres = b->gres;
@@ -385,7 +387,7 @@ dagbound_status dagbound_create_batch(int32_t num_dags, const int64_t* node_off,
     }
   }
   const size_t gres_words = sweep_gres_words(b->class_max_n, b->class_off, (int32_t)max_n);
-  const size_t rows_words = max_n > 256 ? (size_t)ROW_REGIONS * 2 * (size_t)max_n * 8 : 0;
+  const size_t rows_words = sweep_rows_words(b->class_max_n, b->class_off, (int32_t)max_n, b->rows_off);
   b->block_size = table_bytes(D, tn, te, gres_words) + rows_words * 8 + 256;
   hipError_t e = dev_alloc(&b->block, &b->block_size, device);
   if (e != hipSuccess) {
@@ -822,7 +824,10 @@ dagbound_status dagbound_model_create(uint64_t seed, dagbound_model** out) {
   std::vector<float> h;
   model_init_params(seed, h);
   e = hipMemcpy(m->p, h.data(), h.size() * 4, hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemset(m->g, 0, (size_t)SUR_PARAMS * 4 * 3);
+  // gradient and both Adam moments start at zero (three separate 256-byte
+  // aligned arrays, so one memset over the first would miss the gaps' tail)
+  for (float* z : {m->g, m->m1, m->m2})
+    if (e == hipSuccess) e = hipMemset(z, 0, (size_t)SUR_PARAMS * 4);
   SurArgs s{};
   s.p = m->p;
   s.wfwd = m->wfwd;

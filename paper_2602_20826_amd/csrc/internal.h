@@ -50,7 +50,7 @@ constexpr int RES_SLOTS = 12;
 constexpr int GLOBAL_PASS_GRID = 256;
 // Global row regions for eight-word bitsets: one per workgroup of the
 // persistent first pass (at most this many) and of the second pass.
-constexpr int ROW_REGIONS = 2048;
+constexpr int ROW_REGIONS = 1024;
 enum : int32_t { EVAL_PATH_AUTO = 0, EVAL_PATH_GLOBAL = 1 };
 
 // DAGs are evaluated in size classes (up to 64, 128, 256, 512 nodes), one
@@ -80,8 +80,10 @@ struct SweepArgs {
   uint32_t* gres;               // residual tables: class c owns GLOBAL_PASS_GRID tables of
                                 // class_max_n[c] * 64 words from gres + gres_off[c]
   size_t gres_off[NUM_CLASSES]; // host: word offset of each class's tables
-  uint64_t* grows;              // ROW_REGIONS regions of 2 * max_n * 8 words (predecessor and successor
-                                // rows of DAGs above 256 nodes), or nullptr when no DAG needs them
+  uint64_t* grows;              // row regions (predecessor and successor rows kept in global memory):
+                                // class c owns ROW_REGIONS regions of 2 * class_max_n[c] * NW words
+                                // from grows + rows_off[c]; rows_off[NUM_CLASSES] is the one-launch pool
+  size_t rows_off[NUM_CLASSES + 1];
   int32_t max_n, max_e;
   const int32_t* cand_list;     // [D][K] candidate ids to evaluate, or nullptr (ids 0..K-1)
   int32_t res_slots;            // <= RES_SLOTS
@@ -106,6 +108,10 @@ struct SweepStreams {
   hipEvent_t fork;
   hipEvent_t join[NUM_CLASSES];
 };
+
+// Words of row regions a batch needs, and each pool's offset.
+size_t sweep_rows_words(const int32_t class_max_n[NUM_CLASSES], const int32_t class_off[NUM_CLASSES + 1],
+                        int32_t max_n, size_t rows_off[NUM_CLASSES + 1]);
 
 // Words of residual tables a batch needs (all classes with DAGs).
 size_t sweep_gres_words(const int32_t class_max_n[NUM_CLASSES], const int32_t class_off[NUM_CLASSES + 1],

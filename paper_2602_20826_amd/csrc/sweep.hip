@@ -212,18 +212,22 @@ __device__ inline uint64_t wave_or64(uint64_t x) {
 // Predecessor and successor bitsets of the DAG's nodes live in registers
 // (lane x holds the rows of nodes x, 64 + x, ...) while they are small, and
 // in LDS above that.
-template <int NW> struct RowsInRegs { static constexpr bool value = NW <= 4; };
-// Eight-word rows (DAGs of 257-512 nodes) live in a global-memory region of
-// the workgroup instead of LDS, which keeps the workgroup's LDS small
+// Eight-word rows (DAGs of 257-512 nodes), and four-word rows when the
+// candidate bytes are drawn on the fly (RS), live in a global-memory region
+// of the workgroup instead of LDS, which keeps the workgroup's LDS small
 // enough for several waves per compute unit.
-template <int NW> struct RowsInGlobal { static constexpr bool value = NW == 8; };
+template <int NW, bool RS> struct RowsInGlobal { static constexpr bool value = NW == 8 || (NW == 4 && RS); };
+template <int NW, bool RS> struct RowsInRegs {
+  static constexpr bool value = NW <= 4 && !RowsInGlobal<NW, RS>::value;
+};
 
 // LDS layout of one wavefront (bytes), for the batch's largest DAG.
 struct Lds {
   size_t mem, node, ppv, inv, pb, sb, res, r, map, total;
 };
-__host__ __device__ inline Lds lds_layout(int maxn, int nw, bool big) {
-  const bool regs = nw <= 4;
+__host__ __device__ inline Lds lds_layout(int maxn, int nw, bool big, bool rs) {
+  const bool grows = nw == 8 || (nw == 4 && rs);
+  const bool regs = nw <= 4 && !grows;
   Lds l;
   size_t o = 0;
   l.mem = o;  o += (size_t)maxn * 8;            // members in group order
@@ -231,13 +235,13 @@ __host__ __device__ inline Lds lds_layout(int maxn, int nw, bool big) {
   l.ppv = o;  o += ((size_t)maxn * 2 + 15) & ~(size_t)15;  // min(p, M) by local id
   l.inv = o;  o += ((size_t)maxn * 2 + 15) & ~(size_t)15;  // sigma rank by local id
   l.res = o;  o += big ? 0 : (size_t)RES_SLOTS * WAVE * 4;  // residual table [slot][lane]
-  l.r = o;    o += (size_t)maxn * WAVE;         // candidate bytes [sigma][lane]
+  l.r = o;    o += rs ? 0 : (size_t)maxn * WAVE;  // candidate bytes [sigma][lane] (none when drawn on the fly)
   l.map = o;  o += big ? 0 : (size_t)((maxn + 7) / 8) * WAVE * 4;  // residual slot of a node, 4 bits
   if (regs) {
     // built in the candidate-byte region before the bytes are loaded
     l.pb = l.r;
     l.sb = l.r + (size_t)maxn * nw * 8;
-  } else if (nw == 8) {
+  } else if (grows) {
     l.pb = l.sb = 0;  // in global memory
   } else {
     l.pb = o; o += (size_t)maxn * nw * 8;       // predecessor bitsets by sigma rank
@@ -282,10 +286,10 @@ __device__ inline uint32_t round_share_small(uint32_t cv, uint32_t M, uint32_t W
 // One (DAG, 64-candidate tile).  Returns true if a lane's residual table
 // overflowed (nothing was written; the tile must be redone by the
 // global-table pass).
-template <int NW, bool BIG, bool SMALL>
+template <int NW, bool BIG, bool SMALL, bool RS>
 __device__ bool eval_tile(const SweepArgs& a, int item, unsigned char* smem, uint32_t* gres, uint64_t* grows) {
-  constexpr bool REG = RowsInRegs<NW>::value;
-  constexpr bool GROWS = RowsInGlobal<NW>::value;
+  constexpr bool REG = RowsInRegs<NW, RS>::value;
+  constexpr bool GROWS = RowsInGlobal<NW, RS>::value;
   const int ntile = (a.K + WAVE - 1) / WAVE;
   const int li = item / ntile;
   const int tile = item - li * ntile;
@@ -298,9 +302,9 @@ __device__ bool eval_tile(const SweepArgs& a, int item, unsigned char* smem, uin
   const int N = (int)uni((uint32_t)(a.t.node_off[d + 1] - n0));
   const int64_t e0 = a.t.edge_off[d];
   const uint32_t M = (uint32_t)a.M;
-  const Lds L = lds_layout(a.max_n, NW, BIG);
+  const Lds L = lds_layout(a.max_n, NW, BIG, RS);
   uint2* s_mem = (uint2*)(smem + L.mem);       // {C_hat, pp | s << 16 | last << 31}
-  uint2* s_node = (uint2*)(smem + L.node);     // {C_hat, pp} by sigma rank
+  uint2* s_node = (uint2*)(smem + L.node);     // {C_hat, pp | local id << 16} by sigma rank
   uint16_t* s_ppv = (uint16_t*)(smem + L.ppv); // [local id]
   uint16_t* s_inv = (uint16_t*)(smem + L.inv); // [local id]
   uint64_t* s_pb = GROWS ? grows : (uint64_t*)(smem + L.pb);  // [sigma][NW]
@@ -315,7 +319,12 @@ __device__ bool eval_tile(const SweepArgs& a, int item, unsigned char* smem, uin
   for (int i = lane; i < N * NW; i += WAVE) { s_pb[i] = 0; s_sb[i] = 0; }
   if (GROWS) __threadfence_block();
   __syncthreads();
-  for (int v = lane; v < N; v += WAVE) s_ppv[v] = (uint16_t)s_node[s_inv[v]].y;
+  for (int v = lane; v < N; v += WAVE) {
+    const int s = s_inv[v];
+    const uint32_t y = s_node[s].y;
+    s_ppv[v] = (uint16_t)y;
+    s_node[s].y = y | ((uint32_t)v << 16);
+  }
   // successor bitset of x (this lane's row) and predecessor bits of its successors
   for (int x = lane; x < N; x += WAVE) {
     uint64_t row[NW];
@@ -335,7 +344,7 @@ __device__ bool eval_tile(const SweepArgs& a, int item, unsigned char* smem, uin
     const uint32_t g = a.t.gl[n0 + k];
     const int s = g & 0x7FFF;
     const uint2 nd = s_node[s];
-    s_mem[k] = make_uint2(nd.x, nd.y | ((uint32_t)s << 16) | ((g & 0x8000u) << 16));
+    s_mem[k] = make_uint2(nd.x, (nd.y & 0xFFFFu) | ((uint32_t)s << 16) | ((g & 0x8000u) << 16));
   }
   __syncthreads();
   // released: the sources; finished: none.  With REG, lane x keeps the rows
@@ -370,7 +379,16 @@ __device__ bool eval_tile(const SweepArgs& a, int item, unsigned char* smem, uin
   uint32_t freem = (1u << a.res_slots) - 1u;  // free residual slots
   // ---- candidate bytes of this lane, by sigma rank.  Candidate 0 is the
   // paper's own rule (all zero); lanes past K run zeros and store nothing.
-  if (a.alloc) {
+  // With RS the seeded bytes are drawn where they are used (r_of).
+  const bool rlive = c > 0 && active;
+  const uint64_t rkey = a.alloc ? 0ull : mix64(a.seed ^ mix64((uint64_t)d * 0x9E3779B97F4A7C15ull));
+  auto r_of = [&](uint32_t v, uint32_t pp) -> uint32_t {
+    const uint64_t word = mix64(rkey ^ (((uint64_t)c << 32) | (uint64_t)(v >> 2)));
+    const uint32_t h16 = (uint32_t)(word >> (16 * (v & 3))) & 0xFFFFu;
+    return rlive ? 1u + ((h16 * min(pp, 255u)) >> 16) : 0u;
+  };
+  if (RS) {
+  } else if (a.alloc) {
     if (c > 0 && active) {
       // 16-byte aligned loads over the lane's row; an aligned chunk holding a
       // byte of the row never leaves that byte's page.
@@ -391,10 +409,9 @@ __device__ bool eval_tile(const SweepArgs& a, int item, unsigned char* smem, uin
       for (int v = 0; v < N; v++) s_r[v * WAVE + lane] = 0;
     }
   } else {
-    const uint64_t key = mix64(a.seed ^ mix64((uint64_t)d * 0x9E3779B97F4A7C15ull));
     uint64_t word = 0;
     for (int v = 0; v < N; v++) {
-      if ((v & 3) == 0) word = mix64(key ^ (((uint64_t)c << 32) | (uint64_t)(v >> 2)));
+      if ((v & 3) == 0) word = mix64(rkey ^ (((uint64_t)c << 32) | (uint64_t)(v >> 2)));
       const uint32_t range = min((uint32_t)s_ppv[v], 255u);
       const uint32_t h16 = (uint32_t)(word >> (16 * (v & 3))) & 0xFFFFu;
       const uint32_t r = 1u + ((h16 * range) >> 16);
@@ -471,11 +488,21 @@ __device__ bool eval_tile(const SweepArgs& a, int item, unsigned char* smem, uin
       uint2 rec = rec0;
       if (base != k && base + lane < kend) rec = s_mem[base + lane];
       const int cnt = min(WAVE, kend - base);
-      uint32_t rnext = s_r[(((uint32_t)__builtin_amdgcn_readlane((int)rec.y, 0) >> 16) & 0x7FFF) * WAVE + lane];
+      uint32_t rnext = 0, recv = 0;
+      if (RS) {  // local ids of the chunk's members
+        if (base + lane < kend) recv = s_node[(rec.y >> 16) & 0x7FFF].y >> 16;
+      } else {
+        rnext = s_r[(((uint32_t)__builtin_amdgcn_readlane((int)rec.y, 0) >> 16) & 0x7FFF) * WAVE + lane];
+      }
       for (int i = 0; i < cnt; i++) {
         const int s = ((uint32_t)__builtin_amdgcn_readlane((int)rec.y, i) >> 16) & 0x7FFF;
-        const uint32_t rv = rnext;
-        if (i + 1 < cnt) rnext = s_r[(((uint32_t)__builtin_amdgcn_readlane((int)rec.y, i + 1) >> 16) & 0x7FFF) * WAVE + lane];
+        uint32_t rv = rnext;
+        if (RS) {
+          rv = r_of((uint32_t)__builtin_amdgcn_readlane((int)recv, i),
+                    (uint32_t)__builtin_amdgcn_readlane((int)rec.y, i) & 0xFFFFu);
+        } else if (i + 1 < cnt) {
+          rnext = s_r[(((uint32_t)__builtin_amdgcn_readlane((int)rec.y, i + 1) >> 16) & 0x7FFF) * WAVE + lane];
+        }
         if (!bit_get_u<NW>(rel, s)) continue;
         uint32_t cv = (uint32_t)__builtin_amdgcn_readlane((int)rec.x, i);
         if (bit_get_u<NW>(seg, s)) cv = *res_at(s);
@@ -507,13 +534,13 @@ __device__ bool eval_tile(const SweepArgs& a, int item, unsigned char* smem, uin
     int cn = S ? (CURSOR ? pq.pop(Q) : pop_first<NW>(Q)) : -1;
     int ci = max(cn, 0);
     uint2 nd = s_node[ci];
-    uint32_t rc = s_r[ci * WAVE + lane];
+    uint32_t rc = RS ? 0u : s_r[ci * WAVE + lane];
     uint32_t mw = BIG ? 0u : s_map[(ci >> 3) * WAVE + lane];
     bool go = cn >= 0;
     while (go) {
       const int cur = cn;
       const uint2 ndc = nd;
-      const uint32_t rcc = rc, mwc = mw;
+      const uint32_t rcc = RS ? r_of(ndc.y >> 16, ndc.y & 0xFFFFu) : rc, mwc = mw;
       // remaining load of cur: read before the next node's data, so that
       // waiting for it leaves those reads in flight
       bool sg;
@@ -530,9 +557,9 @@ __device__ bool eval_tile(const SweepArgs& a, int item, unsigned char* smem, uin
       cn = CURSOR ? pq.pop(Q) : pop_first<NW>(Q);
       ci = max(cn, 0);
       nd = s_node[ci];
-      rc = s_r[ci * WAVE + lane];
+      if (!RS) rc = s_r[ci * WAVE + lane];
       if (!BIG) mw = s_map[(ci >> 3) * WAVE + lane];
-      const uint32_t mx = min(ndc.y, cc);
+      const uint32_t mx = min(ndc.y & 0xFFFFu, cc);
       const uint32_t mc = min(rcc ? min(rcc, mx) : mx, S);
       const uint64_t cap = (uint64_t)maxC * mc;
       const bool fits = (uint64_t)cc <= cap;
@@ -712,65 +739,67 @@ __device__ bool eval_tile(const SweepArgs& a, int item, unsigned char* smem, uin
 // First pass: one tile per workgroup, residual table in LDS.  A tile that
 // overflows it restarts at once with one of the global-memory tables, or,
 // when all are taken, is listed for the second pass.
-template <int NW, bool SMALL>
+template <int NW, bool SMALL, bool RS>
 __device__ void first_pass_tile(const SweepArgs& a, int item, unsigned char* smem, uint32_t* counters,
                                 uint32_t* list, uint64_t* grows) {
-  if (eval_tile<NW, false, SMALL>(a, item, smem, nullptr, grows)) {
+  if (eval_tile<NW, false, SMALL, RS>(a, item, smem, nullptr, grows)) {
     uint32_t g = 0;
     if (threadIdx.x == 0) g = atomicAdd(&counters[1], 1u);
     g = __shfl(g, 0);
     __syncthreads();
     if (g < (uint32_t)GLOBAL_PASS_GRID) {
-      eval_tile<NW, true, SMALL>(a, item, smem, a.gres + (size_t)g * (size_t)a.max_n * WAVE, grows);
+      eval_tile<NW, true, SMALL, RS>(a, item, smem, a.gres + (size_t)g * (size_t)a.max_n * WAVE, grows);
     } else if (threadIdx.x == 0) {
       list[atomicAdd(&counters[0], 1u)] = (uint32_t)item;
     }
   }
 }
 
-// Row region of workgroup `slot` (eight-word bitsets only).
+// Row region of workgroup `slot` (rows in global memory only).
+template <int NW>
 __device__ inline uint64_t* rows_of(const SweepArgs& a, int slot) {
-  return a.grows ? a.grows + (size_t)slot * 2 * (size_t)a.max_n * 8 : nullptr;
+  return a.grows ? a.grows + (size_t)slot * 2 * (size_t)a.max_n * NW : nullptr;
 }
 
-template <int NW, bool SMALL>
+template <int NW, bool SMALL, bool RS>
 __global__ __launch_bounds__(64) void k_eval(SweepArgs a, uint32_t* counters, uint32_t* list) {
   extern __shared__ __align__(16) unsigned char smem[];
-  // eight-word bitsets run the persistent form only (their row regions are
-  // per running workgroup)
-  if constexpr (!RowsInGlobal<NW>::value) first_pass_tile<NW, SMALL>(a, blockIdx.x, smem, counters, list, nullptr);
+  // rows in global memory run the persistent form only (their row regions
+  // are per running workgroup)
+  if constexpr (!RowsInGlobal<NW, RS>::value)
+    first_pass_tile<NW, SMALL, RS>(a, blockIdx.x, smem, counters, list, nullptr);
 }
 
 // Persistent form of the first pass: as many workgroups as fit on the device
 // at once, each taking tiles from a work counter until all `total` are taken.
 // Every workgroup leaves the loop when the counter passes `total`.
-template <int NW, bool SMALL>
+template <int NW, bool SMALL, bool RS>
 __global__ __launch_bounds__(64) void k_eval_persistent(SweepArgs a, uint32_t* counters, uint32_t* list,
                                                         int total) {
   extern __shared__ __align__(16) unsigned char smem[];
-  uint64_t* grows = rows_of(a, blockIdx.x);
+  uint64_t* grows = rows_of<NW>(a, blockIdx.x);
   for (;;) {
     uint32_t item = 0;
     if (threadIdx.x == 0) item = atomicAdd(&counters[2], 1u);
     item = __shfl(item, 0);
     if (item >= (uint32_t)total) break;
-    first_pass_tile<NW, SMALL>(a, (int)item, smem, counters, list, grows);
+    first_pass_tile<NW, SMALL, RS>(a, (int)item, smem, counters, list, grows);
     __syncthreads();
   }
 }
 
 // Second pass: the tiles the first pass listed (or every tile when
 // `direct`), residual tables in global memory sized to hold every node.
-template <int NW, bool SMALL>
+template <int NW, bool SMALL, bool RS>
 __global__ __launch_bounds__(64) void k_eval_global(SweepArgs a, const uint32_t* counters, const uint32_t* list,
                                                     int direct, int total) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int count = direct ? total : (int)counters[0];
   uint32_t* gres = a.gres + (size_t)blockIdx.x * (size_t)a.max_n * WAVE;
-  uint64_t* grows = rows_of(a, blockIdx.x);
+  uint64_t* grows = rows_of<NW>(a, blockIdx.x);
   for (int q = blockIdx.x; q < count; q += gridDim.x) {
     const int item = direct ? q : (int)list[q];
-    eval_tile<NW, true, SMALL>(a, item, smem, gres, grows);
+    eval_tile<NW, true, SMALL, RS>(a, item, smem, gres, grows);
     __syncthreads();
   }
 }
@@ -792,16 +821,17 @@ __global__ void k_best_final(const unsigned long long* best, int32_t D, int32_t*
   }
 }
 
-template <int NW, bool SMALL>
+template <int NW, bool SMALL, bool RS>
 hipError_t launch_nw(const SweepArgs& a, uint32_t* counters, uint32_t* list, hipStream_t stream) {
   const int ntile = (a.K + WAVE - 1) / WAVE;
   const int total = a.list_len * ntile;
   hipError_t e = hipSuccess;
   if (total <= 0) return e;
-  // eight-word rows need a row region per running workgroup: persistent only
-  if (a.path != EVAL_PATH_GLOBAL && (a.persistent || RowsInGlobal<NW>::value)) {
-    const size_t lds = lds_layout(a.max_n, NW, false).total;
-    const void* fn = (const void*)k_eval_persistent<NW, SMALL>;
+  constexpr bool GROWS = RowsInGlobal<NW, RS>::value;
+  // rows in global memory need a row region per running workgroup: persistent only
+  if (a.path != EVAL_PATH_GLOBAL && (a.persistent || GROWS)) {
+    const size_t lds = lds_layout(a.max_n, NW, false, RS).total;
+    const void* fn = (const void*)k_eval_persistent<NW, SMALL, RS>;
     e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     int per_cu = 0, dev = 0, cus = 0;
@@ -810,35 +840,40 @@ hipError_t launch_nw(const SweepArgs& a, uint32_t* counters, uint32_t* list, hip
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess) return e;
     int grid = max(1, min(total, max(1, per_cu) * max(1, cus)));
-    if (RowsInGlobal<NW>::value) grid = min(grid, ROW_REGIONS);
-    hipLaunchKernelGGL((k_eval_persistent<NW, SMALL>), dim3(grid), dim3(WAVE), lds, stream, a, counters, list,
+    if (GROWS) grid = min(grid, ROW_REGIONS);
+    hipLaunchKernelGGL((k_eval_persistent<NW, SMALL, RS>), dim3(grid), dim3(WAVE), lds, stream, a, counters, list,
                        total);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   } else if (a.path != EVAL_PATH_GLOBAL) {
-    const size_t lds = lds_layout(a.max_n, NW, false).total;
-    e = hipFuncSetAttribute((const void*)k_eval<NW, SMALL>,
+    const size_t lds = lds_layout(a.max_n, NW, false, RS).total;
+    e = hipFuncSetAttribute((const void*)k_eval<NW, SMALL, RS>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_eval<NW, SMALL>), dim3(total), dim3(WAVE), lds, stream, a, counters, list);
+    hipLaunchKernelGGL((k_eval<NW, SMALL, RS>), dim3(total), dim3(WAVE), lds, stream, a, counters, list);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
-  const size_t lds = lds_layout(a.max_n, NW, true).total;
-  e = hipFuncSetAttribute((const void*)k_eval_global<NW, SMALL>,
+  const size_t lds = lds_layout(a.max_n, NW, true, RS).total;
+  e = hipFuncSetAttribute((const void*)k_eval_global<NW, SMALL, RS>,
                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   const int grid = a.path == EVAL_PATH_GLOBAL ? min(total, GLOBAL_PASS_GRID) : GLOBAL_PASS_GRID;
-  hipLaunchKernelGGL((k_eval_global<NW, SMALL>), dim3(grid), dim3(WAVE), lds, stream, a, counters, list,
+  hipLaunchKernelGGL((k_eval_global<NW, SMALL, RS>), dim3(grid), dim3(WAVE), lds, stream, a, counters, list,
                      a.path == EVAL_PATH_GLOBAL ? 1 : 0, total);
   return hipGetLastError();
 }
 
+// Seeded candidates of DAGs above 128 nodes are drawn where they are used
+// (no LDS for the bytes); smaller DAGs keep them in LDS.
 template <bool SMALL>
 hipError_t launch_class(int cls, const SweepArgs& a, uint32_t* counters, uint32_t* list, hipStream_t stream) {
+  const bool rs = a.alloc == nullptr;
   switch (cls) {
-    case 0: return launch_nw<1, SMALL>(a, counters, list, stream);
-    case 1: return launch_nw<2, SMALL>(a, counters, list, stream);
-    case 2: return launch_nw<4, SMALL>(a, counters, list, stream);
-    default: return launch_nw<8, SMALL>(a, counters, list, stream);
+    case 0: return launch_nw<1, SMALL, false>(a, counters, list, stream);
+    case 1: return launch_nw<2, SMALL, false>(a, counters, list, stream);
+    case 2: return rs ? launch_nw<4, SMALL, true>(a, counters, list, stream)
+                      : launch_nw<4, SMALL, false>(a, counters, list, stream);
+    default: return rs ? launch_nw<8, SMALL, true>(a, counters, list, stream)
+                       : launch_nw<8, SMALL, false>(a, counters, list, stream);
   }
 }
 
@@ -847,7 +882,20 @@ hipError_t launch_class(int cls, const SweepArgs& a, uint32_t* counters, uint32_
 size_t sweep_lds_need(int max_n, int max_e) {
   (void)max_e;
   const int nw = 1 << class_of(max_n);
-  return lds_layout(max_n, nw, false).total;
+  return lds_layout(max_n, nw, false, false).total;
+}
+
+size_t sweep_rows_words(const int32_t class_max_n[NUM_CLASSES], const int32_t class_off[NUM_CLASSES + 1],
+                        int32_t max_n, size_t rows_off[NUM_CLASSES + 1]) {
+  size_t w = 0;
+  for (int c = 0; c < NUM_CLASSES; c++) {
+    rows_off[c] = w;
+    if (c >= 2 && class_off[c + 1] > class_off[c]) w += (size_t)ROW_REGIONS * 2 * (size_t)class_max_n[c] * (4u << (c - 2));
+  }
+  rows_off[NUM_CLASSES] = w;  // the one-launch mode's pool
+  const int cls = class_of(max_n);
+  if (cls >= 2) w += (size_t)ROW_REGIONS * 2 * (size_t)max_n * (4u << (cls - 2));
+  return w;
 }
 
 size_t sweep_gres_words(const int32_t class_max_n[NUM_CLASSES], const int32_t class_off[NUM_CLASSES + 1],
@@ -875,11 +923,13 @@ hipError_t launch_sweep(const SweepArgs& a, hipStream_t stream, const SweepStrea
       ac.list_len = a.class_off[c + 1] - a.class_off[c];
       ac.max_n = a.class_max_n[c];
       ac.gres = a.gres + a.gres_off[c];
+      ac.grows = a.grows ? a.grows + a.rows_off[c] : nullptr;
     } else {
       // one launch over all DAGs, sized by the largest, with the shared pool
       if (c != class_of(a.max_n)) continue;
       ac.dag_list = nullptr;
       ac.list_len = a.D;
+      ac.grows = a.grows ? a.grows + a.rows_off[NUM_CLASSES] : nullptr;
     }
     if (ac.list_len <= 0) continue;
     hipStream_t sc = stream;

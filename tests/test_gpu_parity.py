@@ -283,16 +283,19 @@ def mixed_size_batch():
     return W.from_dags(dags)
 
 
-@pytest.mark.parametrize("classes,streams,persistent", [(1, 1, 0), (1, 0, 0), (0, 1, 0), (1, 1, 1), (0, 0, 1)])
-def test_mixed_size_classes(torch_dev, classes, streams, persistent):
+@pytest.mark.parametrize("classes,streams,persistent,seeded",
+                         [(1, 1, 0, 0), (1, 0, 0, 0), (0, 1, 0, 0), (1, 1, 1, 0), (0, 0, 1, 0),
+                          (1, 1, 0, 1), (0, 1, 0, 1), (1, 0, 1, 1)])
+def test_mixed_size_classes(torch_dev, classes, streams, persistent, seeded):
+    # seeded: DAGs above 128 nodes draw their candidate bytes where they use them
     batch = mixed_size_batch()
     sizes = np.diff(batch.node_off)
     assert sizes.max() > 256 and (sizes <= 64).any() and ((sizes > 64) & (sizes <= 128)).any()
     K, M = 70, 256
     alloc = W.alloc_bytes(batch, M, K, seed=5)
     say("mixed size classes:", batch.num_dags, "DAGs, size_classes", classes, "class_streams", streams,
-        "persistent", persistent)
-    got = gpu_eval(torch_dev, batch, M, K, alloc,
+        "persistent", persistent, "seeded", seeded)
+    got = gpu_eval(torch_dev, batch, M, K, alloc, seed=5 if seeded else None,
                    tuning={"size_classes": classes, "class_streams": streams, "persistent": persistent})
     check_against_oracle(batch, M, K, alloc, got)
 
