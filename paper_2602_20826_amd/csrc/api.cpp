@@ -441,7 +441,8 @@ dagbound_status dagbound_create_batch(int32_t num_dags, const int64_t* node_off,
   }
   if (e == hipSuccess) e = hipMemsetAsync(b->err, 0xFF, sizeof(unsigned long long), st);
   if (e == hipSuccess) e = hipMemsetAsync(b->err + 1, 0, sizeof(unsigned long long), st);
-  if (e == hipSuccess) e = launch_prep(b->t, in, num_dags, num_cus, (int32_t)max_n, b->err, st);
+  if (e == hipSuccess)
+    e = launch_prep(b->t, in, num_dags, num_cus, (int32_t)max_n, b->order, b->class_off, b->err, st);
   unsigned long long errw[2] = {~0ull, 0};
   if (e == hipSuccess) e = hipMemcpyAsync(errw, b->err, sizeof errw, hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);

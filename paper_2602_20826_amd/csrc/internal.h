@@ -38,8 +38,11 @@ enum : uint32_t { PREP_E_CYCLE = 2, PREP_E_RANGE = 3, PREP_E_DUP = 4, PREP_E_OVE
                   PREP_E_INTERNAL = 9 };
 
 // err[0]: first failing DAG and code; err[1]: largest load of the batch.
+// With `order` (DAG ids grouped by size class, class c at class_off[c]),
+// one launch per class; without, one launch sized for max_n.
 hipError_t launch_prep(const Tables& t, const PrepInputs& in, int32_t D, int32_t M, int32_t max_n,
-                       unsigned long long* err, hipStream_t stream);
+                       const int32_t* order, const int32_t class_off[5], unsigned long long* err,
+                       hipStream_t stream);
 
 // Slots of the per-lane table of segmented residuals in the first
 // evaluation pass; a tile that needs more goes to the global-memory pass.

@@ -57,7 +57,7 @@ __host__ __device__ constexpr size_t prep_lds_bytes(int NW) {
 }
 
 template <int NW>
-__global__ __launch_bounds__(64) void k_prep(Tables t, PrepInputs in, int32_t M,
+__global__ __launch_bounds__(64) void k_prep(Tables t, PrepInputs in, int32_t M, const int32_t* list,
                                             unsigned long long* err) {
   constexpr int NMAX = NW * 64;
   extern __shared__ __align__(16) unsigned char smem[];
@@ -78,7 +78,7 @@ __global__ __launch_bounds__(64) void k_prep(Tables t, PrepInputs in, int32_t M,
   uint16_t* s_theta = s_perm + NMAX;                 // join nodes in Theta order
   uint8_t* s_state = (uint8_t*)(s_theta + NMAX);     // closure state: 0 open, 1 done, 2 new
 
-  const int d = blockIdx.x;
+  const int d = list ? list[blockIdx.x] : (int)blockIdx.x;
   const int lane = threadIdx.x;
   const int64_t n0 = t.node_off[d];
   const int N = (int)(t.node_off[d + 1] - n0);
@@ -374,26 +374,43 @@ __global__ __launch_bounds__(64) void k_prep(Tables t, PrepInputs in, int32_t M,
 }
 
 template <int NW>
-hipError_t launch_prep_nw(const Tables& t, const PrepInputs& in, int32_t D, int32_t M,
+hipError_t launch_prep_nw(const Tables& t, const PrepInputs& in, int32_t count, int32_t M, const int32_t* list,
                           unsigned long long* err, hipStream_t stream) {
+  if (count <= 0) return hipSuccess;
   const size_t lds = prep_lds_bytes(NW);
   hipError_t e = hipFuncSetAttribute((const void*)k_prep<NW>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_prep<NW>, dim3(D), dim3(64), lds, stream, t, in, M, err);
+  hipLaunchKernelGGL(k_prep<NW>, dim3(count), dim3(64), lds, stream, t, in, M, list, err);
   return hipGetLastError();
 }
 
 }  // namespace
 
 hipError_t launch_prep(const Tables& t, const PrepInputs& in, int32_t D, int32_t M, int32_t max_n,
+                       const int32_t* order, const int32_t class_off[NUM_CLASSES + 1],
                        unsigned long long* err, hipStream_t stream) {
   if (D <= 0) return hipSuccess;
-  if (max_n <= 64) return launch_prep_nw<1>(t, in, D, M, err, stream);
-  if (max_n <= 128) return launch_prep_nw<2>(t, in, D, M, err, stream);
-  if (max_n <= 256) return launch_prep_nw<4>(t, in, D, M, err, stream);
-  if (max_n <= 512) return launch_prep_nw<8>(t, in, D, M, err, stream);
-  return hipErrorInvalidValue;
+  if (max_n > 512) return hipErrorInvalidValue;
+  if (!order) {  // one launch sized for the largest DAG
+    switch (class_of(max_n)) {
+      case 0: return launch_prep_nw<1>(t, in, D, M, nullptr, err, stream);
+      case 1: return launch_prep_nw<2>(t, in, D, M, nullptr, err, stream);
+      case 2: return launch_prep_nw<4>(t, in, D, M, nullptr, err, stream);
+      default: return launch_prep_nw<8>(t, in, D, M, nullptr, err, stream);
+    }
+  }
+  // DAGs above 128 nodes (whose bitsets are large) get a launch per size
+  // class, largest first; the rest share one launch sized for 128 nodes
+  hipError_t e = launch_prep_nw<8>(t, in, class_off[4] - class_off[3], M, order + class_off[3], err, stream);
+  if (e == hipSuccess)
+    e = launch_prep_nw<4>(t, in, class_off[3] - class_off[2], M, order + class_off[2], err, stream);
+  if (e == hipSuccess) {
+    const int32_t n = class_off[2] - class_off[0];
+    e = class_off[2] > class_off[1] ? launch_prep_nw<2>(t, in, n, M, order, err, stream)
+                                    : launch_prep_nw<1>(t, in, n, M, order, err, stream);
+  }
+  return e;
 }
 
 }  // namespace dagbound
