@@ -56,6 +56,12 @@ __host__ __device__ constexpr size_t prep_lds_bytes(int NW) {
          + (size_t)NW * 64;             // closure state bytes
 }
 
+// Word w of node v's bitset row: rows of NW words with the word index XOR-ed
+// by v's low bits, so lanes reading the same word of consecutive rows hit
+// different LDS banks.
+template <int NW>
+__device__ inline int rw(int v, int w) { return v * NW + (w ^ (v & (NW - 1))); }
+
 template <int NW>
 __global__ __launch_bounds__(64) void k_prep(Tables t, PrepInputs in, int32_t M, const int32_t* list,
                                             unsigned long long* err) {
@@ -95,15 +101,19 @@ __global__ __launch_bounds__(64) void k_prep(Tables t, PrepInputs in, int32_t M,
 
   // Task model (Section 2.1): loads and parallelism.
   uint32_t wmax = 0;
+  unsigned long long lsum = 0;  // summed per lane, then over the wave
   for (int v = lane; v < N; v += WAVE) {
     int64_t w = in.wcet[n0 + v];
     int32_t p = in.par[n0 + v];
     if (w < 1 || w > 0x7fffffffLL || p < 1) { atomicCAS(&s_misc[0], 0u, (uint32_t)PREP_E_RANGE); w = 1; p = 1; }
     s_wcet[v] = (uint32_t)w;
     s_par[v] = (uint32_t)p;
-    atomicAdd(s_sum, (unsigned long long)w);
+    lsum += (unsigned long long)w;
     wmax = max(wmax, (uint32_t)w);
   }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) lsum += __shfl_xor(lsum, o);
+  if (lane == 0) *s_sum = lsum;
   wmax = wave_max_u32(wmax);
   if (lane == 0 && N > 0) atomicMax(&err[1], (unsigned long long)wmax);
   // Edges: range, self-loop, duplicates (an LDS bitset of predecessors).
@@ -112,7 +122,7 @@ __global__ __launch_bounds__(64) void k_prep(Tables t, PrepInputs in, int32_t M,
     if (u < 0 || u >= N || v < 0 || v >= N) { atomicCAS(&s_misc[0], 0u, (uint32_t)PREP_E_RANGE); continue; }
     if (u == v) { atomicCAS(&s_misc[0], 0u, (uint32_t)PREP_E_CYCLE); continue; }
     uint64_t bit = 1ull << (u & 63);
-    uint64_t old = atomicOr((unsigned long long*)&s_pred[v * NW + (u >> 6)], (unsigned long long)bit);
+    uint64_t old = atomicOr((unsigned long long*)&s_pred[rw<NW>(v, u >> 6)], (unsigned long long)bit);
     if (old & bit) { atomicCAS(&s_misc[0], 0u, (uint32_t)PREP_E_DUP); continue; }
     atomicAdd(&s_indeg[v], 1u);
     atomicAdd(&s_cursor[u], 1u);
@@ -134,23 +144,23 @@ __global__ __launch_bounds__(64) void k_prep(Tables t, PrepInputs in, int32_t M,
       if (s_state[v]) continue;
       bool ready = true;
 #pragma unroll
-      for (int w = 0; w < NW; w++) ready = ready && !(s_pred[v * NW + w] & ~s_done[w]);
+      for (int w = 0; w < NW; w++) ready = ready && !(s_pred[rw<NW>(v, w)] & ~s_done[w]);
       if (!ready) continue;
       uint64_t acc[NW];
 #pragma unroll
-      for (int w = 0; w < NW; w++) acc[w] = s_pred[v * NW + w];
+      for (int w = 0; w < NW; w++) acc[w] = s_pred[rw<NW>(v, w)];
 #pragma unroll
       for (int w = 0; w < NW; w++) {
-        uint64_t b = s_pred[v * NW + w];
+        uint64_t b = s_pred[rw<NW>(v, w)];
         while (b) {
           int u = w * 64 + __builtin_ctzll(b);
           b &= b - 1;
 #pragma unroll
-          for (int x = 0; x < NW; x++) acc[x] |= s_anc[u * NW + x];
+          for (int x = 0; x < NW; x++) acc[x] |= s_anc[rw<NW>(u, x)];
         }
       }
 #pragma unroll
-      for (int w = 0; w < NW; w++) s_anc[v * NW + w] = acc[w];
+      for (int w = 0; w < NW; w++) s_anc[rw<NW>(v, w)] = acc[w];
       s_state[v] = 2;
     }
     __syncthreads();
@@ -176,12 +186,24 @@ __global__ __launch_bounds__(64) void k_prep(Tables t, PrepInputs in, int32_t M,
   }
 
   // Eq. 2: W^anc(v) = C_hat_v + sum of C_hat over ance(v).
+  // Four ancestors per step, so that their loads are in flight together.
   for (int v = lane; v < N; v += WAVE) {
     int64_t sum = s_wcet[v];
 #pragma unroll
     for (int w = 0; w < NW; w++) {
-      uint64_t b = s_anc[v * NW + w];
-      while (b) { sum += s_wcet[w * 64 + __builtin_ctzll(b)]; b &= b - 1; }
+      uint64_t b = s_anc[rw<NW>(v, w)];
+      while (b) {
+        uint32_t x[4];
+#pragma unroll
+        for (int t = 0; t < 4; t++) {
+          x[t] = 0;
+          if (b) {
+            x[t] = s_wcet[w * 64 + __builtin_ctzll(b)];
+            b &= b - 1;
+          }
+        }
+        sum += (int64_t)x[0] + x[1] + x[2] + x[3];
+      }
     }
     s_wanc[v] = sum;
   }
@@ -208,13 +230,50 @@ __global__ __launch_bounds__(64) void k_prep(Tables t, PrepInputs in, int32_t M,
   // Eq. 3: B_k = ance(theta_k) minus earlier blocks, i.e. v lands in the
   // first block (in Theta order) whose join node has v as an ancestor; the
   // rest form the residual block (index nth).
-  for (int v = lane; v < N; v += WAVE) {
-    int b = nth;
-    for (int k = 0; k < nth; k++) {
-      const int th = s_theta[k];
-      if ((s_anc[th * NW + (v >> 6)] >> (v & 63)) & 1) { b = k; break; }
+  // The join nodes are walked in Theta order (wave-uniform); each lane
+  // assigns its nodes (v = lane, lane + 64, ...) to the first join node whose
+  // ancestor row holds them, and the walk ends once every node is assigned.
+  {
+    int blk[NW];
+    uint64_t open[NW];
+#pragma unroll
+    for (int j = 0; j < NW; j++) {
+      blk[j] = nth;
+      open[j] = __ballot(j * 64 + lane < N);
     }
-    s_block[v] = b;
+    // Theta ids 64 at a time in registers; the next join node's row is
+    // read one step ahead.
+    uint32_t chunk = lane < nth ? s_theta[lane] : 0u;
+    uint64_t row[NW];
+    if (nth > 0) {
+      const int th0 = __builtin_amdgcn_readlane((int)chunk, 0);
+#pragma unroll
+      for (int j = 0; j < NW; j++) row[j] = s_anc[rw<NW>(th0, j)];
+    }
+    for (int k = 0; k < nth; k++) {
+      bool any = false;
+#pragma unroll
+      for (int j = 0; j < NW; j++) any = any || open[j] != 0;
+      if (!any) break;
+      uint64_t cur[NW];
+#pragma unroll
+      for (int j = 0; j < NW; j++) cur[j] = row[j];
+      if (k + 1 < nth) {
+        if (((k + 1) & 63) == 0) chunk = k + 1 + lane < nth ? s_theta[k + 1 + lane] : 0u;
+        const int thn = __builtin_amdgcn_readlane((int)chunk, (k + 1) & 63);
+#pragma unroll
+        for (int j = 0; j < NW; j++) row[j] = s_anc[rw<NW>(thn, j)];
+      }
+#pragma unroll
+      for (int j = 0; j < NW; j++) {
+        const bool hit = ((open[j] >> lane) & 1) && ((cur[j] >> lane) & 1);
+        if (hit) blk[j] = k;
+        open[j] &= ~__ballot(hit);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < NW; j++)
+      if (j * 64 + lane < N) s_block[j * 64 + lane] = blk[j];
   }
   __syncthreads();
   // In-block parent: a node has at most one predecessor in its own block, so
@@ -224,7 +283,7 @@ __global__ __launch_bounds__(64) void k_prep(Tables t, PrepInputs in, int32_t M,
     int parent = -1, cnt = 0;
 #pragma unroll
     for (int w = 0; w < NW; w++) {
-      uint64_t b = s_pred[v * NW + w];
+      uint64_t b = s_pred[rw<NW>(v, w)];
       while (b) {
         int u = w * 64 + __builtin_ctzll(b);
         b &= b - 1;
@@ -250,7 +309,7 @@ __global__ __launch_bounds__(64) void k_prep(Tables t, PrepInputs in, int32_t M,
   int blk[NW], psig[NW];
   uint32_t mmax[NW];
   bool grouped[NW];
-  uint64_t G[NW];
+  uint8_t* s_gflag = s_state;  // grouped flag by sigma rank (the closure state is dead here)
 #pragma unroll
   for (int k = 0; k < NW; k++) {
     const int s = k * 64 + lane;
@@ -263,9 +322,10 @@ __global__ __launch_bounds__(64) void k_prep(Tables t, PrepInputs in, int32_t M,
       blk[k] = s_block[v];
       psig[k] = s_parent[v] < 0 ? -1 : (int)s_sig[s_parent[v]];
       mmax[k] = min(s_par[v], s_wcet[v]);
+      s_gflag[s] = 0;
     }
-    G[k] = 0;
   }
+  __syncthreads();
   uint16_t* gl = t.gl + n0;
   int gpos = 0, ng = 0;
   for (;;) {
@@ -280,13 +340,7 @@ __global__ __launch_bounds__(64) void k_prep(Tables t, PrepInputs in, int32_t M,
     int nh = 0;
 #pragma unroll
     for (int k = 0; k < NW; k++) {
-      bool pg = psig[k] < 0;
-      if (!pg) {
-        uint64_t gw = 0;
-#pragma unroll
-        for (int w = 0; w < NW; w++) gw |= (psig[k] >> 6) == w ? G[w] : 0ull;
-        pg = (gw >> (psig[k] & 63)) & 1;
-      }
+      const bool pg = psig[k] < 0 || s_gflag[psig[k]] != 0;
       head[k] = !grouped[k] && blk[k] == bmin && pg;
       hb[k] = __ballot(head[k]);
       nh += __popcll(hb[k]);
@@ -330,12 +384,13 @@ __global__ __launch_bounds__(64) void k_prep(Tables t, PrepInputs in, int32_t M,
         const int pos = gpos + base + __popcll(sb[k] & lanes_below(lane));
         gl[pos] = (uint16_t)(s | (pos == gpos + cnt - 1 ? 0x8000 : 0));
         grouped[k] = true;
+        s_gflag[s] = 1;
       }
       base += __popcll(sb[k]);
-      G[k] |= sb[k];
     }
     gpos += cnt;
     ng++;
+    __syncthreads();
   }
   if (lane == 0) t.ngroups[d] = ng;
 
