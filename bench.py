@@ -187,7 +187,7 @@ def cpu_baseline(batch, M, K, seed, gpu_bounds, max_seconds: float = 30.0):
     }
 
 
-def search_block(torch, db, W, n_train: int, n_test: int) -> dict:
+def search_block(torch, db, W, n_train: int, n_test: int, epochs: int) -> dict:
     """Best-bound gap to exhaustive search on held-out learned-proposal DAGs
     (4,096 seeded candidates each): the surrogate's top-16 plus the paper's
     rule, the paper's rule alone, and 16 plain random candidates, with the
@@ -203,7 +203,6 @@ def search_block(torch, db, W, n_train: int, n_test: int) -> dict:
     t0 = time.perf_counter()
     shards = P.label_shards(torch, train, M, 256, seed=11, per_shard=2000)
     model = db.Model(3)
-    epochs = 20
     hist = P.train(model, shards, epochs, lr=2e-3, lr_end=2e-4)
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t0
@@ -231,7 +230,8 @@ def main() -> int:
                     "explicit bytes (same values)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-search", action="store_true", help="skip the learned-proposal comparison")
-    ap.add_argument("--search-train", type=int, default=5000, help="training DAGs (x 256 labelled candidates)")
+    ap.add_argument("--search-train", type=int, default=20000, help="training DAGs (x 256 labelled candidates)")
+    ap.add_argument("--search-epochs", type=int, default=60, help="training epochs over those DAGs")
     ap.add_argument("--search-test", type=int, default=5000, help="held-out DAGs (x 4096 seeded candidates)")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="one copy of known size plus one evaluation launch, for counter passes")
@@ -349,7 +349,7 @@ def main() -> int:
     }
     if not args.no_search:
         print("[bench] learned proposal: label, train, compare searches", file=sys.stderr, flush=True)
-        out["best_gap"] = search_block(torch, db, W, args.search_train, args.search_test)
+        out["best_gap"] = search_block(torch, db, W, args.search_train, args.search_test, args.search_epochs)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         torch.cuda.synchronize()
