@@ -171,7 +171,7 @@ struct dagbound_batch {
   size_t block_size = 0;
   Tables t{};
   unsigned long long* best = nullptr;  // [D] packed per-DAG minimum
-  unsigned long long* err = nullptr;   // [2] first failing DAG, largest load
+  unsigned long long* err = nullptr;   // [2] first failing DAG, any load >= 2^20
   uint32_t* gres = nullptr;            // residual tables of the global evaluation pass
   bool small_loads = false;            // every load < 2^20
   // DAG ids grouped by size class (the evaluation launches one kernel per class)
@@ -452,7 +452,7 @@ dagbound_status dagbound_create_batch(int32_t num_dags, const int64_t* node_off,
     return hip_fail(e, "preprocessing");
   }
   const unsigned long long err = errw[0];
-  b->small_loads = errw[1] < (1ull << 20);
+  b->small_loads = errw[1] == 0;
   if (err != ~0ull) {
     const long long d = (long long)(err >> 8);
     const unsigned code = (unsigned)(err & 0xFF);

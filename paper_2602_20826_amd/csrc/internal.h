@@ -37,7 +37,7 @@ struct PrepInputs {
 enum : uint32_t { PREP_E_CYCLE = 2, PREP_E_RANGE = 3, PREP_E_DUP = 4, PREP_E_OVERFLOW = 8,
                   PREP_E_INTERNAL = 9 };
 
-// err[0]: first failing DAG and code; err[1]: largest load of the batch.
+// err[0]: first failing DAG and code; err[1]: nonzero if some load is 2^20 or more.
 // With `order` (DAG ids grouped by size class, class c at class_off[c]),
 // one launch per class; without, one launch sized for max_n.
 hipError_t launch_prep(const Tables& t, const PrepInputs& in, int32_t D, int32_t M, int32_t max_n,

@@ -91,6 +91,22 @@ __global__ __launch_bounds__(64) void k_prep(Tables t, PrepInputs in, int32_t M,
   const int64_t e0 = t.edge_off[d];
   const int64_t E = t.edge_off[d + 1] - e0;
 
+  // the first loads of node and edge data are issued before the LDS is
+  // cleared, so their latency overlaps it
+  constexpr int EPRE = 4;
+  int64_t w_first = 1;
+  int32_t p_first = 1;
+  if (lane < N) {
+    w_first = in.wcet[n0 + lane];
+    p_first = in.par[n0 + lane];
+  }
+  int32_t eu[EPRE], ev[EPRE];
+#pragma unroll
+  for (int q = 0; q < EPRE; q++) {
+    const int64_t k = lane + (int64_t)q * WAVE;
+    eu[q] = k < E ? in.src[e0 + k] : 0;
+    ev[q] = k < E ? in.dst[e0 + k] : 0;
+  }
   if (lane == 0) { s_misc[0] = 0; s_misc[1] = 0; *s_sum = 0; }
   for (int i = lane; i < N * NW; i += WAVE) { s_pred[i] = 0; s_anc[i] = 0; }
   for (int w = lane; w < NW; w += WAVE) s_done[w] = 0;
@@ -103,8 +119,8 @@ __global__ __launch_bounds__(64) void k_prep(Tables t, PrepInputs in, int32_t M,
   uint32_t wmax = 0;
   unsigned long long lsum = 0;  // summed per lane, then over the wave
   for (int v = lane; v < N; v += WAVE) {
-    int64_t w = in.wcet[n0 + v];
-    int32_t p = in.par[n0 + v];
+    int64_t w = v == lane ? w_first : in.wcet[n0 + v];
+    int32_t p = v == lane ? p_first : in.par[n0 + v];
     if (w < 1 || w > 0x7fffffffLL || p < 1) { atomicCAS(&s_misc[0], 0u, (uint32_t)PREP_E_RANGE); w = 1; p = 1; }
     s_wcet[v] = (uint32_t)w;
     s_par[v] = (uint32_t)p;
@@ -115,17 +131,34 @@ __global__ __launch_bounds__(64) void k_prep(Tables t, PrepInputs in, int32_t M,
   for (int o = 32; o > 0; o >>= 1) lsum += __shfl_xor(lsum, o);
   if (lane == 0) *s_sum = lsum;
   wmax = wave_max_u32(wmax);
-  if (lane == 0 && N > 0) atomicMax(&err[1], (unsigned long long)wmax);
+  // err[1] flags a load of 2^20 or more somewhere in the batch (set rarely,
+  // so DAGs do not queue on one global address)
+  if (lane == 0 && wmax >= (1u << 20)) atomicOr(&err[1], 1ull);
   // Edges: range, self-loop, duplicates (an LDS bitset of predecessors).
-  for (int64_t k = lane; k < E; k += WAVE) {
-    int32_t u = in.src[e0 + k], v = in.dst[e0 + k];
-    if (u < 0 || u >= N || v < 0 || v >= N) { atomicCAS(&s_misc[0], 0u, (uint32_t)PREP_E_RANGE); continue; }
-    if (u == v) { atomicCAS(&s_misc[0], 0u, (uint32_t)PREP_E_CYCLE); continue; }
-    uint64_t bit = 1ull << (u & 63);
-    uint64_t old = atomicOr((unsigned long long*)&s_pred[rw<NW>(v, u >> 6)], (unsigned long long)bit);
-    if (old & bit) { atomicCAS(&s_misc[0], 0u, (uint32_t)PREP_E_DUP); continue; }
-    atomicAdd(&s_indeg[v], 1u);
-    atomicAdd(&s_cursor[u], 1u);
+  // The first EPRE rounds come from the loads issued above; later rounds
+  // load EPRE at a time.
+  for (int64_t kb = 0; kb < E; kb += (int64_t)EPRE * WAVE) {
+    if (kb > 0) {
+#pragma unroll
+      for (int q = 0; q < EPRE; q++) {
+        const int64_t k = kb + lane + (int64_t)q * WAVE;
+        eu[q] = k < E ? in.src[e0 + k] : 0;
+        ev[q] = k < E ? in.dst[e0 + k] : 0;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < EPRE; q++) {
+      const int64_t k = kb + lane + (int64_t)q * WAVE;
+      if (k >= E) continue;
+      const int32_t u = eu[q], v = ev[q];
+      if (u < 0 || u >= N || v < 0 || v >= N) { atomicCAS(&s_misc[0], 0u, (uint32_t)PREP_E_RANGE); continue; }
+      if (u == v) { atomicCAS(&s_misc[0], 0u, (uint32_t)PREP_E_CYCLE); continue; }
+      uint64_t bit = 1ull << (u & 63);
+      uint64_t old = atomicOr((unsigned long long*)&s_pred[rw<NW>(v, u >> 6)], (unsigned long long)bit);
+      if (old & bit) { atomicCAS(&s_misc[0], 0u, (uint32_t)PREP_E_DUP); continue; }
+      atomicAdd(&s_indeg[v], 1u);
+      atomicAdd(&s_cursor[u], 1u);
+    }
   }
   __syncthreads();
   if (s_misc[0] == 0 && *s_sum >= (1ull << 40)) {
