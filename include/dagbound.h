@@ -69,7 +69,7 @@ enum { DAGBOUND_ALLOC_EXPLICIT = 0, DAGBOUND_ALLOC_SEEDED = 1 };
 enum { DAGBOUND_SEARCH_EXHAUSTIVE = 0, DAGBOUND_SEARCH_SURROGATE = 1 };
 
 /* Limits of this build. */
-#define DAGBOUND_MAX_NODES_PER_DAG 512   /* N_d, source and sink included */
+#define DAGBOUND_MAX_NODES_PER_DAG 8000  /* N_d, source and sink included */
 #define DAGBOUND_MAX_CANDIDATES (1 << 22)
 
 /*
@@ -159,7 +159,7 @@ dagbound_status dagbound_eval_bounds(dagbound_batch* batch, int64_t* bounds, int
  *              and candidate 0 plus the top_k best-scored ones are evaluated
  *              exactly.  The result is exact for the candidates evaluated;
  *              ties go to the candidate listed first (0, then by score).
- *   top_k      SURROGATE: 1..min(63, K-1); ignored by EXHAUSTIVE.
+ *   top_k      SURROGATE: 1..min(255, K-1); ignored by EXHAUSTIVE.
  *   model      NULL for EXHAUSTIVE.
  *   best_idx   int32 [D]; best_bound int64 [D] (NULL only when D = 0).  An
  *              empty DAG reports candidate 0 with bound 0.
@@ -193,8 +193,10 @@ dagbound_status dagbound_get_division(dagbound_batch* batch, int32_t d, int64_t*
  *   "eval_path"       0 (default): LDS tables first, as above; 1: global
  *                     tables for every tile.
  *   "size_classes"    1 (default): one launch per DAG size class (up to 64,
- *                     128, 256, 512 nodes); 0: one launch over all DAGs,
- *                     sized for the largest.
+ *                     128, 256, 512 nodes, and larger); 0: one launch over
+ *                     all DAGs, sized for the largest.  DAGs above 512 nodes
+ *                     run one wavefront per (DAG, candidate); "residual_slots",
+ *                     "eval_path" and "persistent" do not apply to them.
  *   "class_streams"   1 (default): the class launches run concurrently on
  *                     side streams of the device (forked from and joined back
  *                     to the caller's stream with events); 0: in turn on the

@@ -132,8 +132,8 @@ struct Carve {
   }
 };
 
-size_t table_bytes(int64_t D, int64_t tn, int64_t te, size_t gres_words) {
-  return 18 * 256 + (size_t)(D + 1) * 8 * 2 + (size_t)tn * 8 + (size_t)D * 8 + 16 +
+size_t table_bytes(int64_t D, int64_t tn, int64_t te, size_t gres_words, bool mrec) {
+  return 19 * 256 + (size_t)(D + 1) * 8 * 2 + (size_t)tn * 8 + (size_t)D * 8 + 24 + (mrec ? (size_t)tn * 8 : 0) +
          (size_t)tn * 4 + (size_t)(tn + D) * 4 + (size_t)D * 4 + (size_t)tn * 2 * 4 +
          (size_t)te * 2 + gres_words * 4 + (size_t)D * 4;
 }
@@ -145,7 +145,7 @@ std::vector<std::array<hipStream_t, NUM_CLASSES>> g_side;
 
 hipError_t side_streams(int device, hipStream_t out[NUM_CLASSES]) {
   std::lock_guard<std::mutex> lk(g_stream_mu);
-  if ((int)g_side.size() <= device) g_side.resize(device + 1, {nullptr, nullptr, nullptr, nullptr});
+  if ((int)g_side.size() <= device) g_side.resize(device + 1, std::array<hipStream_t, NUM_CLASSES>{});
   for (int c = 0; c < NUM_CLASSES; c++) {
     if (!g_side[device][c]) {
       hipError_t e = hipStreamCreateWithFlags(&g_side[device][c], hipStreamNonBlocking);
@@ -171,23 +171,23 @@ struct dagbound_batch {
   size_t block_size = 0;
   Tables t{};
   unsigned long long* best = nullptr;  // [D] packed per-DAG minimum
-  unsigned long long* err = nullptr;   // [2] first failing DAG, any load >= 2^20
+  unsigned long long* err = nullptr;   // [3] first failing DAG, any load >= 2^20, large-DAG work counter
   uint32_t* gres = nullptr;            // residual tables of the global evaluation pass
   bool small_loads = false;            // every load < 2^20
   // DAG ids grouped by size class (the evaluation launches one kernel per class)
   int32_t* order = nullptr;
   std::vector<int32_t> order_host;
-  int32_t class_off[NUM_CLASSES + 1] = {0, 0, 0, 0, 0};
-  int32_t class_max_n[NUM_CLASSES] = {0, 0, 0, 0};
+  int32_t class_off[NUM_CLASSES + 1] = {};
+  int32_t class_max_n[NUM_CLASSES] = {};
   bool size_classes = true;
   bool class_streams = true;           // class launches on side streams
   bool persistent = false;             // first pass as a persistent kernel
   bool autotune_pending = false;       // time the launch plans on the next evaluation
   float plan_ms[4] = {0, 0, 0, 0};     // last autotune: (persistent, class_streams) = (p, s) at 2p + s
-  size_t gres_off[NUM_CLASSES] = {0, 0, 0, 0};
-  uint64_t* grows = nullptr;           // row regions for DAGs above 128 nodes
-  size_t rows_off[NUM_CLASSES + 1] = {0, 0, 0, 0, 0};
-  hipEvent_t ev[NUM_CLASSES + 1] = {nullptr, nullptr, nullptr, nullptr, nullptr};  // fork, joins
+  size_t gres_off[NUM_CLASSES] = {};
+  uint64_t* grows = nullptr;           // row regions for DAGs of 129-512 nodes
+  size_t rows_off[NUM_CLASSES + 1] = {};
+  hipEvent_t ev[NUM_CLASSES + 1] = {};  // fork, joins
   // per-allocation-set scratch: tiles handed to the global pass
   void* ovf_block = nullptr;
   size_t ovf_block_size = 0;
@@ -369,26 +369,24 @@ dagbound_status dagbound_create_batch(int32_t num_dags, const int64_t* node_off,
   b->max_e = (int32_t)std::min<int64_t>(max_e, INT32_MAX);
   b->node_off = no;
   b->edge_off = eo;
+  int32_t large_max_e = 0;  // most edges of a DAG above 512 nodes
   {
     std::vector<int32_t> cnt(NUM_CLASSES + 1, 0);
     for (int64_t d = 0; d < D; d++) {
       const int cls = class_of((int)(no[d + 1] - no[d]));
       cnt[cls + 1]++;
       b->class_max_n[cls] = std::max<int32_t>(b->class_max_n[cls], (int32_t)(no[d + 1] - no[d]));
+      if (cls == LARGE_CLASS) large_max_e = std::max<int32_t>(large_max_e, (int32_t)(eo[d + 1] - eo[d]));
     }
     for (int c = 0; c < NUM_CLASSES; c++) cnt[c + 1] += cnt[c];
     for (int c = 0; c <= NUM_CLASSES; c++) b->class_off[c] = cnt[c];
     b->order_host.resize((size_t)D);
     for (int64_t d = 0; d < D; d++) b->order_host[(size_t)cnt[class_of((int)(no[d + 1] - no[d]))]++] = (int32_t)d;
-    size_t off = (size_t)GLOBAL_PASS_GRID * (size_t)max_n * 64;  // the one-launch pool comes first
-    for (int c = 0; c < NUM_CLASSES; c++) {
-      b->gres_off[c] = off;
-      if (b->class_off[c + 1] > b->class_off[c]) off += (size_t)GLOBAL_PASS_GRID * (size_t)b->class_max_n[c] * 64;
-    }
   }
-  const size_t gres_words = sweep_gres_words(b->class_max_n, b->class_off, (int32_t)max_n);
+  const int32_t n_large = b->class_off[LARGE_CLASS + 1] - b->class_off[LARGE_CLASS];
+  const size_t gres_words = sweep_gres_words(b->class_max_n, b->class_off, (int32_t)max_n, b->gres_off);
   const size_t rows_words = sweep_rows_words(b->class_max_n, b->class_off, (int32_t)max_n, b->rows_off);
-  b->block_size = table_bytes(D, tn, te, gres_words) + rows_words * 8 + 256;
+  b->block_size = table_bytes(D, tn, te, gres_words, n_large > 0) + rows_words * 8 + 256;
   hipError_t e = dev_alloc(&b->block, &b->block_size, device);
   if (e != hipSuccess) {
     delete b;
@@ -401,7 +399,7 @@ dagbound_status dagbound_create_batch(int32_t num_dags, const int64_t* node_off,
   b->t.edge_off = d_eo;
   b->t.wanc = cv.take<int64_t>(tn);
   b->best = cv.take<unsigned long long>(D);
-  b->err = cv.take<unsigned long long>(2);
+  b->err = cv.take<unsigned long long>(3);
   b->gres = cv.take<uint32_t>(gres_words);
   if (rows_words) b->grows = cv.take<uint64_t>(rows_words);
   b->t.wc = cv.take<uint32_t>(tn);
@@ -413,6 +411,7 @@ dagbound_status dagbound_create_batch(int32_t num_dags, const int64_t* node_off,
   b->t.inv = cv.take<uint16_t>(tn);
   b->t.succ = cv.take<uint16_t>(te);
   b->order = cv.take<int32_t>(D);
+  if (n_large > 0) b->t.mrec = cv.take<uint2>(tn);
 
   // Inputs: device pointers are read in place; host arrays go through a
   // staging block that is released when this call returns.
@@ -440,13 +439,24 @@ dagbound_status dagbound_create_batch(int32_t num_dags, const int64_t* node_off,
     }
   }
   if (e == hipSuccess) e = hipMemsetAsync(b->err, 0xFF, sizeof(unsigned long long), st);
-  if (e == hipSuccess) e = hipMemsetAsync(b->err + 1, 0, sizeof(unsigned long long), st);
+  if (e == hipSuccess) e = hipMemsetAsync(b->err + 1, 0, 2 * sizeof(unsigned long long), st);
+  // global scratch of the large-DAG preprocessing, released with the staging
+  void* lscratch = nullptr;
+  size_t lscratch_size = 0;
+  if (e == hipSuccess && n_large > 0) {
+    lscratch_size = (size_t)std::min(n_large, PREP_LARGE_GRID) *
+                    prep_large_scratch_bytes(b->class_max_n[LARGE_CLASS], large_max_e);
+    e = dev_alloc(&lscratch, &lscratch_size, device);
+    if (e != hipSuccess) lscratch = nullptr;
+  }
   if (e == hipSuccess)
-    e = launch_prep(b->t, in, num_dags, num_cus, (int32_t)max_n, b->order, b->class_off, b->err, st);
+    e = launch_prep(b->t, in, num_dags, num_cus, (int32_t)max_n, b->order, b->class_off, b->err, lscratch,
+                    b->class_max_n[LARGE_CLASS], large_max_e, st);
   unsigned long long errw[2] = {~0ull, 0};
   if (e == hipSuccess) e = hipMemcpyAsync(errw, b->err, sizeof errw, hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   dev_release(stage, stage_size, device);
+  dev_release(lscratch, lscratch_size, device);
   if (e != hipSuccess) {
     batch_free(b);
     return hip_fail(e, "preprocessing");
@@ -596,8 +606,8 @@ dagbound_status dagbound_best_allocation(dagbound_batch* b, uint32_t search, int
     if (!model) return fail(DAGBOUND_E_ARG, "surrogate search needs a model");
     if (!b->has_alloc) return fail(DAGBOUND_E_STATE, "set_allocations has not been called");
     if (b->mode != DAGBOUND_ALLOC_SEEDED) return fail(DAGBOUND_E_ARG, "surrogate search needs seeded candidates");
-    if (top_k < 1 || top_k > 63 || top_k >= b->K)
-      return fail(DAGBOUND_E_ARG, "top_k = %d outside [1, min(63, K-1)]", top_k);
+    if (top_k < 1 || top_k > 255 || top_k >= b->K)
+      return fail(DAGBOUND_E_ARG, "top_k = %d outside [1, min(255, K-1)]", top_k);
     return surrogate_best(b, const_cast<dagbound_model*>(model), top_k, best_idx, best_bound, ptr_kind,
                           (hipStream_t)hip_stream);
   }
@@ -963,7 +973,7 @@ dagbound_status dagbound_model_select(dagbound_model* m, dagbound_batch* b, int3
   g_err.clear();
   if (!m || !b || !cand) return fail(DAGBOUND_E_ARG, "model, batch or cand is NULL");
   if (K < 1 || K > 16384) return fail(DAGBOUND_E_ARG, "K = %d outside [1, 16384]", K);
-  if (top_k < 0 || top_k > 63 || top_k >= K) return fail(DAGBOUND_E_ARG, "top_k = %d outside [0, min(63, K-1)]", top_k);
+  if (top_k < 0 || top_k > 255 || top_k >= K) return fail(DAGBOUND_E_ARG, "top_k = %d outside [0, min(255, K-1)]", top_k);
   if (nodes < 1 || nodes > 64) return fail(DAGBOUND_E_ARG, "nodes = %d outside [1, 64]", nodes);
   if (ptr_kind != DAGBOUND_PTR_DEVICE) return fail(DAGBOUND_E_ARG, "model_select takes device pointers");
   if (m->device != b->device) return fail(DAGBOUND_E_ARG, "model and batch live on different devices");

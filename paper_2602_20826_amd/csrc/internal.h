@@ -23,6 +23,8 @@ struct Tables {
   uint16_t* succ;           // [T_E] successor sigma ranks, DAG d at edge_off[d]
   int64_t* wanc;            // [T_N] W^anc by local node id (inspection)
   int32_t* ngroups;         // [D] |Pi|
+  uint2* mrec;              // [T_N] member records in group order, {C_hat, min(p, M) | sigma << 16 |
+                            // last << 31}; written only when the batch holds a DAG above 512 nodes
 };
 
 struct PrepInputs {
@@ -37,12 +39,24 @@ struct PrepInputs {
 enum : uint32_t { PREP_E_CYCLE = 2, PREP_E_RANGE = 3, PREP_E_DUP = 4, PREP_E_OVERFLOW = 8,
                   PREP_E_INTERNAL = 9 };
 
-// err[0]: first failing DAG and code; err[1]: nonzero if some load is 2^20 or more.
+// err[0]: first failing DAG and code; err[1]: nonzero if some load is 2^20
+// or more; err[2]: work counter of the large-DAG preprocessing (zeroed).
 // With `order` (DAG ids grouped by size class, class c at class_off[c]),
-// one launch per class; without, one launch sized for max_n.
+// one launch per class; without, one launch sized for max_n.  DAGs above
+// 512 nodes use `lscratch` (prep_large_scratch_bytes of their largest size).
 hipError_t launch_prep(const Tables& t, const PrepInputs& in, int32_t D, int32_t M, int32_t max_n,
-                       const int32_t* order, const int32_t class_off[5], unsigned long long* err,
-                       hipStream_t stream);
+                       const int32_t* order, const int32_t* class_off, unsigned long long* err,
+                       void* lscratch, int32_t large_max_n, int32_t large_max_e, hipStream_t stream);
+
+// Largest DAG the large-DAG kernels take, and the workgroups of their
+// preprocessing launch (each with its own scratch region).
+constexpr int LARGE_MAX_N = 8000;
+constexpr int PREP_LARGE_GRID = 256;
+size_t prep_large_scratch_bytes(int32_t max_n, int32_t max_e);
+// Preprocessing of `count` DAGs above 512 nodes (ids from `list`, or 0..count-1).
+hipError_t launch_prep_large(const Tables& t, const PrepInputs& in, int32_t count, int32_t M, const int32_t* list,
+                             unsigned long long* err, void* scratch, int32_t max_n, int32_t max_e,
+                             hipStream_t stream);
 
 // Slots of the per-lane table of segmented residuals in the first
 // evaluation pass; a tile that needs more goes to the global-memory pass.
@@ -56,12 +70,19 @@ constexpr int GLOBAL_PASS_GRID = 256;
 constexpr int ROW_REGIONS = 1024;
 enum : int32_t { EVAL_PATH_AUTO = 0, EVAL_PATH_GLOBAL = 1 };
 
-// DAGs are evaluated in size classes (up to 64, 128, 256, 512 nodes), one
-// launch per class, so that a small DAG never pays for a large one's
-// bitsets and LDS.
-constexpr int NUM_CLASSES = 4;
+// DAGs are evaluated in size classes (up to 64, 128, 256, 512 nodes, and
+// larger), one launch per class, so that a small DAG never pays for a large
+// one's bitsets and LDS.  The last class runs one wavefront per (DAG,
+// candidate) with its lanes over nodes.
+constexpr int NUM_CLASSES = 5;
+constexpr int LARGE_CLASS = 4;
 constexpr int COUNTERS_PER_CLASS = 3;
-__host__ __device__ constexpr int class_of(int n) { return n <= 64 ? 0 : n <= 128 ? 1 : n <= 256 ? 2 : 3; }
+__host__ __device__ constexpr int class_of(int n) {
+  return n <= 64 ? 0 : n <= 128 ? 1 : n <= 256 ? 2 : n <= 512 ? 3 : LARGE_CLASS;
+}
+// Residual-load regions of the large-DAG evaluation (one per running
+// wavefront, class_max_n words each).
+constexpr int LARGE_SLOTS = 4096;
 
 struct SweepArgs {
   Tables t;
@@ -80,8 +101,9 @@ struct SweepArgs {
   uint32_t* ovf_list;           // [D * ceil(K/64)] tiles handed to the global pass
   uint32_t* ovf_count;          // [COUNTERS_PER_CLASS * NUM_CLASSES]: per class, tiles listed,
                                 // global tables taken, tiles taken by the persistent pass
-  uint32_t* gres;               // residual tables: class c owns GLOBAL_PASS_GRID tables of
-                                // class_max_n[c] * 64 words from gres + gres_off[c]
+  uint32_t* gres;               // residual tables: class c < LARGE_CLASS owns GLOBAL_PASS_GRID
+                                // tables of class_max_n[c] * 64 words from gres + gres_off[c];
+                                // the large class owns LARGE_SLOTS regions of class_max_n words
   size_t gres_off[NUM_CLASSES]; // host: word offset of each class's tables
   uint64_t* grows;              // row regions (predecessor and successor rows kept in global memory):
                                 // class c owns ROW_REGIONS regions of 2 * class_max_n[c] * NW words
@@ -103,6 +125,11 @@ constexpr int BEST_SHIFT = 22;
 size_t sweep_lds_need(int max_n, int max_e);
 constexpr size_t LDS_LIMIT = 160 * 1024;
 
+// The large-DAG evaluation of one launch (DAGs a.dag_list, or all), on the
+// work counter `counter` (zeroed by k_eval_init).
+hipError_t launch_eval_large(const SweepArgs& a, uint32_t* counter, hipStream_t stream);
+size_t eval_large_lds_bytes(int max_n);
+
 // Side streams for the size classes: each class launch runs on its own
 // stream, forked from and joined back to the caller's stream by events, so
 // that one class's tail overlaps the others' work.
@@ -116,9 +143,10 @@ struct SweepStreams {
 size_t sweep_rows_words(const int32_t class_max_n[NUM_CLASSES], const int32_t class_off[NUM_CLASSES + 1],
                         int32_t max_n, size_t rows_off[NUM_CLASSES + 1]);
 
-// Words of residual tables a batch needs (all classes with DAGs).
+// Words of residual tables a batch needs (the one-launch pool first, then
+// every class with DAGs), and each class's offset.
 size_t sweep_gres_words(const int32_t class_max_n[NUM_CLASSES], const int32_t class_off[NUM_CLASSES + 1],
-                        int32_t max_n);
+                        int32_t max_n, size_t gres_off[NUM_CLASSES]);
 
 // Evaluates every (DAG, candidate) pair; also resets `best` and fills it.
 // With `ss`, the class launches run concurrently on its side streams.

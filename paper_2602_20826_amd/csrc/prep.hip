@@ -415,7 +415,13 @@ __global__ __launch_bounds__(64) void k_prep(Tables t, PrepInputs in, int32_t M,
       if (sel[k]) {
         const int s = k * 64 + lane;
         const int pos = gpos + base + __popcll(sb[k] & lanes_below(lane));
-        gl[pos] = (uint16_t)(s | (pos == gpos + cnt - 1 ? 0x8000 : 0));
+        const uint32_t last = pos == gpos + cnt - 1 ? 0x8000u : 0u;
+        gl[pos] = (uint16_t)(s | last);
+        if (t.mrec) {  // member records, kept when the batch also holds large DAGs
+          const int v = s_perm[s];
+          t.mrec[n0 + pos] =
+              make_uint2(s_wcet[v], min(s_par[v], (uint32_t)M) | ((uint32_t)s << 16) | (last << 16));
+        }
         grouped[k] = true;
         s_gflag[s] = 1;
       }
@@ -476,21 +482,25 @@ hipError_t launch_prep_nw(const Tables& t, const PrepInputs& in, int32_t count, 
 }  // namespace
 
 hipError_t launch_prep(const Tables& t, const PrepInputs& in, int32_t D, int32_t M, int32_t max_n,
-                       const int32_t* order, const int32_t class_off[NUM_CLASSES + 1],
-                       unsigned long long* err, hipStream_t stream) {
+                       const int32_t* order, const int32_t* class_off, unsigned long long* err,
+                       void* lscratch, int32_t large_max_n, int32_t large_max_e, hipStream_t stream) {
   if (D <= 0) return hipSuccess;
-  if (max_n > 512) return hipErrorInvalidValue;
+  if (max_n > LARGE_MAX_N) return hipErrorInvalidValue;
   if (!order) {  // one launch sized for the largest DAG
     switch (class_of(max_n)) {
       case 0: return launch_prep_nw<1>(t, in, D, M, nullptr, err, stream);
       case 1: return launch_prep_nw<2>(t, in, D, M, nullptr, err, stream);
       case 2: return launch_prep_nw<4>(t, in, D, M, nullptr, err, stream);
-      default: return launch_prep_nw<8>(t, in, D, M, nullptr, err, stream);
+      case 3: return launch_prep_nw<8>(t, in, D, M, nullptr, err, stream);
+      default: return hipErrorInvalidValue;  // large DAGs need their class's scratch sizes
     }
   }
   // DAGs above 128 nodes (whose bitsets are large) get a launch per size
   // class, largest first; the rest share one launch sized for 128 nodes
-  hipError_t e = launch_prep_nw<8>(t, in, class_off[4] - class_off[3], M, order + class_off[3], err, stream);
+  hipError_t e = launch_prep_large(t, in, class_off[5] - class_off[4], M, order + class_off[4], err, lscratch,
+                                   large_max_n, large_max_e, stream);
+  if (e == hipSuccess)
+    e = launch_prep_nw<8>(t, in, class_off[4] - class_off[3], M, order + class_off[3], err, stream);
   if (e == hipSuccess)
     e = launch_prep_nw<4>(t, in, class_off[3] - class_off[2], M, order + class_off[2], err, stream);
   if (e == hipSuccess) {

@@ -881,6 +881,7 @@ hipError_t launch_class(int cls, const SweepArgs& a, uint32_t* counters, uint32_
 
 size_t sweep_lds_need(int max_n, int max_e) {
   (void)max_e;
+  if (class_of(max_n) == LARGE_CLASS) return eval_large_lds_bytes(max_n);
   const int nw = 1 << class_of(max_n);
   return lds_layout(max_n, nw, false, false).total;
 }
@@ -890,29 +891,38 @@ size_t sweep_rows_words(const int32_t class_max_n[NUM_CLASSES], const int32_t cl
   size_t w = 0;
   for (int c = 0; c < NUM_CLASSES; c++) {
     rows_off[c] = w;
-    if (c >= 2 && class_off[c + 1] > class_off[c]) w += (size_t)ROW_REGIONS * 2 * (size_t)class_max_n[c] * (4u << (c - 2));
+    if (c >= 2 && c < LARGE_CLASS && class_off[c + 1] > class_off[c])
+      w += (size_t)ROW_REGIONS * 2 * (size_t)class_max_n[c] * (4u << (c - 2));
   }
   rows_off[NUM_CLASSES] = w;  // the one-launch mode's pool
   const int cls = class_of(max_n);
-  if (cls >= 2) w += (size_t)ROW_REGIONS * 2 * (size_t)max_n * (4u << (cls - 2));
+  if (cls >= 2 && cls < LARGE_CLASS) w += (size_t)ROW_REGIONS * 2 * (size_t)max_n * (4u << (cls - 2));
   return w;
 }
 
+// Residual words of one class's launch: GLOBAL_PASS_GRID tables of n * 64
+// words, or LARGE_SLOTS regions of n words for the large class.
+static size_t gres_pool_words(int cls, int32_t n) {
+  return cls == LARGE_CLASS ? (size_t)LARGE_SLOTS * (size_t)n : (size_t)GLOBAL_PASS_GRID * (size_t)n * WAVE;
+}
+
 size_t sweep_gres_words(const int32_t class_max_n[NUM_CLASSES], const int32_t class_off[NUM_CLASSES + 1],
-                        int32_t max_n) {
-  size_t w = (size_t)GLOBAL_PASS_GRID * (size_t)max_n * WAVE;  // one pool for the one-launch mode
-  for (int c = 0; c < NUM_CLASSES; c++)
-    if (class_off[c + 1] > class_off[c]) w += (size_t)GLOBAL_PASS_GRID * (size_t)class_max_n[c] * WAVE;
+                        int32_t max_n, size_t gres_off[NUM_CLASSES]) {
+  size_t w = gres_pool_words(class_of(max_n), max_n);  // one pool for the one-launch mode
+  for (int c = 0; c < NUM_CLASSES; c++) {
+    gres_off[c] = w;
+    if (class_off[c + 1] > class_off[c]) w += gres_pool_words(c, class_max_n[c]);
+  }
   return w;
 }
 
 hipError_t launch_sweep(const SweepArgs& a, hipStream_t stream, const SweepStreams* ss) {
   if (a.D <= 0) return hipSuccess;
-  if (a.max_n > 512) return hipErrorInvalidValue;
+  if (a.max_n > LARGE_MAX_N) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_eval_init, dim3((a.D + 255) / 256), dim3(256), 0, stream, a.best, a.D, a.ovf_count);
   hipError_t e = hipGetLastError();
   const int ntile = (a.K + WAVE - 1) / WAVE;
-  int launched[NUM_CLASSES] = {0, 0, 0, 0};
+  int launched[NUM_CLASSES] = {};
   const bool fork = ss != nullptr && a.order != nullptr;
   if (e == hipSuccess && fork) e = hipEventRecord(ss->fork, stream);
   // largest DAGs first: their tiles are the longest
@@ -940,8 +950,9 @@ hipError_t launch_sweep(const SweepArgs& a, hipStream_t stream, const SweepStrea
     }
     uint32_t* counters = a.ovf_count + COUNTERS_PER_CLASS * c;
     uint32_t* list = a.ovf_list + (size_t)(a.order ? a.class_off[c] : 0) * ntile;
-    e = a.small_loads ? launch_class<true>(c, ac, counters, list, sc)
-                      : launch_class<false>(c, ac, counters, list, sc);
+    if (c == LARGE_CLASS) e = launch_eval_large(ac, counters, sc);
+    else e = a.small_loads ? launch_class<true>(c, ac, counters, list, sc)
+                           : launch_class<false>(c, ac, counters, list, sc);
     if (e == hipSuccess && fork) {
       e = hipEventRecord(ss->join[c], sc);
       launched[c] = 1;

@@ -21,7 +21,7 @@ OK, E_ARG, E_CYCLE, E_RANGE, E_DUP_EDGE, E_OOM, E_DEVICE, E_STATE, E_OVERFLOW, E
 PTR_HOST, PTR_DEVICE = 0, 1
 ALLOC_EXPLICIT, ALLOC_SEEDED = 0, 1
 SEARCH_EXHAUSTIVE, SEARCH_SURROGATE = 0, 1
-MAX_NODES_PER_DAG = 512
+MAX_NODES_PER_DAG = 8000
 MAX_CANDIDATES = 1 << 22
 MODEL_PARAMS = 100356
 

@@ -479,7 +479,7 @@ def test_validation_errors(torch_dev):
     _expect(B.E_RANGE, 3, [0], [1], [1, 0, 1], [1, 1, 1])
     _expect(B.E_RANGE, 3, [0], [1], [1, 2**31, 1], [1, 1, 1])
     _expect(B.E_RANGE, 3, [0], [1], [1, 1, 1], [1, 0, 1])
-    n = 600
+    n = 8001
     _expect(B.E_UNSUPPORTED, n, [], [], [1] * n, [1] * n)
 
 
