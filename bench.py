@@ -41,13 +41,16 @@ def sweep_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def algorithmic_bytes(batch, K: int, explicit: bool = True) -> int:
+def algorithmic_bytes(batch, K: int, explicit: bool = True, large: bool = False) -> int:
     """Bytes the method must move for one evaluation launch: each candidate's
     bytes (N_d per candidate, explicit mode only), its 8-byte bound, and the
-    DAG's own data once (17 bytes per node, 4 per edge)."""
+    DAG's own data once (17 bytes per node and 4 per edge for the tables of
+    the kernels up to 512 nodes; 34 per node and 2 per edge for the node
+    records of the large-DAG kernel)."""
     n = np.diff(batch.node_off).astype(np.int64)
     e = np.diff(batch.edge_off).astype(np.int64)
-    return int(np.sum((K * n if explicit else 0) + 8 * K + 17 * n + 4 * e))
+    per_dag = 34 * n + 2 * e if large else 17 * n + 4 * e
+    return int(np.sum((K * n if explicit else 0) + 8 * K + per_dag))
 
 
 def measured_traffic(workload_key: str):
@@ -163,7 +166,7 @@ def cpu_baseline(batch, M, K, seed, gpu_bounds, max_seconds: float = 30.0):
     threads = max(1, min(16, os.cpu_count() or 1))
     D = batch.num_dags
     # size the sample from a short probe so the leg stays near its budget
-    probe_n = min(D, 500)
+    probe_n = min(D, 500 if batch.node_off[-1] < 500 * 1000 else 16)
     probe = batch.subset(range(probe_n))
     pa = W.alloc_bytes(probe, M, K, seed=seed)
     t0 = time.perf_counter()
@@ -217,14 +220,45 @@ def search_block(torch, db, W, n_train: int, n_test: int, epochs: int) -> dict:
     return res
 
 
+def large_block(torch, db, W, n_train: int, n_test_first: int, test, epochs: int) -> dict:
+    """Large-compiler DAGs: surrogate-guided search (16,384 seeded candidates
+    ranked, the top 64 and the paper's rule evaluated exactly) against plain
+    search (the first seeded candidates, exhaustively) at the same time
+    budget, with gaps to exhaustive search over all 16,384 on a sample.  The
+    model is trained here, deterministically, on other DAGs of the workload
+    (256 candidates each, labelled by the exact kernel)."""
+    from paper_2602_20826_amd import proposal as P
+
+    wl = W.WORKLOADS[5]
+    M = wl.num_cus
+    train = W.generate_workload(5, count=n_train, first=10**6)
+    t0 = time.perf_counter()
+    shards = P.label_shards(torch, train, M, 256, seed=11, per_shard=250)
+    model = db.Model(3)
+    hist = P.train(model, shards, epochs, lr=2e-3, lr_end=2e-4)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    for sh in shards:
+        sh.batch.close()
+    res = P.compare_budget(torch, model, test, M, wl.K, seed=5, top_k=64, per_shard=2500, exh_dags=20)
+    model.close()
+    res["workload"] = (f"large-compiler: {test.num_dags} DAGs x {wl.K} seeded candidates, surrogate top-64; "
+                       f"model trained on {n_train} other DAGs x 256 labelled candidates, {epochs} epochs")
+    res["train_seconds"] = train_s
+    res["final_train_loss"] = hist[-1]
+    return res
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=["batched-layered", "persistent-mixed"], default="batched-layered",
-                    help="batched-layered (default; 100,000 DAGs x 64 explicit candidates) or persistent-mixed "
-                         "(DAGs of 50-500 nodes x 256 candidates)")
+    ap.add_argument("--workload", choices=["batched-layered", "persistent-mixed", "large-compiler"],
+                    default="batched-layered",
+                    help="batched-layered (default; 100,000 DAGs x 64 explicit candidates), persistent-mixed "
+                         "(DAGs of 50-500 nodes x 256 candidates) or large-compiler (10,000 DAGs of "
+                         "1,000-5,000 nodes x 64 seeded candidates, and the surrogate against plain search)")
     ap.add_argument("--dags", type=int, default=None, help="number of DAGs (default: the workload's)")
     ap.add_argument("--seeded", action="store_true", help="seeded candidates drawn on the GPU instead of "
                     "explicit bytes (same values)")
@@ -233,6 +267,8 @@ def main() -> int:
     ap.add_argument("--search-train", type=int, default=20000, help="training DAGs (x 256 labelled candidates)")
     ap.add_argument("--search-epochs", type=int, default=60, help="training epochs over those DAGs")
     ap.add_argument("--search-test", type=int, default=5000, help="held-out DAGs (x 4096 seeded candidates)")
+    ap.add_argument("--large-train", type=int, default=2000, help="large-compiler training DAGs (x 256)")
+    ap.add_argument("--large-epochs", type=int, default=20, help="large-compiler training epochs")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="one copy of known size plus one evaluation launch, for counter passes")
     ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -254,9 +290,12 @@ def main() -> int:
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     db.load_library()
-    wk = 2 if args.workload == "batched-layered" else 3
+    wk = {"batched-layered": 2, "persistent-mixed": 3, "large-compiler": 5}[args.workload]
     wl = W.WORKLOADS[wk]
     M, K = wl.num_cus, wl.K
+    if wk == 5:  # exact evaluation of 64 seeded candidates per DAG (16,384 are ranked by the surrogate)
+        K = 64
+        args.seeded = True
     print(f"[bench] generating {wl.name}", file=sys.stderr, flush=True)
     batch = W.generate_workload(wk, count=args.dags)
     D = batch.num_dags
@@ -306,16 +345,20 @@ def main() -> int:
     sweep_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
     evals = D * K
     value = evals * args.steps / elapsed
-    alg = algorithmic_bytes(batch, K, explicit=not args.seeded)
+    alg = algorithmic_bytes(batch, K, explicit=not args.seeded, large=wk == 5)
     achieved = alg / (sweep_ms * 1e-3) / 1e9
     key = f"{args.workload}/{D}x{K}" + ("/seeded" if args.seeded else "")
     if args.workload == "batched-layered":
         desc = (f"batched-layered: {D} DAGs, 20-100 internal nodes (+source/sink), layered width 1-16 p=0.3, "
                 f"WCET 1-1000, parallelism 1-32, M=256, {K} {'seeded' if args.seeded else 'explicit'} candidates")
-    else:
+    elif wk == 3:
         desc = (f"persistent-mixed: {D} DAGs, log-uniform 50-500 internal nodes (+source/sink), half ER p=0.05, "
                 f"half layered width 1-32 p=0.3, WCET log-uniform 1-1e5, parallelism 1-64, M=256, "
                 f"{K} {'seeded' if args.seeded else 'explicit'} candidates")
+    else:
+        desc = (f"large-compiler: {D} DAGs, 1,000-5,000 internal nodes (+source/sink), layered width 1-64 p=0.3 "
+                f"with skip edges p=0.02 over 2-8 layers, WCET lognormal(3, 1.5), parallelism 1-128, M=256, "
+                f"{K} seeded candidates")
     out = {
         "metric": "exact DAG-bound evals/sec + best-bound gap vs exhaustive, surrogate vs plain",
         "value": value,
@@ -341,13 +384,17 @@ def main() -> int:
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": measured_traffic(key),
-            "kernel": "k_eval (one eval_bounds launch: k_eval_init, k_eval, k_eval_global)",
+            "kernel": ("k_eval_large (one eval_bounds launch)" if wk == 5 else
+                       "k_eval (one eval_bounds launch: k_eval_init, k_eval, k_eval_global)"),
             "kernel_ms": sweep_ms,
             "algorithmic_bytes_per_launch": alg,
         },
         "best_gap": None,
     }
-    if not args.no_search:
+    if not args.no_search and wk == 5:
+        print("[bench] large-compiler: label, train, surrogate against plain search", file=sys.stderr, flush=True)
+        out["best_gap"] = large_block(torch, db, W, args.large_train, 0, batch, args.large_epochs)
+    elif not args.no_search:
         print("[bench] learned proposal: label, train, compare searches", file=sys.stderr, flush=True)
         out["best_gap"] = search_block(torch, db, W, args.search_train, args.search_test, args.search_epochs)
     if not args.no_cpu_baseline:

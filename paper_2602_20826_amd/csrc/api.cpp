@@ -133,7 +133,7 @@ struct Carve {
 };
 
 size_t table_bytes(int64_t D, int64_t tn, int64_t te, size_t gres_words, bool mrec) {
-  return 19 * 256 + (size_t)(D + 1) * 8 * 2 + (size_t)tn * 8 + (size_t)D * 8 + 24 + (mrec ? (size_t)tn * 8 : 0) +
+  return 20 * 256 + (size_t)(D + 1) * 8 * 2 + (size_t)tn * 8 + (size_t)D * 8 + 24 + (mrec ? (size_t)tn * 32 : 0) +
          (size_t)tn * 4 + (size_t)(tn + D) * 4 + (size_t)D * 4 + (size_t)tn * 2 * 4 +
          (size_t)te * 2 + gres_words * 4 + (size_t)D * 4;
 }
@@ -174,6 +174,7 @@ struct dagbound_batch {
   unsigned long long* err = nullptr;   // [3] first failing DAG, any load >= 2^20, large-DAG work counter
   uint32_t* gres = nullptr;            // residual tables of the global evaluation pass
   bool small_loads = false;            // every load < 2^20
+  bool small_indeg = false;            // every in-degree < 256
   // DAG ids grouped by size class (the evaluation launches one kernel per class)
   int32_t* order = nullptr;
   std::vector<int32_t> order_host;
@@ -246,6 +247,7 @@ SweepArgs sweep_args(const dagbound_batch* b) {
   a.res_slots = b->res_slots;
   a.path = b->eval_path;
   a.small_loads = b->small_loads ? 1 : 0;
+  a.small_indeg = b->small_indeg ? 1 : 0;
   a.persistent = b->persistent ? 1 : 0;
   return a;
 }
@@ -411,7 +413,10 @@ dagbound_status dagbound_create_batch(int32_t num_dags, const int64_t* node_off,
   b->t.inv = cv.take<uint16_t>(tn);
   b->t.succ = cv.take<uint16_t>(te);
   b->order = cv.take<int32_t>(D);
-  if (n_large > 0) b->t.mrec = cv.take<uint2>(tn);
+  if (n_large > 0) {
+    b->t.nrec = cv.take<uint4>(tn);
+    b->t.mrec = cv.take<uint4>(tn);
+  }
 
   // Inputs: device pointers are read in place; host arrays go through a
   // staging block that is released when this call returns.
@@ -462,7 +467,8 @@ dagbound_status dagbound_create_batch(int32_t num_dags, const int64_t* node_off,
     return hip_fail(e, "preprocessing");
   }
   const unsigned long long err = errw[0];
-  b->small_loads = errw[1] == 0;
+  b->small_loads = (errw[1] & 1) == 0;
+  b->small_indeg = (errw[1] & 2) == 0;
   if (err != ~0ull) {
     const long long d = (long long)(err >> 8);
     const unsigned code = (unsigned)(err & 0xFF);
@@ -758,11 +764,13 @@ void model_init_params(uint64_t seed, std::vector<float>& h) {
   fill(SUR_OFF_WA, SUR_HID * SUR_OUT, SUR_HID, SUR_OUT);
 }
 
-// Activation workspace of a batch; returns the argument block.
-dagbound_status model_workspace(dagbound_model* m, const dagbound_batch* b, SurArgs* s) {
+// Activation workspace of a batch; returns the argument block.  Inference
+// (train = false) leaves out the gradient buffers (about half the bytes).
+dagbound_status model_workspace(dagbound_model* m, const dagbound_batch* b, SurArgs* s, bool train) {
   const int64_t R = b->tn, D = b->D;
-  const int64_t nchunk = (R + SUR_CHUNK - 1) / SUR_CHUNK;
-  const size_t need = 32 * 256 + (size_t)R * sur_node_bytes() + (size_t)(R + D) * 4 + (size_t)b->te * 4 +
+  const int64_t nchunk = train ? (R + SUR_CHUNK - 1) / SUR_CHUNK : 0;
+  const size_t node = train ? sur_node_bytes() : sur_node_bytes() - sur_node_grad_bytes();
+  const size_t need = 32 * 256 + (size_t)R * node + (size_t)(R + D) * 4 + (size_t)b->te * 4 +
                       (size_t)nchunk * (256 * 128 + 128) * 4 + (size_t)D * 4;
   if (m->ws_size < need) {
     dev_release(m->ws, m->ws_size, m->device);
@@ -790,18 +798,20 @@ dagbound_status model_workspace(dagbound_model* m, const dagbound_batch* b, SurA
   s->wbwd = m->wbwd;
   s->X = c.take<float>((size_t)R * SUR_FIN);
   s->A = c.take<float>((size_t)R * SUR_OUT);
-  s->dA = c.take<float>((size_t)R * SUR_OUT);
   for (int l = 0; l <= SUR_LAYERS; l++) s->H[l] = c.take<__bf16>((size_t)R * SUR_HID);
   for (int l = 0; l < SUR_LAYERS; l++) s->G[l] = c.take<__bf16>((size_t)R * SUR_HID);
-  s->dZ[0] = c.take<__bf16>((size_t)R * SUR_HID);
-  s->dZ[1] = c.take<__bf16>((size_t)R * SUR_HID);
-  s->DT = c.take<float>((size_t)R * 256);
   s->dag_of = c.take<int32_t>((size_t)R);
   s->nboff = c.take<uint32_t>((size_t)(R + D));
   s->nb = c.take<uint16_t>((size_t)b->te * 2);
-  s->partial = c.take<float>((size_t)nchunk * 256 * 128);
-  s->partial2 = c.take<float>((size_t)nchunk * 128);
   s->loss_part = c.take<float>((size_t)D);
+  if (train) {
+    s->dA = c.take<float>((size_t)R * SUR_OUT);
+    s->dZ[0] = c.take<__bf16>((size_t)R * SUR_HID);
+    s->dZ[1] = c.take<__bf16>((size_t)R * SUR_HID);
+    s->DT = c.take<float>((size_t)R * 256);
+    s->partial = c.take<float>((size_t)nchunk * 256 * 128);
+    s->partial2 = c.take<float>((size_t)nchunk * 128);
+  }
   return DAGBOUND_OK;
 }
 
@@ -897,7 +907,7 @@ dagbound_status dagbound_model_forward(dagbound_model* m, dagbound_batch* b, flo
   DeviceGuard g(m->device);
   hipStream_t st = (hipStream_t)hip_stream;
   SurArgs s;
-  dagbound_status rc = model_workspace(m, b, &s);
+  dagbound_status rc = model_workspace(m, b, &s, false);
   if (rc != DAGBOUND_OK) return rc;
   hipError_t e = sur_features(s, st);
   if (e == hipSuccess) e = sur_forward(s, st);
@@ -934,7 +944,7 @@ dagbound_status dagbound_model_train_step(dagbound_model* m, dagbound_batch* b, 
   DeviceGuard g(m->device);
   hipStream_t st = (hipStream_t)hip_stream;
   SurArgs s;
-  dagbound_status rc = model_workspace(m, b, &s);
+  dagbound_status rc = model_workspace(m, b, &s, true);
   if (rc != DAGBOUND_OK) return rc;
   const int64_t* dbounds = bounds;
   void* tmp = nullptr;
@@ -980,7 +990,7 @@ dagbound_status dagbound_model_select(dagbound_model* m, dagbound_batch* b, int3
   DeviceGuard g(m->device);
   hipStream_t st = (hipStream_t)hip_stream;
   SurArgs s;
-  dagbound_status rc = model_workspace(m, b, &s);
+  dagbound_status rc = model_workspace(m, b, &s, false);
   if (rc != DAGBOUND_OK) return rc;
   hipError_t e = sur_features(s, st);
   if (e == hipSuccess) e = sur_forward(s, st);
@@ -1000,7 +1010,7 @@ dagbound_status surrogate_best(dagbound_batch* b, dagbound_model* m, int32_t top
   if (m->device != b->device) return fail(DAGBOUND_E_ARG, "model and batch live on different devices");
   DeviceGuard g(b->device);
   SurArgs s;
-  dagbound_status rc = model_workspace(m, b, &s);
+  dagbound_status rc = model_workspace(m, b, &s, false);
   if (rc != DAGBOUND_OK) return rc;
   const int32_t kk = top_k + 1;
   void* tmp = nullptr;

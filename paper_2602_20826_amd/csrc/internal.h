@@ -23,8 +23,11 @@ struct Tables {
   uint16_t* succ;           // [T_E] successor sigma ranks, DAG d at edge_off[d]
   int64_t* wanc;            // [T_N] W^anc by local node id (inspection)
   int32_t* ngroups;         // [D] |Pi|
-  uint2* mrec;              // [T_N] member records in group order, {C_hat, min(p, M) | sigma << 16 |
-                            // last << 31}; written only when the batch holds a DAG above 512 nodes
+  // Node records for the large-DAG evaluation, written only when the batch
+  // holds a DAG above 512 nodes: {C_hat, min(p, M) | sigma << 16 | last << 31,
+  // first successor (offset in the DAG's succ), local id | out-degree << 16}.
+  uint4* nrec;              // [T_N] by sigma rank (last = 0)
+  uint4* mrec;              // [T_N] in group order (last marks a group's last member)
 };
 
 struct PrepInputs {
@@ -39,8 +42,9 @@ struct PrepInputs {
 enum : uint32_t { PREP_E_CYCLE = 2, PREP_E_RANGE = 3, PREP_E_DUP = 4, PREP_E_OVERFLOW = 8,
                   PREP_E_INTERNAL = 9 };
 
-// err[0]: first failing DAG and code; err[1]: nonzero if some load is 2^20
-// or more; err[2]: work counter of the large-DAG preprocessing (zeroed).
+// err[0]: first failing DAG and code; err[1]: bit 0 if some load is 2^20 or
+// more, bit 1 if some in-degree is 256 or more; err[2]: work counter of the
+// large-DAG preprocessing (zeroed).
 // With `order` (DAG ids grouped by size class, class c at class_off[c]),
 // one launch per class; without, one launch sized for max_n.  DAGs above
 // 512 nodes use `lscratch` (prep_large_scratch_bytes of their largest size).
@@ -114,6 +118,7 @@ struct SweepArgs {
   int32_t res_slots;            // <= RES_SLOTS
   int32_t path;                 // EVAL_PATH_*
   int32_t small_loads;          // every C_hat < 2^20
+  int32_t small_indeg;          // every in-degree < 256
   int32_t persistent;           // first pass as a persistent kernel over a work counter
 };
 
@@ -191,6 +196,7 @@ struct SurArgs {
 };
 
 size_t sur_node_bytes();
+size_t sur_node_grad_bytes();  // the part only training uses
 hipError_t sur_features(const SurArgs& s, hipStream_t st);
 hipError_t sur_forward(const SurArgs& s, hipStream_t st);
 hipError_t sur_head_train(const SurArgs& s, int32_t K, uint64_t seed, const int64_t* bounds, float scale,

@@ -21,17 +21,19 @@
 //
 // Evaluation (k_eval_large): one wavefront per (DAG, candidate), lanes over
 // nodes, persistent over a 64-bit work counter.  Per candidate the LDS holds
-// the released / finished / segmented / member / finished-now bitsets, the
-// counts of unfinished predecessors (16 bits per node) and the candidate
-// bytes by sigma rank; residual loads of segmented nodes are in a global
-// region of the wavefront.  A slot (Algorithm 2 for one group, then Lemma 1):
+// the released / segmented / member / released-in-this-slot bitsets, the
+// counts of unfinished predecessors (8 or 16 bits per node) and, for
+// explicit bytes, the candidate bytes by sigma rank (seeded bytes are drawn
+// where they are used); residual loads of segmented nodes are in a global
+// region of the wavefront.  Node data come from one 16-byte record per node
+// (in sigma order for parallel nodes, in group order for members).  A slot (Algorithm 2 for one group, then Lemma 1):
 // the members are one lane each (W(pi_j), Eq. 5, Eq. 1 through wave
 // reductions); the parallel nodes are taken 64 at a time in sigma order and
 // Eqs. 6-7 become a prefix sum: the node at prefix P_i is reached while
 // P_i < S, takes min(m, S - P_i) units, and the first reached node that does
 // not fit in maxC * m is segmented, which stops the launching; finished
-// nodes then decrement their successors' counts, and a count reaching zero
-// releases the successor.  All arithmetic is integer.
+// nodes decrement their successors' counts at once, and a count reaching
+// zero releases the successor when the slot ends.  All arithmetic is integer.
 #include <climits>
 
 #include "internal.h"
@@ -230,7 +232,7 @@ __device__ uint32_t block_scan(int n, F f, uint32_t* out, uint32_t* wtot) {
 // a .. b - 1 of the group list in order.  One wavefront; returns the number
 // of groups, or -1 if a step finds no head.
 __device__ int group_block(const Tables& t, int64_t n0, int a, int b, int32_t M, const PrepScratch& S,
-                           const uint32_t* wcl, uint8_t* gflag, uint64_t* sel) {
+                           uint8_t* gflag, uint64_t* sel) {
   const int lane = threadIdx.x & 63;
   const int nc = (b - a + 63) >> 6;
   int gpos = a, ng = 0;
@@ -287,8 +289,6 @@ __device__ int group_block(const Tables& t, int64_t n0, int a, int b, int32_t M,
         const int g = gpos + base + __popcll(sb & lanes_below(lane));
         const uint32_t last = g == gpos + take - 1 ? 0x8000u : 0u;
         t.gl[n0 + g] = (uint16_t)(s | last);
-        const int v = S.perm[s];
-        t.mrec[n0 + g] = make_uint2(wcl[v], min(S.par[v], (uint32_t)M) | ((uint32_t)s << 16) | (last << 16));
         gflag[s] = 1;
       }
       base += __popcll(sb);
@@ -405,11 +405,15 @@ __device__ void prep_one(const Tables& t, const PrepInputs& in, int32_t M, int d
     S.succl[atomicAdd(&S.outc[u], 1u)] = (uint16_t)v;
   }
   __syncthreads();
+  uint32_t dmax = 0;
   for (int v = tid; v < N; v += PT) {
     const uint32_t deg = S.predoff[v + 1] - S.predoff[v];
     cnt[v] = deg;
+    dmax = max(dmax, deg);
     if (deg == 0) S.topo[atomicAdd(&misc[M_TAIL], 1u)] = (uint16_t)v;
   }
+  dmax = wave_max(dmax);
+  if (lane == 0 && dmax >= 256) atomicOr(&err[1], 2ull);  // in-degrees need 16-bit counts
   __syncthreads();
 
   // Ancestor closure by Kahn levels: the rows of a level are final once
@@ -574,7 +578,7 @@ __device__ void prep_one(const Tables& t, const PrepInputs& in, int32_t M, int d
       if (sg >= nseg) break;
       const int a = S.topo[sg];
       const int b = sg + 1 < nseg ? (int)S.topo[sg + 1] : N;
-      const int g = group_block(t, n0, a, b, M, S, wcl, gflag, sel);
+      const int g = group_block(t, n0, a, b, M, S, gflag, sel);
       if (g < 0) {
         if (lane == 0) atomicCAS(&misc[M_ERR], 0u, (uint32_t)PREP_E_INTERNAL);
         break;
@@ -615,6 +619,16 @@ __device__ void prep_one(const Tables& t, const PrepInputs& in, int32_t M, int d
       }
       out[j] = x;
     }
+    t.nrec[n0 + s] = make_uint4(wcl[u], min(S.par[u], (uint32_t)M) | ((uint32_t)s << 16), soff[s],
+                                (uint32_t)u | ((a1 - a0) << 16));
+  }
+  __syncthreads();
+  // member records in group order
+  for (int k = tid; k < N; k += PT) {
+    const uint32_t g = t.gl[n0 + k];
+    uint4 r = t.nrec[n0 + (g & 0x7FFF)];
+    r.y |= (g & 0x8000u) << 16;
+    t.mrec[n0 + k] = r;
   }
 }
 
@@ -664,26 +678,34 @@ __device__ inline uint64_t mix64(uint64_t z) {
   return z ^ (z >> 31);
 }
 
-// LDS of one evaluation wavefront (bytes), for DAGs of up to maxn nodes.
+// LDS of one evaluation wavefront (bytes), for DAGs of up to maxn nodes:
+// 8-bit counts when every in-degree is below 256, no byte table when the
+// candidate bytes are drawn where they are used.
 struct EvalLds {
-  size_t rel, fin, seg, gm, dn, cnt, r, total;
+  size_t rel, seg, gm, pend, cnt, r, total;
 };
-__host__ __device__ inline EvalLds eval_lds(int maxn) {
+__host__ __device__ inline EvalLds eval_lds(int maxn, bool c8, bool rs) {
   EvalLds l;
   const size_t nw = (size_t)(maxn + 63) / 64;
   size_t o = 0;
-  l.rel = o; o += nw * 8;  // released, unfinished
-  l.fin = o; o += nw * 8;  // finished
-  l.seg = o; o += nw * 8;  // segmented, unfinished (remaining load in the residual region)
-  l.gm = o;  o += nw * 8;  // members of the current group
-  l.dn = o;  o += nw * 8;  // launched whole in the current slot, then finished now
-  l.cnt = o; o += (size_t)(maxn + 1) / 2 * 4;  // unfinished predecessors, 16 bits per node
-  l.r = o;   o += ((size_t)maxn + 15) & ~(size_t)15;  // candidate bytes by sigma rank
+  l.rel = o;  o += nw * 8;  // released, unfinished
+  l.seg = o;  o += nw * 8;  // segmented, unfinished (remaining load in the residual region)
+  l.gm = o;   o += nw * 8;  // members of the current group
+  l.pend = o; o += nw * 8;  // released during the current slot
+  l.cnt = o;  o += (c8 ? (size_t)(maxn + 3) / 4 : (size_t)(maxn + 1) / 2) * 4;  // unfinished predecessors
+  l.r = o;    o += rs ? 0 : ((size_t)maxn + 15) & ~(size_t)15;  // candidate bytes by sigma rank
   l.total = o;
   return l;
 }
 
-template <bool SMALL>
+// Orders the wavefront's LDS and global accesses (one wavefront per
+// workgroup: lanes communicate through memory in program order).
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+template <bool SMALL, bool RS, bool C8>
 __device__ void eval_one(const SweepArgs& a, uint64_t item, unsigned char* smem, uint32_t* res) {
   const int lane = threadIdx.x;
   const uint64_t li = item / (uint64_t)a.K;
@@ -692,30 +714,36 @@ __device__ void eval_one(const SweepArgs& a, uint64_t item, unsigned char* smem,
   const int c = a.cand_list ? a.cand_list[(int64_t)d * a.K + slot] : slot;
   const int64_t n0 = a.t.node_off[d];
   const int N = (int)uni((uint32_t)(a.t.node_off[d + 1] - n0));
-  const int64_t e0 = a.t.edge_off[d];
   const int NW = (N + 63) >> 6;
   const uint32_t M = (uint32_t)a.M;
-  const EvalLds L = eval_lds(a.max_n);
+  const EvalLds L = eval_lds(a.max_n, C8, RS);
   uint64_t* relw = (uint64_t*)(smem + L.rel);
-  uint64_t* finw = (uint64_t*)(smem + L.fin);
   uint64_t* segw = (uint64_t*)(smem + L.seg);
   uint64_t* gmw = (uint64_t*)(smem + L.gm);
-  uint64_t* dnw = (uint64_t*)(smem + L.dn);
+  uint64_t* pendw = (uint64_t*)(smem + L.pend);
   uint32_t* cnt = (uint32_t*)(smem + L.cnt);
   uint8_t* rb = smem + L.r;
-  const uint32_t* wc = a.t.wc + n0;
-  const uint16_t* pp = a.t.pp + n0;
   const uint16_t* indeg = a.t.indeg + n0;
-  const uint16_t* inv = a.t.inv + n0;
-  const uint32_t* soff = a.t.soff + n0 + d;
-  const uint16_t* succ = a.t.succ + e0;
-  const uint2* mrec = a.t.mrec + n0;
+  const uint16_t* succ = a.t.succ + a.t.edge_off[d];
+  const uint4* mrec = a.t.mrec + n0;
+  const uint4* nrec = a.t.nrec + n0;
 
-  // ---- state: sources released, nothing finished; candidate bytes.
-  for (int i = lane; i < (N + 1) / 2; i += WAVE) {
-    const uint32_t lo = indeg[2 * i];
-    const uint32_t hi = 2 * i + 1 < N ? (uint32_t)indeg[2 * i + 1] : 0u;
-    cnt[i] = lo | (hi << 16);
+  // ---- state: sources released, nothing finished; counts of unfinished
+  // predecessors (four 8-bit or two 16-bit counts per word).
+  if (C8) {
+    for (int i = lane; i < (N + 3) / 4; i += WAVE) {
+      uint32_t w = 0;
+#pragma unroll
+      for (int q = 0; q < 4; q++)
+        if (4 * i + q < N) w |= (uint32_t)indeg[4 * i + q] << (8 * q);
+      cnt[i] = w;
+    }
+  } else {
+    for (int i = lane; i < (N + 1) / 2; i += WAVE) {
+      const uint32_t lo = indeg[2 * i];
+      const uint32_t hi = 2 * i + 1 < N ? (uint32_t)indeg[2 * i + 1] : 0u;
+      cnt[i] = lo | (hi << 16);
+    }
   }
   for (int base = 0; base < N; base += WAVE) {
     const int s = base + lane;
@@ -723,31 +751,72 @@ __device__ void eval_one(const SweepArgs& a, uint64_t item, unsigned char* smem,
     if (lane == 0) relw[base >> 6] = src;
   }
   for (int w = lane; w < NW; w += WAVE) {
-    finw[w] = 0;
     segw[w] = 0;
     gmw[w] = 0;
-    dnw[w] = 0;
+    pendw[w] = 0;
   }
-  if (c == 0) {  // the paper's own rule
-    for (int s = lane; s < N; s += WAVE) rb[s] = 0;
-  } else if (a.alloc) {
-    const uint8_t* row = a.alloc + (int64_t)a.K * n0 + (int64_t)c * N;
-    for (int v = lane; v < N; v += WAVE) rb[inv[v]] = row[v];
-  } else {
-    const uint64_t rkey = mix64(a.seed ^ mix64((uint64_t)d * 0x9E3779B97F4A7C15ull));
-    for (int v = lane; v < N; v += WAVE) {
-      const int s = inv[v];
-      const uint32_t range = min((uint32_t)pp[s], 255u);
-      const uint64_t word = mix64(rkey ^ (((uint64_t)c << 32) | (uint64_t)(v >> 2)));
-      const uint32_t h16 = (uint32_t)(word >> (16 * (v & 3))) & 0xFFFFu;
-      rb[s] = (uint8_t)(1u + ((h16 * range) >> 16));
+  // candidate bytes: candidate 0 is the paper's own rule (all zero)
+  const uint64_t rkey = mix64(a.seed ^ mix64((uint64_t)d * 0x9E3779B97F4A7C15ull));
+  if (!RS) {
+    const uint16_t* inv = a.t.inv + n0;
+    if (c == 0 || !a.alloc) {
+      for (int s = lane; s < N; s += WAVE) rb[s] = 0;
+    } else {
+      const uint8_t* row = a.alloc + (int64_t)a.K * n0 + (int64_t)c * N;
+      for (int v = lane; v < N; v += WAVE) rb[inv[v]] = row[v];
     }
   }
-  __syncthreads();
+  // byte of node s (local id v, min(p, M) = pp)
+  auto r_of = [&](int s, uint32_t v, uint32_t pp) -> uint32_t {
+    if (!RS) return rb[s];
+    const uint64_t word = mix64(rkey ^ (((uint64_t)c << 32) | (uint64_t)(v >> 2)));
+    const uint32_t h16 = (uint32_t)(word >> (16 * (v & 3))) & 0xFFFFu;
+    return c == 0 ? 0u : 1u + ((h16 * min(pp, 255u)) >> 16);
+  };
+  // One finished node's successors lose an unfinished predecessor; a count
+  // reaching zero releases the successor (after the slot).
+  auto dec = [&](int x) {
+    if (C8) {
+      const uint32_t sh = (x & 3) * 8;
+      const uint32_t old = atomicSub(&cnt[x >> 2], 1u << sh);
+      if (((old >> sh) & 0xFFu) == 1u) atomicOr((unsigned long long*)&pendw[x >> 6], 1ull << (x & 63));
+    } else {
+      const uint32_t sh = (x & 1) * 16;
+      const uint32_t old = atomicSub(&cnt[x >> 1], 1u << sh);
+      if (((old >> sh) & 0xFFFFu) == 1u) atomicOr((unsigned long long*)&pendw[x >> 6], 1ull << (x & 63));
+    }
+  };
+  // Releases by the finished nodes held in `lanes` (record .z = first
+  // successor, .w >> 16 = out-degree), two nodes' lists loaded together.
+  auto release = [&](uint64_t lanes, uint32_t rz, uint32_t rw) {
+    while (lanes) {
+      const int b0 = __builtin_ctzll(lanes);
+      lanes &= lanes - 1;
+      const int b1 = lanes ? __builtin_ctzll(lanes) : b0;
+      const bool two = lanes != 0;
+      lanes &= lanes - 1;
+      const uint32_t ea0 = (uint32_t)__builtin_amdgcn_readlane((int)rz, b0);
+      const uint32_t dg0 = (uint32_t)__builtin_amdgcn_readlane((int)rw, b0) >> 16;
+      const uint32_t ea1 = (uint32_t)__builtin_amdgcn_readlane((int)rz, b1);
+      const uint32_t dg1 = two ? (uint32_t)__builtin_amdgcn_readlane((int)rw, b1) >> 16 : 0u;
+      const int x0 = (uint32_t)lane < dg0 ? (int)succ[ea0 + lane] : -1;
+      const int x1 = (uint32_t)lane < dg1 ? (int)succ[ea1 + lane] : -1;
+      if (x0 >= 0) dec(x0);
+      if (x1 >= 0) dec(x1);
+      for (uint32_t o = WAVE; o < dg0; o += WAVE)
+        if (o + lane < dg0) dec(succ[ea0 + o + lane]);
+      for (uint32_t o = WAVE; o < dg1; o += WAVE)
+        if (o + lane < dg1) dec(succ[ea1 + o + lane]);
+    }
+  };
+  wave_sync();
 
   uint64_t bound = 0, cp = 0;
   int k = 0;
-  uint2 rec = lane < N ? mrec[lane] : make_uint2(0u, 0u);
+  // (records are picked by assignment, not by a conditional expression,
+  // which would select between their addresses and spill them)
+  uint4 rec = make_uint4(0u, 0u, 0u, 0u);
+  if (lane < N) rec = mrec[lane];
   while (k < N) {
     // group extent from the end marks
     int kend;
@@ -768,153 +837,152 @@ __device__ void eval_one(const SweepArgs& a, uint64_t item, unsigned char* smem,
         kend = min(kend, N);
       }
     }
-    const uint2 rnext = kend + lane < N ? mrec[kend + lane] : make_uint2(0u, 0u);
+    uint4 rnext = make_uint4(0u, 0u, 0u, 0u);
+    if (kend + lane < N) rnext = mrec[kend + lane];
+    auto chunk = [&](int base) {
+      uint4 r1 = rec;
+      if (base != k) {
+        r1 = make_uint4(0u, 0u, 0u, 0u);
+        if (base + lane < kend) r1 = mrec[base + lane];
+      }
+      return r1;
+    };
     // Pass 1: member set and W(pi_j), the remaining load of the released
     // members (Eq. 5).
     uint64_t W = 0;
     for (int base = k; base < kend; base += WAVE) {
-      const uint2 r1 = base == k ? rec : (base + lane < kend ? mrec[base + lane] : make_uint2(0u, 0u));
-      const bool mine = base + lane < kend;
+      const uint4 r1 = chunk(base);
       const int s = (r1.y >> 16) & 0x7FFF;
-      if (mine) {
+      if (base + lane < kend) {
         atomicOr((unsigned long long*)&gmw[s >> 6], 1ull << (s & 63));
         if ((relw[s >> 6] >> (s & 63)) & 1) W += ((segw[s >> 6] >> (s & 63)) & 1) ? res[s] : r1.x;
       }
     }
     W = wave_sum64(W);
-    if (W != 0) {
-      // Pass 2: parallelism (the candidate byte, or Eq. 5) and execution
-      // time (Eq. 1) of each released member.
-      uint32_t maxC = 0, sm = 0;
-      uint64_t A = 0;
+    wave_sync();
+    if (W == 0) {
+      // every member finished earlier (or is not released): nothing runs
       for (int base = k; base < kend; base += WAVE) {
-        const uint2 r1 = base == k ? rec : (base + lane < kend ? mrec[base + lane] : make_uint2(0u, 0u));
-        const int s = (r1.y >> 16) & 0x7FFF;
-        if (base + lane < kend && ((relw[s >> 6] >> (s & 63)) & 1)) {
-          const uint32_t cv = ((segw[s >> 6] >> (s & 63)) & 1) ? res[s] : r1.x;
-          const uint32_t mx = min(r1.y & 0xFFFFu, cv);
-          const uint32_t rv = rb[s];
-          const uint32_t m = rv ? min(rv, mx) : max(1u, min(mx, round_share(cv, M, W)));
-          const uint32_t C = ceil_div<SMALL>(cv, m);
-          maxC = max(maxC, C);
-          sm += m;
-          A += (uint64_t)m * C;
-        }
+        const uint4 r1 = chunk(base);
+        if (base + lane < kend) gmw[((r1.y >> 16) & 0x7FFF) >> 6] = 0;
       }
-      maxC = wave_max(maxC);
-      sm = wave_sum(sm);
-      A = wave_sum64(A);
-      __syncthreads();  // member bits complete
-      // Eqs. 6-7: parallel nodes (released, outside the group) in sigma
-      // order take the spare units S.
-      const uint32_t S = sm < M ? M - sm : 0u;
-      if (S > 0) {
-        const uint64_t pw0 = lane < NW ? relw[lane] & ~gmw[lane] : 0ull;
-        const uint64_t pw1 = lane + WAVE < NW ? relw[lane + WAVE] & ~gmw[lane + WAVE] : 0ull;
-        uint32_t Pc = 0;
-        bool stop = false;
-        for (int h = 0; h < 2 && !stop; h++) {
-          const uint64_t pw = h ? pw1 : pw0;
-          uint64_t nz = __ballot(pw != 0);
-          while (nz && !stop) {
-            const int jl = __builtin_ctzll(nz);
-            nz &= nz - 1;
-            const int j = h * WAVE + jl;
-            const uint64_t word = readlane64(pw, jl);
-            const bool on = (word >> lane) & 1;
-            const int s = j * WAVE + lane;
-            const uint64_t sw = segw[j];
-            uint32_t cc = 0, mcp = 0;
-            if (on) {
-              cc = ((sw >> lane) & 1) ? res[s] : wc[s];
-              const uint32_t mx = min((uint32_t)pp[s], cc);
-              const uint32_t rr = rb[s];
-              mcp = rr ? min(rr, mx) : mx;
-            }
-            const uint32_t incl = wave_incl_sum(mcp);
-            const uint32_t Pi = Pc + incl - mcp;
-            const bool reached = on && Pi < S;
-            const uint32_t mc = reached ? min(mcp, S - Pi) : 0u;
-            const uint64_t cap = (uint64_t)maxC * mc;
-            const bool fits = (uint64_t)cc <= cap;
-            const uint64_t nofit = __ballot(reached && !fits);
-            uint64_t launched = __ballot(reached && fits);
-            if (nofit) {
-              // segmented: launched for maxC * m units, the rest stays released
-              const int f = __builtin_ctzll(nofit);
-              launched &= lanes_below(f);
-              if (lane == f) res[s] = cc - (uint32_t)cap;
-              if (lane == 0) segw[j] = sw | (1ull << f);
-              stop = true;
-            } else {
-              Pc = min(Pc + lane63(incl), S);
-              stop = Pc >= S;
-            }
-            if (lane == 0) dnw[j] = launched;
-          }
-        }
+      wave_sync();
+      k = kend;
+      rec = rnext;
+      continue;
+    }
+    // the parallel-node candidates (released, outside the group) are fixed
+    // now; their first word's records are loaded ahead
+    const uint64_t pw0 = lane < NW ? relw[lane] & ~gmw[lane] : 0ull;
+    const uint64_t pw1 = lane + WAVE < NW ? relw[lane + WAVE] & ~gmw[lane + WAVE] : 0ull;
+    const uint64_t nz0 = __ballot(pw0 != 0), nz1 = __ballot(pw1 != 0);
+    const int j0 = nz0 ? __builtin_ctzll(nz0) : (nz1 ? WAVE + __builtin_ctzll(nz1) : -1);
+    uint4 pre = make_uint4(0u, 0u, 0u, 0u);
+    if (j0 >= 0) {
+      const uint64_t word = readlane64(j0 < WAVE ? pw0 : pw1, j0 & 63);
+      if ((word >> lane) & 1) pre = nrec[j0 * WAVE + lane];
+    }
+    // Pass 2: parallelism (the candidate byte, or Eq. 5) and execution time
+    // (Eq. 1) of each released member; the released members finish.
+    uint32_t maxC = 0, sm = 0;
+    uint64_t A = 0;
+    for (int base = k; base < kend; base += WAVE) {
+      const uint4 r1 = chunk(base);
+      const int s = (r1.y >> 16) & 0x7FFF;
+      const bool rl = base + lane < kend && ((relw[s >> 6] >> (s & 63)) & 1);
+      if (rl) {
+        const bool sg = (segw[s >> 6] >> (s & 63)) & 1;
+        const uint32_t cv = sg ? res[s] : r1.x;
+        const uint32_t pp = r1.y & 0xFFFFu;
+        const uint32_t mx = min(pp, cv);
+        const uint32_t rv = r_of(s, r1.w & 0xFFFFu, pp);
+        const uint32_t m = rv ? min(rv, mx) : max(1u, min(mx, round_share(cv, M, W)));
+        const uint32_t C = ceil_div<SMALL>(cv, m);
+        maxC = max(maxC, C);
+        sm += m;
+        A += (uint64_t)m * C;
       }
-      // Lemma 1, plus the list-scheduling term if the members oversubscribe.
-      uint64_t R = maxC;
-      if (sm > M) R += (A - maxC) / M;
-      bound += R;
-      cp += maxC;
-      __syncthreads();
-      // Finished now: the released members and the nodes launched whole.
-      uint64_t dn0 = 0, dn1 = 0;
-      for (int w = lane, h = 0; w < NW && h < 2; w += WAVE, h++) {
-        const uint64_t x = (relw[w] & gmw[w]) | dnw[w];
-        if (x) {
-          relw[w] &= ~x;
-          finw[w] |= x;
-          segw[w] &= ~x;
-        }
-        gmw[w] = 0;
-        dnw[w] = 0;
-        if (h) dn1 = x;
-        else dn0 = x;
+      const uint64_t fl = __ballot(rl);
+      if (rl) {
+        const uint64_t bit = 1ull << (s & 63);
+        atomicAnd((unsigned long long*)&relw[s >> 6], ~bit);
+        atomicAnd((unsigned long long*)&segw[s >> 6], ~bit);
       }
-      __syncthreads();
-      // Releases: each finished node decrements its successors' counts of
-      // unfinished predecessors; a count reaching zero releases the node.
-      for (int h = 0; h < 2; h++) {
-        const uint64_t dw = h ? dn1 : dn0;
-        uint64_t nz = __ballot(dw != 0);
-        while (nz) {
+      release(fl, r1.z, r1.w);
+    }
+    maxC = wave_max(maxC);
+    sm = wave_sum(sm);
+    A = wave_sum64(A);
+    wave_sync();
+    // Eqs. 6-7: parallel nodes in sigma order take the spare units S; the
+    // node at prefix P_i is reached while P_i < S and takes min(m, S - P_i);
+    // the first reached node that does not fit in maxC * m is segmented and
+    // the launching stops.
+    const uint32_t S = sm < M ? M - sm : 0u;
+    if (S > 0 && j0 >= 0) {
+      uint32_t Pc = 0;
+      bool stop = false;
+      for (int h = j0 >> 6; h < 2 && !stop; h++) {
+        const uint64_t pw = h ? pw1 : pw0;
+        uint64_t nz = h ? nz1 : nz0;
+        while (nz && !stop) {
           const int jl = __builtin_ctzll(nz);
           nz &= nz - 1;
           const int j = h * WAVE + jl;
-          const uint64_t word = readlane64(dw, jl);
-          // successor ranges of the word's nodes, one lane each
-          uint32_t ea = 0, eb = 0;
-          if ((word >> lane) & 1) {
-            ea = soff[j * WAVE + lane];
-            eb = soff[j * WAVE + lane + 1];
+          const uint64_t word = readlane64(pw, jl);
+          const bool on = (word >> lane) & 1;
+          const int s = j * WAVE + lane;
+          uint4 r = pre;
+          if (j != j0 && on) r = nrec[s];
+          const uint64_t sw = segw[j];
+          uint32_t cc = 0, mcp = 0;
+          if (on) {
+            cc = ((sw >> lane) & 1) ? res[s] : r.x;
+            const uint32_t pp = r.y & 0xFFFFu;
+            const uint32_t mx = min(pp, cc);
+            const uint32_t rr = r_of(s, r.w & 0xFFFFu, pp);
+            mcp = rr ? min(rr, mx) : mx;
           }
-          uint64_t bits = word;
-          while (bits) {
-            const int b = __builtin_ctzll(bits);
-            bits &= bits - 1;
-            const uint32_t xa = (uint32_t)__builtin_amdgcn_readlane((int)ea, b);
-            const uint32_t xb = (uint32_t)__builtin_amdgcn_readlane((int)eb, b);
-            for (uint32_t e = xa + lane; e < xb; e += WAVE) {
-              const int x = succ[e];
-              const uint32_t sh = (x & 1) * 16;
-              const uint32_t old = atomicSub(&cnt[x >> 1], 1u << sh);
-              if (((old >> sh) & 0xFFFFu) == 1u) atomicOr((unsigned long long*)&relw[x >> 6], 1ull << (x & 63));
-            }
+          const uint32_t incl = wave_incl_sum(mcp);
+          const uint32_t Pi = Pc + incl - mcp;
+          const bool reached = on && Pi < S;
+          const uint32_t mc = reached ? min(mcp, S - Pi) : 0u;
+          const uint64_t cap = (uint64_t)maxC * mc;
+          const bool fits = (uint64_t)cc <= cap;
+          const uint64_t nofit = __ballot(reached && !fits);
+          uint64_t launched = __ballot(reached && fits);
+          uint64_t segbit = 0;
+          if (nofit) {
+            // segmented: it runs maxC * m of its load, the rest stays released
+            const int f = __builtin_ctzll(nofit);
+            launched &= lanes_below(f);
+            if (lane == f) res[s] = cc - (uint32_t)cap;
+            segbit = 1ull << f;
+            stop = true;
+          } else {
+            Pc = min(Pc + lane63(incl), S);
+            stop = Pc >= S;
           }
+          if (lane == 0) {
+            relw[j] &= ~launched;
+            segw[j] = (sw & ~launched) | segbit;
+          }
+          release(launched, r.z, r.w);
         }
       }
-    } else {
-      // every member finished earlier (or is not released): nothing runs
-      __syncthreads();
-      for (int base = k; base < kend; base += WAVE) {
-        const uint2 r1 = base == k ? rec : (base + lane < kend ? mrec[base + lane] : make_uint2(0u, 0u));
-        if (base + lane < kend) gmw[((r1.y >> 16) & 0x7FFF) >> 6] = 0;
-      }
     }
-    __syncthreads();
+    // Lemma 1, plus the list-scheduling term if the members oversubscribe.
+    uint64_t R = maxC;
+    if (sm > M) R += (A - maxC) / M;
+    bound += R;
+    cp += maxC;
+    wave_sync();
+    for (int w = lane; w < NW; w += WAVE) {
+      relw[w] |= pendw[w];
+      pendw[w] = 0;
+      gmw[w] = 0;
+    }
+    wave_sync();
     k = kend;
     rec = rnext;
   }
@@ -928,7 +996,7 @@ __device__ void eval_one(const SweepArgs& a, uint64_t item, unsigned char* smem,
   }
 }
 
-template <bool SMALL>
+template <bool SMALL, bool RS, bool C8>
 __global__ __launch_bounds__(64) void k_eval_large(SweepArgs a, unsigned long long* counter, uint64_t total) {
   extern __shared__ __align__(16) unsigned char smem[];
   uint32_t* res = a.gres + (size_t)blockIdx.x * (size_t)a.max_n;
@@ -937,9 +1005,33 @@ __global__ __launch_bounds__(64) void k_eval_large(SweepArgs a, unsigned long lo
     if (threadIdx.x == 0) item = atomicAdd(counter, 1ull);
     item = ((uint64_t)uni((uint32_t)(item >> 32)) << 32) | uni((uint32_t)item);  // lane 0's
     if (item >= total) break;
-    eval_one<SMALL>(a, item, smem, res);
-    __syncthreads();
+    eval_one<SMALL, RS, C8>(a, item, smem, res);
+    wave_sync();
   }
+}
+
+template <bool SMALL, bool RS, bool C8>
+hipError_t launch_large_v(const SweepArgs& a, unsigned long long* counter, uint64_t total, hipStream_t stream) {
+  const size_t lds = eval_lds(a.max_n, C8, RS).total;
+  const void* fn = (const void*)k_eval_large<SMALL, RS, C8>;
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  int per_cu = 0, dev = 0, cus = 0;
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, WAVE, lds);
+  if (e == hipSuccess) e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return e;
+  const uint64_t cap = (uint64_t)max(1, per_cu) * (uint64_t)max(1, cus);
+  uint64_t g = total < cap ? total : cap;
+  if (g > (uint64_t)LARGE_SLOTS) g = LARGE_SLOTS;
+  hipLaunchKernelGGL((k_eval_large<SMALL, RS, C8>), dim3((unsigned)g), dim3(WAVE), lds, stream, a, counter, total);
+  return hipGetLastError();
+}
+
+template <bool SMALL, bool RS>
+hipError_t launch_large_c(const SweepArgs& a, unsigned long long* counter, uint64_t total, hipStream_t stream) {
+  return a.small_indeg ? launch_large_v<SMALL, RS, true>(a, counter, total, stream)
+                       : launch_large_v<SMALL, RS, false>(a, counter, total, stream);
 }
 
 }  // namespace
@@ -948,12 +1040,12 @@ size_t prep_large_scratch_bytes(int32_t max_n, int32_t max_e) {
   return prep_scratch(nullptr, max_n, max(max_e, 1)).bytes;
 }
 
-size_t eval_large_lds_bytes(int max_n) { return eval_lds(max_n).total; }
+size_t eval_large_lds_bytes(int max_n) { return eval_lds(max_n, false, false).total; }
 
 hipError_t launch_prep_large(const Tables& t, const PrepInputs& in, int32_t count, int32_t M, const int32_t* list,
                              unsigned long long* err, void* scratch, int32_t NL, int32_t EL, hipStream_t stream) {
   if (count <= 0) return hipSuccess;
-  if (NL > LARGE_MAX_N || !scratch || !t.mrec) return hipErrorInvalidValue;
+  if (NL > LARGE_MAX_N || !scratch || !t.mrec || !t.nrec) return hipErrorInvalidValue;
   const size_t lds = prep_lds(NL).total;
   hipError_t e = hipFuncSetAttribute((const void*)k_prep_large, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
@@ -966,26 +1058,12 @@ hipError_t launch_prep_large(const Tables& t, const PrepInputs& in, int32_t coun
 hipError_t launch_eval_large(const SweepArgs& a, uint32_t* counter, hipStream_t stream) {
   const uint64_t total = (uint64_t)a.list_len * (uint64_t)a.K;
   if (total == 0) return hipSuccess;
-  if (a.max_n > LARGE_MAX_N || !a.t.mrec) return hipErrorInvalidValue;
-  const size_t lds = eval_lds(a.max_n).total;
-  const void* fn = a.small_loads ? (const void*)k_eval_large<true> : (const void*)k_eval_large<false>;
-  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  if (e != hipSuccess) return e;
-  int per_cu = 0, dev = 0, cus = 0;
-  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, WAVE, lds);
-  if (e == hipSuccess) e = hipGetDevice(&dev);
-  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  if (e != hipSuccess) return e;
-  const uint64_t cap = (uint64_t)max(1, per_cu) * (uint64_t)max(1, cus);
-  uint64_t g = total < cap ? total : cap;
-  if (g > (uint64_t)LARGE_SLOTS) g = LARGE_SLOTS;
-  const int grid = (int)g;
+  if (a.max_n > LARGE_MAX_N || !a.t.mrec || !a.t.nrec) return hipErrorInvalidValue;
   unsigned long long* ctr = (unsigned long long*)counter;
+  const bool rs = a.alloc == nullptr;  // seeded bytes drawn where they are used
   if (a.small_loads)
-    hipLaunchKernelGGL(k_eval_large<true>, dim3(grid), dim3(WAVE), lds, stream, a, ctr, total);
-  else
-    hipLaunchKernelGGL(k_eval_large<false>, dim3(grid), dim3(WAVE), lds, stream, a, ctr, total);
-  return hipGetLastError();
+    return rs ? launch_large_c<true, true>(a, ctr, total, stream) : launch_large_c<true, false>(a, ctr, total, stream);
+  return rs ? launch_large_c<false, true>(a, ctr, total, stream) : launch_large_c<false, false>(a, ctr, total, stream);
 }
 
 }  // namespace dagbound

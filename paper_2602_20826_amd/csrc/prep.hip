@@ -131,8 +131,8 @@ __global__ __launch_bounds__(64) void k_prep(Tables t, PrepInputs in, int32_t M,
   for (int o = 32; o > 0; o >>= 1) lsum += __shfl_xor(lsum, o);
   if (lane == 0) *s_sum = lsum;
   wmax = wave_max_u32(wmax);
-  // err[1] flags a load of 2^20 or more somewhere in the batch (set rarely,
-  // so DAGs do not queue on one global address)
+  // err[1] bit 0 flags a load of 2^20 or more somewhere in the batch (set
+  // rarely, so DAGs do not queue on one global address)
   if (lane == 0 && wmax >= (1u << 20)) atomicOr(&err[1], 1ull);
   // Edges: range, self-loop, duplicates (an LDS bitset of predecessors).
   // The first EPRE rounds come from the loads issued above; later rounds
@@ -161,6 +161,12 @@ __global__ __launch_bounds__(64) void k_prep(Tables t, PrepInputs in, int32_t M,
     }
   }
   __syncthreads();
+  {
+    uint32_t dmax = 0;
+    for (int v = lane; v < N; v += WAVE) dmax = max(dmax, s_indeg[v]);
+    dmax = wave_max_u32(dmax);
+    if (lane == 0 && dmax >= 256) atomicOr(&err[1], 2ull);
+  }
   if (s_misc[0] == 0 && *s_sum >= (1ull << 40)) {
     if (lane == 0) s_misc[0] = PREP_E_OVERFLOW;
   }
@@ -417,11 +423,6 @@ __global__ __launch_bounds__(64) void k_prep(Tables t, PrepInputs in, int32_t M,
         const int pos = gpos + base + __popcll(sb[k] & lanes_below(lane));
         const uint32_t last = pos == gpos + cnt - 1 ? 0x8000u : 0u;
         gl[pos] = (uint16_t)(s | last);
-        if (t.mrec) {  // member records, kept when the batch also holds large DAGs
-          const int v = s_perm[s];
-          t.mrec[n0 + pos] =
-              make_uint2(s_wcet[v], min(s_par[v], (uint32_t)M) | ((uint32_t)s << 16) | (last << 16));
-        }
         grouped[k] = true;
         s_gflag[s] = 1;
       }
@@ -464,6 +465,24 @@ __global__ __launch_bounds__(64) void k_prep(Tables t, PrepInputs in, int32_t M,
     const int32_t u = in.src[e0 + k], v = in.dst[e0 + k];
     const uint32_t pos = atomicAdd(&s_cursor[u], 1u);
     t.succ[e0 + pos] = s_sig[v];
+  }
+  // Node records of the large-DAG evaluation (kept when the batch also
+  // holds DAGs above 512 nodes, which may run every DAG in that kernel).
+  if (t.nrec) {
+    __syncthreads();
+    for (int s = lane; s < N; s += WAVE) {
+      const int v = s_perm[s];
+      const uint32_t deg = soff[s + 1] - soff[s];
+      t.nrec[n0 + s] = make_uint4(s_wcet[v], min(s_par[v], (uint32_t)M) | ((uint32_t)s << 16), soff[s],
+                                  (uint32_t)v | (deg << 16));
+    }
+    __syncthreads();
+    for (int k = lane; k < N; k += WAVE) {
+      const uint32_t g = gl[k];
+      uint4 r = t.nrec[n0 + (g & 0x7FFF)];
+      r.y |= (g & 0x8000u) << 16;
+      t.mrec[n0 + k] = r;
+    }
   }
 }
 

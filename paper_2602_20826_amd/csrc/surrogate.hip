@@ -616,6 +616,11 @@ size_t sur_node_bytes() {
   return 8 * 4 + 4 * 4 * 2 + 9 * 128 * 2 + 256 * 4 + 4;
 }
 
+size_t sur_node_grad_bytes() {
+  // dA (4 fp32) + dZ x 2 (bf16 x 128) + DT (256 fp32)
+  return 4 * 4 + 2 * 128 * 2 + 256 * 4;
+}
+
 hipError_t sur_features(const SurArgs& s, hipStream_t st) {
   hipLaunchKernelGGL(k_dag_of, dim3(s.D), dim3(64), 0, st, s.t.node_off, s.D, s.dag_of);
   const size_t lds = (size_t)s.max_n * 20 + 64;

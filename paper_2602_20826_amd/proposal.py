@@ -121,3 +121,97 @@ def compare_search(torch, model: db.Model, dags, M: int, K: int, seed: int, top_
         "gain_over_random_mean": float(np.mean(1.0 - sur / rnd)),
         "dags_improved_over_paper_rule": int(np.sum(sur < c0)),
     }
+
+
+def compare_budget(torch, model: db.Model, dags, M: int, K: int, seed: int, top_k: int, per_shard: int,
+                   exh_dags: int) -> Dict:
+    """Surrogate-guided search against plain search at the same time budget,
+    on DAGs taken per_shard at a time:
+      - surrogate: candidate 0 plus the top_k of K seeded candidates ranked by
+        the model, evaluated exactly (one best_allocation call, timed);
+      - plain: the first K_p seeded candidates (candidate 0 and K_p - 1 random
+        ones) evaluated exactly, K_p sized so that this exhaustive search takes
+        about the surrogate's time (from the measured rate of a 64-candidate
+        evaluation of the same shard), timed;
+      - exhaustive over all K candidates on the first exh_dags DAGs of each
+        shard, as the reference of the gaps (and timed, for its DAGs/s).
+    Returns mean gaps and times."""
+    dev = torch.device("cuda:0")
+    st = torch.cuda.current_stream(dev)
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    sur_all, plain_all, c0_all, exh_all, sur_s, plain_s, exh_s = [], [], [], [], [], [], []
+    kps = []
+    for s0 in range(0, dags.num_dags, per_shard):
+        sub = dags.subset(range(s0, min(dags.num_dags, s0 + per_shard)))
+        D = sub.num_dags
+        b = _dev_batch(torch, dev, sub, M)
+        idx = torch.empty(D, dtype=torch.int32, device=dev)
+        best = torch.empty(D, dtype=torch.int64, device=dev)
+        db.set_allocations(b, K, db.ALLOC_SEEDED, None, seed)
+        db.best_allocation(b, idx, best, search=db.SEARCH_SURROGATE, top_k=top_k, model=model, stream=st)
+        t_sur = timed(lambda: db.best_allocation(b, idx, best, search=db.SEARCH_SURROGATE, top_k=top_k,
+                                                 model=model, stream=st))
+        sur = best.cpu().numpy().astype(np.float64)
+        # rate of exact search on this shard, then the plain budget
+        db.set_allocations(b, 64, db.ALLOC_SEEDED, None, seed)
+        out64 = torch.empty(D * 64, dtype=torch.int64, device=dev)
+        db.eval_bounds(b, out64, stream=st)
+        t64 = timed(lambda: db.eval_bounds(b, out64, stream=st))
+        kp = int(max(top_k + 1, min(K, round(64 * t_sur / t64))))
+        db.set_allocations(b, kp, db.ALLOC_SEEDED, None, seed)
+        outp = torch.empty(D * kp, dtype=torch.int64, device=dev)
+        t_plain = timed(lambda: db.eval_bounds(b, outp, stream=st))
+        pl = outp.view(D, kp)
+        plain = pl.min(1).values.cpu().numpy().astype(np.float64)
+        c0 = pl[:, 0].cpu().numpy().astype(np.float64)
+        # exhaustive reference on the first DAGs of the shard
+        ne = min(exh_dags, D)
+        ex = sub.subset(range(ne))
+        be = _dev_batch(torch, dev, ex, M)
+        db.set_allocations(be, K, db.ALLOC_SEEDED, None, seed)
+        ie = torch.empty(ne, dtype=torch.int32, device=dev)
+        bx = torch.empty(ne, dtype=torch.int64, device=dev)
+        exh_s.append((ne, timed(lambda: db.best_allocation(be, ie, bx, stream=st))))
+        exh_all.append(bx.cpu().numpy().astype(np.float64))
+        be.close()
+        b.close()
+        sur_all.append(sur)
+        plain_all.append(plain)
+        c0_all.append(c0)
+        sur_s.append(t_sur)
+        plain_s.append(t_plain)
+        kps.append(kp)
+    sur, plain, c0 = np.concatenate(sur_all), np.concatenate(plain_all), np.concatenate(c0_all)
+    exh = np.concatenate(exh_all)
+    first = np.concatenate([np.arange(len(x)) < len(e) for x, e in zip(sur_all, exh_all)])
+
+    def gap(x, ref):
+        g = x / ref - 1.0
+        return {"mean": float(g.mean()), "p99": float(np.quantile(g, 0.99)), "max": float(g.max()),
+                "exact_frac": float(np.mean(g == 0))}
+
+    D = len(sur)
+    return {
+        "dags": D, "K": K, "top_k": top_k,
+        "surrogate_seconds": float(sum(sur_s)), "plain_seconds": float(sum(plain_s)),
+        "surrogate_dags_per_s": D / sum(sur_s), "plain_dags_per_s": D / sum(plain_s),
+        "exhaustive_dags_per_s": sum(n for n, _ in exh_s) / sum(t for _, t in exh_s),
+        "speedup_vs_exhaustive": (D / sum(sur_s)) / (sum(n for n, _ in exh_s) / sum(t for _, t in exh_s)),
+        "plain_candidates": kps,
+        "surrogate_vs_plain": {"mean": float(np.mean(sur / plain - 1.0)),
+                               "better_frac": float(np.mean(sur < plain)),
+                               "equal_frac": float(np.mean(sur == plain)),
+                               "worse_frac": float(np.mean(sur > plain))},
+        "gap_vs_exhaustive_dags": int(first.sum()),
+        "gap_surrogate": gap(sur[first], exh),
+        "gap_plain": gap(plain[first], exh),
+        "gap_paper_rule": gap(c0[first], exh),
+        "gain_over_paper_rule_mean": float(np.mean(1.0 - sur / c0)),
+    }
