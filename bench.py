@@ -166,7 +166,7 @@ def cpu_baseline(batch, M, K, seed, gpu_bounds, max_seconds: float = 30.0):
     threads = max(1, min(16, os.cpu_count() or 1))
     D = batch.num_dags
     # size the sample from a short probe so the leg stays near its budget
-    probe_n = min(D, 500 if batch.node_off[-1] < 500 * 1000 else 16)
+    probe_n = min(D, 500 if batch.node_off[-1] < 1000 * D else 16)  # fewer probe DAGs above 1,000 nodes
     probe = batch.subset(range(probe_n))
     pa = W.alloc_bytes(probe, M, K, seed=seed)
     t0 = time.perf_counter()
@@ -266,7 +266,7 @@ def main() -> int:
     ap.add_argument("--no-search", action="store_true", help="skip the learned-proposal comparison")
     ap.add_argument("--search-train", type=int, default=20000, help="training DAGs (x 256 labelled candidates)")
     ap.add_argument("--search-epochs", type=int, default=60, help="training epochs over those DAGs")
-    ap.add_argument("--search-test", type=int, default=5000, help="held-out DAGs (x 4096 seeded candidates)")
+    ap.add_argument("--search-test", type=int, default=100000, help="held-out DAGs (x 4096 seeded candidates)")
     ap.add_argument("--large-train", type=int, default=2000, help="large-compiler training DAGs (x 256)")
     ap.add_argument("--large-epochs", type=int, default=20, help="large-compiler training epochs")
     ap.add_argument("--traffic-probe", action="store_true",

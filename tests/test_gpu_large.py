@@ -220,3 +220,71 @@ def test_large_validation_errors(torch_dev):
     _expect_large(B.E_OVERFLOW, (n, chain_s, chain_d, [2**31 - 1] * n, ones))
     m = 8001
     _expect_large(B.E_UNSUPPORTED, (m, [], [], [1] * m, [1] * m))
+
+
+def _seeded_rows(batch, dags, M, K, seed, cands=None):
+    """Explicit bytes of DAGs `dags` of `batch` (seeded as in the batch, where
+    the hash takes the DAG's batch index), for candidates `cands` (default all)."""
+    parts = []
+    for d in dags:
+        one = batch.subset([d])
+        n = one.dag(0)[0]
+        full = W.alloc_bytes(one, M, K, seed=seed, first=int(d)).reshape(K, n)
+        parts.append(full if cands is None else full[np.asarray(cands[d])])
+    return np.concatenate([p.ravel() for p in parts])
+
+
+def test_large_compiler_full_size_sampled(torch_dev):
+    # The large-compiler workload at its full size (10,000 DAGs of 1,000-5,000
+    # nodes, about 30M nodes and 420M edges): the bench's exact evaluation (64
+    # seeded candidates) and the surrogate search over 16,384 seeded
+    # candidates with the top 64 verified; sampled DAGs against the oracle.
+    import paper_2602_20826_amd as db
+
+    torch, dev = torch_dev
+    wl = W.WORKLOADS[5]
+    say("large-compiler full size: generating", wl.num_dags, "DAGs")
+    batch = W.generate_workload(5)
+    D, M, K, seed = batch.num_dags, wl.num_cus, 64, 17
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    st = torch.cuda.current_stream(dev)
+    say("create_batch + eval_bounds:", D, "DAGs,", int(batch.node_off[-1]), "nodes x", K)
+    b = db.create_batch(t(batch.node_off), t(batch.edge_off), t(batch.src), t(batch.dst), t(batch.wcet),
+                        t(batch.par), M, stream=st)
+    db.set_allocations(b, K, db.ALLOC_SEEDED, None, seed)
+    out = torch.empty(D * K, dtype=torch.int64, device=dev)
+    db.eval_bounds(b, out, stream=st)
+    idx = torch.empty(D, dtype=torch.int32, device=dev)
+    best = torch.empty(D, dtype=torch.int64, device=dev)
+    db.best_allocation(b, idx, best, stream=st)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(5)
+    sample = sorted(set([0, 1, D // 2, D - 1] + rng.choice(D, 6, replace=False).tolist()))
+    got = out.view(D, K).cpu().numpy()[sample]
+    want, _, _ = oracle.bounds_batch(batch.subset(sample), M, K, _seeded_rows(batch, sample, M, K, seed),
+                                     threads=8)
+    assert np.array_equal(got, want)
+    assert np.array_equal(best.cpu().numpy()[sample], want.min(1))
+    assert np.array_equal(idx.cpu().numpy()[sample], want.argmin(1))
+    # surrogate search: 16,384 seeded candidates ranked, candidate 0 and the
+    # top 64 evaluated exactly
+    KS, top_k = wl.K, 64
+    say("surrogate search:", KS, "candidates, top", top_k)
+    db.set_allocations(b, KS, db.ALLOC_SEEDED, None, seed)
+    model = db.Model(2)
+    cand = torch.empty(D * (top_k + 1), dtype=torch.int32, device=dev)
+    db.model_select(model, b, KS, seed, top_k, 32, cand)
+    db.best_allocation(b, idx, best, search=db.SEARCH_SURROGATE, top_k=top_k, model=model, stream=st)
+    torch.cuda.synchronize()
+    cand = cand.view(D, top_k + 1).cpu().numpy()
+    bi, bb = idx.cpu().numpy(), best.cpu().numpy()
+    model.close()
+    b.close()
+    few = sample[:4]
+    lists = {d: cand[d] for d in few}
+    want, _, _ = oracle.bounds_batch(batch.subset(few), M, top_k + 1,
+                                     _seeded_rows(batch, few, M, KS, seed, lists), threads=8)
+    for i, d in enumerate(few):
+        assert cand[d, 0] == 0 and len(set(cand[d, 1:].tolist())) == top_k
+        pos = int(np.argmin(want[i]))
+        assert bb[d] == want[i, pos] and bi[d] == cand[d, pos], d

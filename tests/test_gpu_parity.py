@@ -202,6 +202,26 @@ def test_batched_layered_full_size_sampled(torch_dev):
     assert np.all(bounds > 0)
 
 
+@pytest.mark.timeout(600)
+def test_persistent_mixed_full_size_sampled(torch_dev):
+    # The whole 1,000,000-DAG persistent-mixed batch (about 197M nodes and
+    # 1.1G edges) with 256 seeded candidates per DAG, as bench.py runs it with
+    # --workload persistent-mixed --seeded; the oracle checks every candidate
+    # of a seeded sample of DAGs.
+    wl = W.WORKLOADS[3]
+    say("persistent-mixed full size: generating", wl.num_dags, "DAGs")
+    batch = W.generate_workload(3)
+    say("persistent-mixed full size:", batch.num_dags, "DAGs x", wl.K, "seeded (sampled check)")
+    got = gpu_eval(torch_dev, batch, wl.num_cus, wl.K, seed=wl.seed, terms=False)
+    rng = np.random.default_rng(43)
+    sample = np.r_[0, np.sort(rng.choice(batch.num_dags, 120, replace=False)), batch.num_dags - 1]
+    parts = [W.alloc_bytes(batch.subset([d]), wl.num_cus, wl.K, seed=wl.seed, first=int(d)) for d in sample]
+    sub = batch.subset(sample)
+    sub_got = [x[sample] if x is not None else None for x in got]
+    check_against_oracle(sub, wl.num_cus, wl.K, np.concatenate(parts), sub_got)
+    assert np.all(got[4] <= got[0][:, 0])
+
+
 def test_seeded_mode_matches_explicit_bytes(torch_dev):
     # The GPU draws seeded candidate bytes itself; the generator draws the
     # same published counter hash into explicit bytes for the oracle.

@@ -192,3 +192,46 @@ def test_surrogate_search_is_exact_on_its_candidates(env):
         assert bb[d] <= want[d, 0]
     b.close()
     model.close()
+
+
+def test_surrogate_search_full_size_sampled(env):
+    # The learned-proposal workload at its full size (100,000 held-out DAGs,
+    # 4,096 seeded candidates each, candidate 0 and the top 16 evaluated
+    # exactly) as bench.py runs it; sampled DAGs against the oracle over
+    # their listed candidates.
+    torch, db = env
+    wl = W.WORKLOADS[4]
+    M, K, seed, top_k = wl.num_cus, wl.K, 5, 16
+    say("learned-proposal full size: generating", wl.num_dags, "DAGs")
+    batch = W.generate_workload(4)
+    D = batch.num_dags
+    dev = torch.device("cuda:0")
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    b = db.create_batch(t(batch.node_off), t(batch.edge_off), t(batch.src), t(batch.dst), t(batch.wcet),
+                        t(batch.par), M)
+    db.set_allocations(b, K, db.ALLOC_SEEDED, None, seed)
+    model = db.Model(6)
+    cand = torch.empty(D * (top_k + 1), dtype=torch.int32, device=dev)
+    say("surrogate selection and search:", D, "DAGs x", K, "top", top_k)
+    db.model_select(model, b, K, seed, top_k, 32, cand)
+    idx = torch.empty(D, dtype=torch.int32, device=dev)
+    best = torch.empty(D, dtype=torch.int64, device=dev)
+    db.best_allocation(b, idx, best, search=db.SEARCH_SURROGATE, top_k=top_k, model=model)
+    torch.cuda.synchronize()
+    cand = cand.view(D, top_k + 1).cpu().numpy()
+    bi, bb = idx.cpu().numpy(), best.cpu().numpy()
+    b.close()
+    model.close()
+    rng = np.random.default_rng(8)
+    sample = [0, D - 1] + sorted(rng.choice(D, 10, replace=False).tolist())
+    parts = []
+    for d in sample:
+        one = batch.subset([d])
+        n = one.dag(0)[0]
+        full = W.alloc_bytes(one, M, K, seed=seed, first=int(d)).reshape(K, n)
+        parts.append(full[cand[d]].ravel())
+    want, _, _ = oracle.bounds_batch(batch.subset(sample), M, top_k + 1, np.concatenate(parts), threads=8)
+    for i, d in enumerate(sample):
+        assert cand[d, 0] == 0 and len(set(cand[d, 1:].tolist())) == top_k
+        pos = int(np.argmin(want[i]))
+        assert bb[d] == want[i, pos] and bi[d] == cand[d, pos], d
