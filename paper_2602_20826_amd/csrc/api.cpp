@@ -371,14 +371,14 @@ dagbound_status dagbound_create_batch(int32_t num_dags, const int64_t* node_off,
   b->max_e = (int32_t)std::min<int64_t>(max_e, INT32_MAX);
   b->node_off = no;
   b->edge_off = eo;
-  int32_t large_max_e = 0;  // most edges of a DAG above 512 nodes
+  int32_t class_max_e[NUM_CLASSES] = {};  // most edges of a DAG of each class
   {
     std::vector<int32_t> cnt(NUM_CLASSES + 1, 0);
     for (int64_t d = 0; d < D; d++) {
       const int cls = class_of((int)(no[d + 1] - no[d]));
       cnt[cls + 1]++;
       b->class_max_n[cls] = std::max<int32_t>(b->class_max_n[cls], (int32_t)(no[d + 1] - no[d]));
-      if (cls == LARGE_CLASS) large_max_e = std::max<int32_t>(large_max_e, (int32_t)(eo[d + 1] - eo[d]));
+      class_max_e[cls] = std::max<int32_t>(class_max_e[cls], (int32_t)std::min<int64_t>(eo[d + 1] - eo[d], INT32_MAX));
     }
     for (int c = 0; c < NUM_CLASSES; c++) cnt[c + 1] += cnt[c];
     for (int c = 0; c <= NUM_CLASSES; c++) b->class_off[c] = cnt[c];
@@ -445,18 +445,20 @@ dagbound_status dagbound_create_batch(int32_t num_dags, const int64_t* node_off,
   }
   if (e == hipSuccess) e = hipMemsetAsync(b->err, 0xFF, sizeof(unsigned long long), st);
   if (e == hipSuccess) e = hipMemsetAsync(b->err + 1, 0, 2 * sizeof(unsigned long long), st);
-  // global scratch of the large-DAG preprocessing, released with the staging
+  // global scratch of the workgroup-per-DAG preprocessing (DAGs above 256
+  // nodes), released with the staging
   void* lscratch = nullptr;
   size_t lscratch_size = 0;
-  if (e == hipSuccess && n_large > 0) {
-    lscratch_size = (size_t)std::min(n_large, PREP_LARGE_GRID) *
-                    prep_large_scratch_bytes(b->class_max_n[LARGE_CLASS], large_max_e);
+  for (int c = 3; c <= LARGE_CLASS; c++)
+    lscratch_size = std::max(lscratch_size, prep_large_scratch_bytes(b->class_off[c + 1] - b->class_off[c],
+                                                                     b->class_max_n[c], class_max_e[c]));
+  if (e == hipSuccess && lscratch_size > 0) {
     e = dev_alloc(&lscratch, &lscratch_size, device);
     if (e != hipSuccess) lscratch = nullptr;
   }
   if (e == hipSuccess)
     e = launch_prep(b->t, in, num_dags, num_cus, (int32_t)max_n, b->order, b->class_off, b->err, lscratch,
-                    b->class_max_n[LARGE_CLASS], large_max_e, st);
+                    b->class_max_n, class_max_e, st);
   unsigned long long errw[2] = {~0ull, 0};
   if (e == hipSuccess) e = hipMemcpyAsync(errw, b->err, sizeof errw, hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);

@@ -48,16 +48,22 @@ enum : uint32_t { PREP_E_CYCLE = 2, PREP_E_RANGE = 3, PREP_E_DUP = 4, PREP_E_OVE
 // With `order` (DAG ids grouped by size class, class c at class_off[c]),
 // one launch per class; without, one launch sized for max_n.  DAGs above
 // 512 nodes use `lscratch` (prep_large_scratch_bytes of their largest size).
+// DAGs above 256 nodes (classes 3 and 4, one launch each) use `lscratch`,
+// which holds the larger of the two classes' prep_large_scratch_bytes.
 hipError_t launch_prep(const Tables& t, const PrepInputs& in, int32_t D, int32_t M, int32_t max_n,
                        const int32_t* order, const int32_t* class_off, unsigned long long* err,
-                       void* lscratch, int32_t large_max_n, int32_t large_max_e, hipStream_t stream);
+                       void* lscratch, const int32_t* class_max_n, const int32_t* class_max_e,
+                       hipStream_t stream);
 
-// Largest DAG the large-DAG kernels take, and the workgroups of their
-// preprocessing launch (each with its own scratch region).
+// Largest DAG the large-DAG kernels take, and the most workgroups of a
+// workgroup-per-DAG preprocessing launch (each with its own scratch region).
 constexpr int LARGE_MAX_N = 8000;
-constexpr int PREP_LARGE_GRID = 256;
-size_t prep_large_scratch_bytes(int32_t max_n, int32_t max_e);
-// Preprocessing of `count` DAGs above 512 nodes (ids from `list`, or 0..count-1).
+constexpr int PREP_LARGE_GRID = 512;
+// Global scratch of a workgroup-per-DAG preprocessing launch over `count`
+// DAGs of up to max_n nodes and max_e edges.
+size_t prep_large_scratch_bytes(int32_t count, int32_t max_n, int32_t max_e);
+// Workgroup-per-DAG preprocessing of `count` DAGs (ids from `list`, or
+// 0..count-1); resets the work counter err[2] on the stream first.
 hipError_t launch_prep_large(const Tables& t, const PrepInputs& in, int32_t count, int32_t M, const int32_t* list,
                              unsigned long long* err, void* scratch, int32_t max_n, int32_t max_e,
                              hipStream_t stream);

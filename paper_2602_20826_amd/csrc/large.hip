@@ -34,6 +34,7 @@
 // not fit in maxC * m is segmented, which stops the launching; finished
 // nodes decrement their successors' counts at once, and a count reaching
 // zero releases the successor when the slot ends.  All arithmetic is integer.
+#include <algorithm>
 #include <climits>
 
 #include "internal.h"
@@ -42,8 +43,7 @@ namespace dagbound {
 namespace {
 
 constexpr int WAVE = 64;
-constexpr int PT = 1024;  // threads of a preprocessing workgroup
-constexpr int PWAVES = PT / WAVE;
+constexpr int PT_MAX = 1024;  // threads of the largest preprocessing workgroup
 constexpr int ID_BITS = 13;  // local ids below 8192 in sort keys
 constexpr uint64_t ID_MASK = (1ull << ID_BITS) - 1;
 
@@ -164,7 +164,7 @@ __host__ __device__ inline PrepLds prep_lds(int NL) {
   l.wcl = o;   o += (size_t)NL * 4;                         // C_hat by local id
   l.cnt = o;   o += (size_t)NL * 4;                         // counts, cursors, blocks
   l.gflag = o; o += ((size_t)NL + 15) & ~(size_t)15;        // grouped flag by sigma rank
-  l.sel = o;   o += (size_t)PWAVES * ((NL + 63) / 64) * 8;  // per-wave selection masks
+  l.sel = o;   o += (size_t)(PT_MAX / WAVE) * ((NL + 63) / 64) * 8;  // per-wave selection masks
   l.misc = o;  o += 64 * 4;
   l.total = o;
   return l;
@@ -173,6 +173,7 @@ __host__ __device__ inline PrepLds prep_lds(int NL) {
 enum { M_ERR = 0, M_ITEM, M_TAIL, M_NTH, M_NG, M_SEG, M_NSEG, M_WTOT = 16 };  // misc words
 
 // Ascending bitonic sort of key[0, P) (P a power of two) by the workgroup.
+template <int PT>
 __device__ void bitonic_sort(uint64_t* key, int P) {
   for (int k = 2; k <= P; k <<= 1) {
     for (int j = k >> 1; j > 0; j >>= 1) {
@@ -193,8 +194,9 @@ __device__ void bitonic_sort(uint64_t* key, int P) {
 
 // Exclusive prefix sums of f(0..n-1) into out[], by the workgroup; returns
 // the total.  Each thread takes a run of consecutive items.
-template <class F>
+template <int PT, class F>
 __device__ uint32_t block_scan(int n, F f, uint32_t* out, uint32_t* wtot) {
+  constexpr int PWAVES = PT / WAVE;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int per = (n + PT - 1) / PT;
   const int i0 = tid * per, i1 = min(n, i0 + per);
@@ -302,8 +304,10 @@ __device__ int group_block(const Tables& t, int64_t n0, int a, int b, int32_t M,
 }
 
 // One DAG.  Every thread of the workgroup calls it and returns together.
+template <int PT>
 __device__ void prep_one(const Tables& t, const PrepInputs& in, int32_t M, int d, unsigned long long* err,
                          const PrepScratch& S, unsigned char* smem, const PrepLds& L) {
+  constexpr int PWAVES = PT / WAVE;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   uint64_t* key = (uint64_t*)(smem + L.key);
   uint32_t* wcl = (uint32_t*)(smem + L.wcl);
@@ -388,8 +392,8 @@ __device__ void prep_one(const Tables& t, const PrepInputs& in, int32_t M, int d
   }
 
   // CSR lists of predecessors and successors.
-  const uint32_t ne = block_scan(N, [&](int i) { return cnt[i]; }, S.predoff, wtot);
-  block_scan(N, [&](int i) { return S.outc[i]; }, S.succoff, wtot);
+  const uint32_t ne = block_scan<PT>(N, [&](int i) { return cnt[i]; }, S.predoff, wtot);
+  block_scan<PT>(N, [&](int i) { return S.outc[i]; }, S.succoff, wtot);
   if (tid == 0) {
     S.predoff[N] = ne;
     S.succoff[N] = ne;
@@ -481,7 +485,7 @@ __device__ void prep_one(const Tables& t, const PrepInputs& in, int32_t M, int d
   }
   for (int v = N + tid; v < P; v += PT) key[v] = ~0ull;
   __syncthreads();
-  bitonic_sort(key, P);
+  bitonic_sort<PT>(key, P);
   for (int s = tid; s < N; s += PT) {
     const int v = (int)(key[s] & ID_MASK);
     S.perm[s] = (uint16_t)v;
@@ -498,7 +502,7 @@ __device__ void prep_one(const Tables& t, const PrepInputs& in, int32_t M, int d
     key[v] = k;
   }
   __syncthreads();
-  bitonic_sort(key, P);
+  bitonic_sort<PT>(key, P);
   const int nth = (int)misc[M_NTH];
 
   // Eq. 3: the block of v is the first k (Theta order) with v in
@@ -559,12 +563,12 @@ __device__ void prep_one(const Tables& t, const PrepInputs& in, int32_t M, int d
   // per nonempty block, segments taken by wavefronts.
   for (int s = tid; s < P; s += PT) key[s] = s < N ? (((uint64_t)S.blk[s] << ID_BITS) | (uint64_t)s) : ~0ull;
   __syncthreads();
-  bitonic_sort(key, P);
+  bitonic_sort<PT>(key, P);
   for (int i = tid; i < N; i += PT) S.blist[i] = (uint16_t)(key[i] & ID_MASK);
   auto starts = [&](int i) -> uint32_t {
     return (i == 0 || (key[i] >> ID_BITS) != (key[i - 1] >> ID_BITS)) ? 1u : 0u;
   };
-  const uint32_t nseg = block_scan(N, starts, S.segs, wtot);
+  const uint32_t nseg = block_scan<PT>(N, starts, S.segs, wtot);
   for (int i = tid; i < N; i += PT)
     if (starts(i)) S.topo[S.segs[i]] = (uint16_t)i;
   __syncthreads();
@@ -604,7 +608,7 @@ __device__ void prep_one(const Tables& t, const PrepInputs& in, int32_t M, int d
   }
   uint32_t* soff = t.soff + n0 + d;
   const uint32_t tot =
-      block_scan(N, [&](int s) { const int v = S.perm[s]; return S.succoff[v + 1] - S.succoff[v]; }, soff, wtot);
+      block_scan<PT>(N, [&](int s) { const int v = S.perm[s]; return S.succoff[v + 1] - S.succoff[v]; }, soff, wtot);
   if (tid == 0) soff[N] = tot;
   for (int s = tid; s < N; s += PT) {
     const int u = S.perm[s];
@@ -619,11 +623,13 @@ __device__ void prep_one(const Tables& t, const PrepInputs& in, int32_t M, int d
       }
       out[j] = x;
     }
-    t.nrec[n0 + s] = make_uint4(wcl[u], min(S.par[u], (uint32_t)M) | ((uint32_t)s << 16), soff[s],
-                                (uint32_t)u | ((a1 - a0) << 16));
+    if (t.nrec)
+      t.nrec[n0 + s] = make_uint4(wcl[u], min(S.par[u], (uint32_t)M) | ((uint32_t)s << 16), soff[s],
+                                  (uint32_t)u | ((a1 - a0) << 16));
   }
   __syncthreads();
-  // member records in group order
+  // member records in group order (batches with DAGs above 512 nodes)
+  if (!t.mrec) return;
   for (int k = tid; k < N; k += PT) {
     const uint32_t g = t.gl[n0 + k];
     uint4 r = t.nrec[n0 + (g & 0x7FFF)];
@@ -632,6 +638,7 @@ __device__ void prep_one(const Tables& t, const PrepInputs& in, int32_t M, int d
   }
 }
 
+template <int PT>
 __global__ __launch_bounds__(PT) void k_prep_large(Tables t, PrepInputs in, int32_t M, const int32_t* list,
                                                    int32_t count, unsigned long long* err, unsigned char* scratch,
                                                    int32_t NL, int32_t EL) {
@@ -645,7 +652,7 @@ __global__ __launch_bounds__(PT) void k_prep_large(Tables t, PrepInputs in, int3
     __syncthreads();
     const uint32_t item = misc[M_ITEM];
     if (item >= (uint32_t)count) break;
-    prep_one(t, in, M, list ? list[item] : (int)item, err, S, smem, L);
+    prep_one<PT>(t, in, M, list ? list[item] : (int)item, err, S, smem, L);
     __syncthreads();
   }
 }
@@ -1036,23 +1043,39 @@ hipError_t launch_large_c(const SweepArgs& a, unsigned long long* counter, uint6
 
 }  // namespace
 
-size_t prep_large_scratch_bytes(int32_t max_n, int32_t max_e) {
-  return prep_scratch(nullptr, max_n, max(max_e, 1)).bytes;
+// Workgroups of one preprocessing launch: 512 threads (two workgroups per
+// compute unit) for DAGs up to 512 nodes, 1024 threads (one per compute
+// unit, whose LDS the largest DAGs fill) above.
+static int prep_large_grid(int32_t count, int32_t max_n) {
+  return std::max(0, std::min(count, max_n <= 512 ? PREP_LARGE_GRID : PREP_LARGE_GRID / 2));
+}
+
+size_t prep_large_scratch_bytes(int32_t count, int32_t max_n, int32_t max_e) {
+  return (size_t)prep_large_grid(count, max_n) * prep_scratch(nullptr, max_n, std::max(max_e, 1)).bytes;
 }
 
 size_t eval_large_lds_bytes(int max_n) { return eval_lds(max_n, false, false).total; }
 
+template <int PT>
+static hipError_t launch_prep_pt(const Tables& t, const PrepInputs& in, int32_t count, int32_t M, const int32_t* list,
+                                 unsigned long long* err, void* scratch, int32_t NL, int32_t EL, hipStream_t stream) {
+  const size_t lds = prep_lds(NL).total;
+  hipError_t e = hipFuncSetAttribute((const void*)k_prep_large<PT>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_prep_large<PT>, dim3(prep_large_grid(count, NL)), dim3(PT), lds, stream, t, in, M, list,
+                     count, err, (unsigned char*)scratch, NL, std::max(EL, 1));
+  return hipGetLastError();
+}
+
 hipError_t launch_prep_large(const Tables& t, const PrepInputs& in, int32_t count, int32_t M, const int32_t* list,
                              unsigned long long* err, void* scratch, int32_t NL, int32_t EL, hipStream_t stream) {
   if (count <= 0) return hipSuccess;
-  if (NL > LARGE_MAX_N || !scratch || !t.mrec || !t.nrec) return hipErrorInvalidValue;
-  const size_t lds = prep_lds(NL).total;
-  hipError_t e = hipFuncSetAttribute((const void*)k_prep_large, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (NL > LARGE_MAX_N || !scratch) return hipErrorInvalidValue;
+  hipError_t e = hipMemsetAsync(err + 2, 0, sizeof(unsigned long long), stream);  // work counter
   if (e != hipSuccess) return e;
-  const int grid = min(count, PREP_LARGE_GRID);
-  hipLaunchKernelGGL(k_prep_large, dim3(grid), dim3(PT), lds, stream, t, in, M, list, count, err,
-                     (unsigned char*)scratch, NL, max(EL, 1));
-  return hipGetLastError();
+  return NL <= 512 ? launch_prep_pt<512>(t, in, count, M, list, err, scratch, NL, EL, stream)
+                   : launch_prep_pt<1024>(t, in, count, M, list, err, scratch, NL, EL, stream);
 }
 
 hipError_t launch_eval_large(const SweepArgs& a, uint32_t* counter, hipStream_t stream) {

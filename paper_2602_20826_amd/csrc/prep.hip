@@ -502,7 +502,8 @@ hipError_t launch_prep_nw(const Tables& t, const PrepInputs& in, int32_t count, 
 
 hipError_t launch_prep(const Tables& t, const PrepInputs& in, int32_t D, int32_t M, int32_t max_n,
                        const int32_t* order, const int32_t* class_off, unsigned long long* err,
-                       void* lscratch, int32_t large_max_n, int32_t large_max_e, hipStream_t stream) {
+                       void* lscratch, const int32_t* class_max_n, const int32_t* class_max_e,
+                       hipStream_t stream) {
   if (D <= 0) return hipSuccess;
   if (max_n > LARGE_MAX_N) return hipErrorInvalidValue;
   if (!order) {  // one launch sized for the largest DAG
@@ -514,12 +515,13 @@ hipError_t launch_prep(const Tables& t, const PrepInputs& in, int32_t D, int32_t
       default: return hipErrorInvalidValue;  // large DAGs need their class's scratch sizes
     }
   }
-  // DAGs above 128 nodes (whose bitsets are large) get a launch per size
-  // class, largest first; the rest share one launch sized for 128 nodes
-  hipError_t e = launch_prep_large(t, in, class_off[5] - class_off[4], M, order + class_off[4], err, lscratch,
-                                   large_max_n, large_max_e, stream);
-  if (e == hipSuccess)
-    e = launch_prep_nw<8>(t, in, class_off[4] - class_off[3], M, order + class_off[3], err, stream);
+  // DAGs above 256 nodes go to the workgroup-per-DAG kernel (large.hip), one
+  // launch per class, largest first; those of 129-256 nodes get a launch of
+  // their own, and the rest share one launch sized for 128 nodes
+  hipError_t e = hipSuccess;
+  for (int c = LARGE_CLASS; c >= 3 && e == hipSuccess; c--)
+    e = launch_prep_large(t, in, class_off[c + 1] - class_off[c], M, order + class_off[c], err, lscratch,
+                          class_max_n[c], class_max_e[c], stream);
   if (e == hipSuccess)
     e = launch_prep_nw<4>(t, in, class_off[3] - class_off[2], M, order + class_off[2], err, stream);
   if (e == hipSuccess) {
