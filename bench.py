@@ -249,6 +249,51 @@ def large_block(torch, db, W, n_train: int, n_test_first: int, test, epochs: int
     return res
 
 
+SUR_GEMM_FLOP_PER_NODE = 3 * 2 * 256 * 128  # three layers of [H | mean of neighbours] (256) x W (256 x 128)
+BF16_PEAK_TFLOPS = 2500.0
+
+
+def surrogate_probe(n_dags: int, reps: int = 5) -> int:
+    """Forward pass of the learned proposal's encoder over n_dags learned-
+    proposal DAGs (a fresh model), timed with HIP events on the launching
+    stream: the layer GEMMs' FLOPs over the whole forward time are a lower
+    bound on the MFMA rate (the kernel-trace summary gives the GEMM kernel's
+    own time)."""
+    import torch
+
+    import paper_2602_20826_amd as db
+    import workloads as W
+
+    db.load_library()
+    wl = W.WORKLOADS[4]
+    batch = W.generate_workload(4, count=n_dags)
+    dev = torch.device("cuda:0")
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    st = torch.cuda.current_stream(dev)
+    b = db.create_batch(t(batch.node_off), t(batch.edge_off), t(batch.src), t(batch.dst), t(batch.wcet),
+                        t(batch.par), wl.num_cus, stream=st)
+    model = db.Model(1)
+    rows = int(batch.node_off[-1])
+    out = torch.empty(rows * 3, dtype=torch.float32, device=dev)
+    db.model_forward(model, b, out, stream=st)
+    ms = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        db.model_forward(model, b, out, stream=st)
+        e1.record(st)
+        torch.cuda.synchronize()
+        ms.append(e0.elapsed_time(e1))
+    model.close()
+    b.close()
+    f = float(np.mean(ms))
+    flop = rows * SUR_GEMM_FLOP_PER_NODE
+    print(json.dumps({"surrogate_forward": {"dags": n_dags, "nodes": rows, "ms": f, "gemm_flop": flop,
+                                            "gemm_tflops_over_forward": flop / f / 1e9,
+                                            "bf16_peak_tflops": BF16_PEAK_TFLOPS}}), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -269,6 +314,8 @@ def main() -> int:
     ap.add_argument("--search-test", type=int, default=100000, help="held-out DAGs (x 4096 seeded candidates)")
     ap.add_argument("--large-train", type=int, default=2000, help="large-compiler training DAGs (x 256)")
     ap.add_argument("--large-epochs", type=int, default=20, help="large-compiler training epochs")
+    ap.add_argument("--surrogate-probe", type=int, default=0, metavar="DAGS",
+                    help="time the surrogate encoder's forward pass over DAGS learned-proposal DAGs")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="one copy of known size plus one evaluation launch, for counter passes")
     ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -278,6 +325,8 @@ def main() -> int:
         return write_traffic(*args.write_traffic)
     if args.traffic_probe:
         return traffic_probe()
+    if args.surrogate_probe:
+        return surrogate_probe(args.surrogate_probe)
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
               "(DAGs are independent: a multi-GPU run would shard the batch by DAG)", file=sys.stderr)

@@ -801,12 +801,13 @@ dagbound_status model_workspace(dagbound_model* m, const dagbound_batch* b, SurA
   s->X = c.take<float>((size_t)R * SUR_FIN);
   s->A = c.take<float>((size_t)R * SUR_OUT);
   for (int l = 0; l <= SUR_LAYERS; l++) s->H[l] = c.take<__bf16>((size_t)R * SUR_HID);
-  for (int l = 0; l < SUR_LAYERS; l++) s->G[l] = c.take<__bf16>((size_t)R * SUR_HID);
+  s->G[0] = c.take<__bf16>((size_t)R * SUR_HID);
   s->dag_of = c.take<int32_t>((size_t)R);
   s->nboff = c.take<uint32_t>((size_t)(R + D));
   s->nb = c.take<uint16_t>((size_t)b->te * 2);
   s->loss_part = c.take<float>((size_t)D);
   if (train) {
+    for (int l = 1; l < SUR_LAYERS; l++) s->G[l] = c.take<__bf16>((size_t)R * SUR_HID);
     s->dA = c.take<float>((size_t)R * SUR_OUT);
     s->dZ[0] = c.take<__bf16>((size_t)R * SUR_HID);
     s->dZ[1] = c.take<__bf16>((size_t)R * SUR_HID);
@@ -913,25 +914,22 @@ dagbound_status dagbound_model_forward(dagbound_model* m, dagbound_batch* b, flo
   if (rc != DAGBOUND_OK) return rc;
   hipError_t e = sur_features(s, st);
   if (e == hipSuccess) e = sur_forward(s, st);
-  // A rows are in sigma order: copy to the caller in local-id order
-  std::vector<float> hA((size_t)b->tn * SUR_OUT);
-  std::vector<uint16_t> inv((size_t)b->tn);
-  if (e == hipSuccess && b->tn > 0) e = hipMemcpyAsync(hA.data(), s.A, hA.size() * 4, hipMemcpyDeviceToHost, st);
-  if (e == hipSuccess && b->tn > 0) e = hipMemcpyAsync(inv.data(), b->t.inv, inv.size() * 2, hipMemcpyDeviceToHost, st);
-  if (e == hipSuccess) e = hipStreamSynchronize(st);
-  if (e != hipSuccess) return hip_fail(e, "surrogate forward");
-  std::vector<float> out((size_t)b->tn * 3);
-  for (int32_t d = 0; d < b->D; d++)
-    for (int64_t v = 0; v < b->node_off[d + 1] - b->node_off[d]; v++) {
-      const int64_t n0 = b->node_off[d];
-      const int64_t srow = n0 + inv[(size_t)(n0 + v)];
-      for (int j = 0; j < 3; j++) out[(size_t)(n0 + v) * 3 + j] = hA[(size_t)srow * SUR_OUT + j];
-    }
-  if (b->tn > 0) {
-    if (ptr_kind == DAGBOUND_PTR_HOST) memcpy(node_out, out.data(), out.size() * 4);
-    else if ((e = hipMemcpy(node_out, out.data(), out.size() * 4, hipMemcpyHostToDevice)) != hipSuccess)
-      return hip_fail(e, "copying node outputs");
+  // A rows are in sigma order: the caller gets them in local-id order
+  float* dout = node_out;
+  void* tmp = nullptr;
+  size_t tmp_size = 0;
+  if (e == hipSuccess && ptr_kind == DAGBOUND_PTR_HOST && b->tn > 0) {
+    tmp_size = (size_t)b->tn * 12;
+    e = dev_alloc(&tmp, &tmp_size, m->device);
+    dout = (float*)tmp;
   }
+  if (e == hipSuccess) e = sur_output_local(s, dout, st);
+  if (e == hipSuccess && ptr_kind == DAGBOUND_PTR_HOST && b->tn > 0)
+    e = hipMemcpyAsync(node_out, dout, (size_t)b->tn * 12, hipMemcpyDeviceToHost, st);
+  const hipError_t es = hipStreamSynchronize(st);  // documented to wait for its work
+  if (e == hipSuccess) e = es;
+  if (tmp) dev_release(tmp, tmp_size, m->device);
+  if (e != hipSuccess) return hip_fail(e, "surrogate forward");
   return DAGBOUND_OK;
 }
 

@@ -210,6 +210,8 @@ hipError_t sur_head_train(const SurArgs& s, int32_t K, uint64_t seed, const int6
 hipError_t sur_backward(const SurArgs& s, hipStream_t st);
 hipError_t sur_adam(const SurArgs& s, float lr, int64_t step, hipStream_t st);
 hipError_t sur_refresh_weights(const SurArgs& s, hipStream_t st);
+// Head coefficients [T_N][3] in local-id order (device pointer).
+hipError_t sur_output_local(const SurArgs& s, float* out, hipStream_t st);
 hipError_t sur_select(const SurArgs& s, int32_t K, uint64_t seed, int32_t T, int32_t top_k, float* scores,
                       int32_t* cand, hipStream_t st);
 

@@ -15,6 +15,8 @@
 //
 // Node rows of every activation array use the batch's node index in sigma
 // order (node_off[d] + sigma rank).
+#include <algorithm>
+
 #include "internal.h"
 
 namespace dagbound {
@@ -150,7 +152,8 @@ __global__ void k_l0_fwd(const float* X, const float* W0, const float* b0, int64
 }
 
 // G = mean over neighbours of H (zero without neighbours): one thread per
-// (node, 8 columns).
+// (node, 8 columns), four neighbour rows loaded together; FP32 sums in list
+// order, one BF16 rounding.
 __global__ void k_agg_fwd(const bf16* H, const int32_t* dag_of, const int64_t* node_off,
                           const uint32_t* nboff, const uint16_t* nb, const int64_t* edge_off,
                           int64_t rows, bf16* G) {
@@ -163,9 +166,26 @@ __global__ void k_agg_fwd(const bf16* H, const int32_t* dag_of, const int64_t* n
   const int s = (int)(r - n0);
   const uint32_t a0 = nboff[n0 + d + s], a1 = nboff[n0 + d + s + 1];
   const uint16_t* list = nb + 2 * edge_off[d];
+  const bf16* Hd = H + n0 * HID + c0;
   float acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  for (uint32_t e = a0; e < a1; e++) {
-    const bf16x8 h = *(const bf16x8*)(H + (n0 + list[e]) * HID + c0);
+  uint32_t e = a0;
+  for (; e + 4 <= a1; e += 4) {
+    const uint32_t i0 = list[e], i1 = list[e + 1], i2 = list[e + 2], i3 = list[e + 3];
+    const bf16x8 h0 = *(const bf16x8*)(Hd + (int64_t)i0 * HID);
+    const bf16x8 h1 = *(const bf16x8*)(Hd + (int64_t)i1 * HID);
+    const bf16x8 h2 = *(const bf16x8*)(Hd + (int64_t)i2 * HID);
+    const bf16x8 h3 = *(const bf16x8*)(Hd + (int64_t)i3 * HID);
+#pragma unroll
+    for (int j = 0; j < 8; j++) acc[j] += bf2f(h0[j]);
+#pragma unroll
+    for (int j = 0; j < 8; j++) acc[j] += bf2f(h1[j]);
+#pragma unroll
+    for (int j = 0; j < 8; j++) acc[j] += bf2f(h2[j]);
+#pragma unroll
+    for (int j = 0; j < 8; j++) acc[j] += bf2f(h3[j]);
+  }
+  for (; e < a1; e++) {
+    const bf16x8 h = *(const bf16x8*)(Hd + (int64_t)list[e] * HID);
 #pragma unroll
     for (int j = 0; j < 8; j++) acc[j] += bf2f(h[j]);
   }
@@ -178,10 +198,10 @@ __global__ void k_agg_fwd(const bf16* H, const int32_t* dag_of, const int64_t* n
 
 // C[rows x NT*32] = epilogue(sum over parts A_p[rows x 128] B_p), B given
 // transposed: Bt[n][k] (k over the parts' 128-wide blocks, KD = 128*parts).
-// One workgroup of 4 wavefronts covers 128 rows; a wavefront computes 32 rows
-// x NT*32 columns with MFMA 32x32x16 (BF16 in, FP32 accumulate).  Bt sits in
-// LDS with rows padded by 16 bytes so the 32 rows a k-step reads spread over
-// the banks.  Epilogue: +bias, relu, store BF16 (mode 0); or store FP32
+// A workgroup of 4 wavefronts loads Bt into LDS once and then covers tiles
+// of 128 rows (persistent over the row tiles); a wavefront computes 32 rows
+// x NT*32 columns with MFMA 32x32x16 (BF16 in, FP32 accumulate).  Bt's rows
+// are padded by 16 bytes so the 32 rows a k-step reads spread over the banks.  Epilogue: +bias, relu, store BF16 (mode 0); or store FP32
 // (mode 1).
 template <int NT, int KD>
 __global__ __launch_bounds__(256) void k_gemm_rows(const bf16* A0, const bf16* A1, const bf16* Bt,
@@ -198,22 +218,30 @@ __global__ __launch_bounds__(256) void k_gemm_rows(const bf16* A0, const bf16* A
   }
   __syncthreads();
   const int wave = tid >> 6, lane = tid & 63;
-  const int64_t r0 = (int64_t)blockIdx.x * 128 + wave * 32;
+  const int64_t ntiles = (rows + 127) / 128;
+  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+  const int64_t r0 = tile * 128 + wave * 32;
   const int64_t ra = r0 + (lane & 31);
   const int kh = (lane >> 5) * 8;
   f16v acc[NT];
 #pragma unroll
   for (int t = 0; t < NT; t++) acc[t] = (f16v){};
-#pragma unroll 2
-  for (int kk = 0; kk < KD; kk += 16) {
-    const bf16* Ap = kk < 128 ? A0 : A1;
-    const int ka = (kk & 127) + kh;
-    bf16x8 a = (bf16x8){};
-    if (ra < rows) a = *(const bf16x8*)(Ap + ra * 128 + ka);
+  // every A fragment of the tile is loaded before the first MFMA, so the
+  // row loads are in flight together
+  bf16x8 af[KD / 16];
+#pragma unroll
+  for (int q = 0; q < KD / 16; q++) {
+    const int kk = q * 16;
+    af[q] = (bf16x8){};
+    if (ra < rows) af[q] = *(const bf16x8*)((kk < 128 ? A0 : A1) + ra * 128 + (kk & 127) + kh);
+  }
+#pragma unroll
+  for (int q = 0; q < KD / 16; q++) {
+    const int kk = q * 16;
 #pragma unroll
     for (int t = 0; t < NT; t++) {
       const bf16x8 b = *(const bf16x8*)(sB + (t * 32 + (lane & 31)) * LDB + kk + kh);
-      acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc[t], 0, 0, 0);
+      acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[q], b, acc[t], 0, 0, 0);
     }
   }
 #pragma unroll
@@ -229,6 +257,7 @@ __global__ __launch_bounds__(256) void k_gemm_rows(const bf16* A0, const bf16* A
         else outf[row * NC + col] = v;
       }
     }
+  }
   }
 }
 
@@ -600,6 +629,17 @@ __global__ __launch_bounds__(64) void k_head_select(Tables t, const float* A, in
   }
 }
 
+// Head coefficients in local-id order: out[n0 + v][j] = A[n0 + sigma(v)][j].
+__global__ void k_out_local(const float* A, const int32_t* dag_of, const int64_t* node_off, const uint16_t* inv,
+                            int64_t rows, float* out) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= rows) return;
+  const int64_t n0 = node_off[dag_of[r]];
+  const int64_t src = n0 + inv[r];
+#pragma unroll
+  for (int j = 0; j < 3; j++) out[r * 3 + j] = A[src * SUR_OUT + j];
+}
+
 __global__ void k_dag_of(const int64_t* node_off, int32_t D, int32_t* dag_of) {
   const int d = blockIdx.x;
   if (d >= D) return;
@@ -607,6 +647,15 @@ __global__ void k_dag_of(const int64_t* node_off, int32_t D, int32_t* dag_of) {
 }
 
 inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+// Workgroups of a persistent row-tile GEMM: two per compute unit (their
+// LDS weight copies fill most of it), at most one per tile.
+inline unsigned gemm_grid(int64_t rows) {
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    cus = 256;
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>((rows + 127) / 128, 2 * (int64_t)cus));
+}
 
 }  // namespace
 
@@ -617,8 +666,9 @@ size_t sur_node_bytes() {
 }
 
 size_t sur_node_grad_bytes() {
-  // dA (4 fp32) + dZ x 2 (bf16 x 128) + DT (256 fp32)
-  return 4 * 4 + 2 * 128 * 2 + 256 * 4;
+  // G of layers 2 and 3 (inference reuses the first for every layer) + dA
+  // (4 fp32) + dZ x 2 (bf16 x 128) + DT (256 fp32)
+  return 2 * 128 * 2 + 4 * 4 + 2 * 128 * 2 + 256 * 4;
 }
 
 hipError_t sur_features(const SurArgs& s, hipStream_t st) {
@@ -637,13 +687,17 @@ hipError_t sur_forward(const SurArgs& s, hipStream_t st) {
   e = hipFuncSetAttribute((const void*)k_gemm_rows<4, 256>, hipFuncAttributeMaxDynamicSharedMemorySize,
                           (int)lds_f);
   if (e != hipSuccess) return e;
+  const unsigned grid = gemm_grid(R);
+  // G is kept for the backward pass when training (dA allocated); inference
+  // reuses one buffer for every layer
   for (int l = 0; l < SUR_LAYERS; l++) {
+    bf16* G = s.dA ? s.G[l] : s.G[0];
     hipLaunchKernelGGL(k_agg_fwd, dim3(blocks_for(R * 16, 256)), dim3(256), 0, st, s.H[l], s.dag_of,
-                       s.t.node_off, s.nboff, s.nb, s.t.edge_off, R, s.G[l]);
-    hipLaunchKernelGGL((k_gemm_rows<4, 256>), dim3(blocks_for(R, 128)), dim3(256), lds_f, st, s.H[l],
-                       s.G[l], s.wfwd + (int64_t)l * 256 * 128,
-                       s.p + SUR_OFF_L1 + (int64_t)l * SUR_LAYER_STRIDE + 2 * HID * HID, R, 0,
-                       s.H[l + 1], (float*)nullptr);
+                       s.t.node_off, s.nboff, s.nb, s.t.edge_off, R, G);
+    hipLaunchKernelGGL((k_gemm_rows<4, 256>), dim3(grid), dim3(256), lds_f, st, s.H[l], G,
+                       s.wfwd + (int64_t)l * 256 * 128,
+                       s.p + SUR_OFF_L1 + (int64_t)l * SUR_LAYER_STRIDE + 2 * HID * HID, R, 0, s.H[l + 1],
+                       (float*)nullptr);
   }
   hipLaunchKernelGGL(k_out_fwd, dim3(blocks_for(R, 256)), dim3(256), 0, st, s.H[SUR_LAYERS],
                      s.p + SUR_OFF_WA, s.p + SUR_OFF_BA, R, s.A);
@@ -679,7 +733,7 @@ hipError_t sur_backward(const SurArgs& s, hipStream_t st) {
                        s.dZ[cur], (const float*)nullptr, R, chunk, s.partial2, 128);
     hipLaunchKernelGGL(k_reduce, dim3(1), dim3(128), 0, st, s.partial2, nchunk, 128, gl + 2 * HID * HID);
     // data gradient: [D | T] = dZ [Ws^T | Wm^T], then aggregate and mask
-    hipLaunchKernelGGL((k_gemm_rows<8, 128>), dim3(blocks_for(R, 128)), dim3(256), lds_b, st, s.dZ[cur],
+    hipLaunchKernelGGL((k_gemm_rows<8, 128>), dim3(gemm_grid(R)), dim3(256), lds_b, st, s.dZ[cur],
                        (const bf16*)nullptr, s.wbwd + (int64_t)l * 256 * 128, (const float*)nullptr, R, 1,
                        (bf16*)nullptr, s.DT);
     hipLaunchKernelGGL(k_agg_bwd, dim3(blocks_for(R * 16, 256)), dim3(256), 0, st, s.DT, s.H[l], s.dag_of,
@@ -718,6 +772,13 @@ hipError_t sur_adam(const SurArgs& s, float lr, int64_t step, hipStream_t st) {
 
 hipError_t sur_refresh_weights(const SurArgs& s, hipStream_t st) {
   hipLaunchKernelGGL(k_weights_bf16, dim3(32, SUR_LAYERS), dim3(256), 0, st, s.p, s.wfwd, s.wbwd);
+  return hipGetLastError();
+}
+
+hipError_t sur_output_local(const SurArgs& s, float* out, hipStream_t st) {
+  if (s.rows <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_out_local, dim3(blocks_for(s.rows, 256)), dim3(256), 0, st, s.A, s.dag_of, s.t.node_off,
+                     s.t.inv, s.rows, out);
   return hipGetLastError();
 }
 

@@ -95,6 +95,10 @@ def compare_search(torch, model: db.Model, dags, M: int, K: int, seed: int, top_
                        stream=stream)  # warm
     t_sur = timed(lambda: db.best_allocation(b, idx, best_sur, search=db.SEARCH_SURROGATE, top_k=top_k,
                                              model=model, stream=stream))
+    # the encoder's forward pass alone (its layer GEMMs run on MFMA)
+    fwd = torch.empty(int(dags.node_off[-1]) * 3, dtype=torch.float32, device=dev)
+    t_fwd = timed(lambda: db.model_forward(model, b, fwd, stream=stream))
+    del fwd
     # paper's rule and plain random: candidates 0..top_k of the same seeded set
     db.set_allocations(b, top_k + 1, db.ALLOC_SEEDED, None, seed)
     small = torch.empty(D * (top_k + 1), dtype=torch.int64, device=dev)
@@ -116,6 +120,8 @@ def compare_search(torch, model: db.Model, dags, M: int, K: int, seed: int, top_
         "dags": D, "K": K, "top_k": top_k,
         "exhaustive_dags_per_s": D / t_exh, "surrogate_dags_per_s": D / t_sur,
         "speedup": t_exh / t_sur,
+        "forward_seconds": t_fwd,
+        "forward_gemm_tflops": int(dags.node_off[-1]) * 3 * 2 * 256 * 128 / t_fwd / 1e12,
         "gap_surrogate": gap(sur), "gap_paper_rule": gap(c0), "gap_random": gap(rnd),
         "gain_over_paper_rule_mean": float(np.mean(1.0 - sur / c0)),
         "gain_over_random_mean": float(np.mean(1.0 - sur / rnd)),
