@@ -668,14 +668,19 @@ __device__ inline uint32_t ceil_div(uint32_t a, uint32_t b) {
   if (SMALL) return ceil_div_small(a, b);
   return (uint32_t)(((uint64_t)a + b - 1) / b);
 }
-// round(cv * M / W) half up, exactly: floor((2 cv M + W) / (2 W)); a double
-// estimate is within one of the quotient and one integer step corrects it.
-__device__ inline uint32_t round_share(uint32_t cv, uint32_t M, uint64_t W) {
+// round(cv * M / W) half up, exactly: floor((2 cv M + W) / (2 W)) with
+// cv <= W.  The quotient is at most M + 1/2 < 2^16; the single-precision
+// estimate fma(2 cv, M, W) * rcp(2 W) has a relative error of a few 2^-24
+// (each input rounded once, the reciprocal within one ulp), so it is off by
+// less than 2^16 * 2^-21 < 1/32 and truncates to the quotient or one of its
+// neighbours; one exact 64-bit step corrects it.
+__device__ inline uint32_t round_share(uint32_t cv, uint32_t M, uint64_t W, float rw2) {
   const uint64_t num = 2ull * cv * M + W;
   const uint64_t den = 2ull * W;
-  uint32_t q = (uint32_t)((double)num / (double)den);
-  if ((uint64_t)(q + 1) * den <= num) q++;
-  else if ((uint64_t)q * den > num) q--;
+  uint32_t q = (uint32_t)(__builtin_fmaf(2.0f * (float)cv, (float)M, (float)W) * rw2);
+  const uint64_t pq = (uint64_t)q * den;
+  if (pq > num) q--;
+  else if (pq + den <= num) q++;
   return q;
 }
 // Counter-based candidate byte (the hash documented for seeded allocations).
@@ -844,8 +849,6 @@ __device__ void eval_one(const SweepArgs& a, uint64_t item, unsigned char* smem,
         kend = min(kend, N);
       }
     }
-    uint4 rnext = make_uint4(0u, 0u, 0u, 0u);
-    if (kend + lane < N) rnext = mrec[kend + lane];
     auto chunk = [&](int base) {
       uint4 r1 = rec;
       if (base != k) {
@@ -855,17 +858,38 @@ __device__ void eval_one(const SweepArgs& a, uint64_t item, unsigned char* smem,
       return r1;
     };
     // Pass 1: member set and W(pi_j), the remaining load of the released
-    // members (Eq. 5).
+    // members (Eq. 5).  A group of at most 64 members keeps each lane's
+    // remaining load for pass 2.
     uint64_t W = 0;
+    uint32_t cv0 = 0;
     for (int base = k; base < kend; base += WAVE) {
       const uint4 r1 = chunk(base);
       const int s = (r1.y >> 16) & 0x7FFF;
+      uint32_t cv = 0;
       if (base + lane < kend) {
         atomicOr((unsigned long long*)&gmw[s >> 6], 1ull << (s & 63));
-        if ((relw[s >> 6] >> (s & 63)) & 1) W += ((segw[s >> 6] >> (s & 63)) & 1) ? res[s] : r1.x;
+        if ((relw[s >> 6] >> (s & 63)) & 1) cv = ((segw[s >> 6] >> (s & 63)) & 1) ? res[s] : r1.x;
       }
+      if (base == k) cv0 = cv;
+      // 64 loads below 2^20 sum below 2^26
+      W += SMALL ? (uint64_t)wave_sum(cv) : wave_sum64(cv);
     }
-    W = wave_sum64(W);
+    // Loads for later phases are issued only now, after the loads this
+    // pass waited for (the vector-memory counter completes in order): the
+    // next group's records and the first two members' successor lists.
+    __builtin_amdgcn_sched_barrier(0);
+    uint4 rnext = make_uint4(0u, 0u, 0u, 0u);
+    if (kend + lane < N) rnext = mrec[kend + lane];
+    const int nm = min(kend - k, 2);
+    const uint32_t pz0 = (uint32_t)__builtin_amdgcn_readlane((int)rec.z, 0);
+    const uint32_t pd0 = (uint32_t)__builtin_amdgcn_readlane((int)rec.w, 0) >> 16;
+    const uint32_t pz1 = (uint32_t)__builtin_amdgcn_readlane((int)rec.z, 1);
+    const uint32_t pd1 = nm > 1 ? (uint32_t)__builtin_amdgcn_readlane((int)rec.w, 1) >> 16 : 0u;
+    int px0 = -1, px1 = -1;
+    if (W != 0) {
+      if ((uint32_t)lane < pd0) px0 = succ[pz0 + lane];
+      if ((uint32_t)lane < pd1) px1 = succ[pz1 + lane];
+    }
     wave_sync();
     if (W == 0) {
       // every member finished earlier (or is not released): nothing runs
@@ -891,35 +915,44 @@ __device__ void eval_one(const SweepArgs& a, uint64_t item, unsigned char* smem,
     }
     // Pass 2: parallelism (the candidate byte, or Eq. 5) and execution time
     // (Eq. 1) of each released member; the released members finish.
+    const float rw2 = __builtin_amdgcn_rcpf((float)(2ull * W));
     uint32_t maxC = 0, sm = 0;
     uint64_t A = 0;
     for (int base = k; base < kend; base += WAVE) {
       const uint4 r1 = chunk(base);
       const int s = (r1.y >> 16) & 0x7FFF;
       const bool rl = base + lane < kend && ((relw[s >> 6] >> (s & 63)) & 1);
+      uint64_t a1 = 0;
       if (rl) {
-        const bool sg = (segw[s >> 6] >> (s & 63)) & 1;
-        const uint32_t cv = sg ? res[s] : r1.x;
+        uint32_t cv = cv0;
+        if (base != k) cv = ((segw[s >> 6] >> (s & 63)) & 1) ? res[s] : r1.x;
         const uint32_t pp = r1.y & 0xFFFFu;
         const uint32_t mx = min(pp, cv);
         const uint32_t rv = r_of(s, r1.w & 0xFFFFu, pp);
-        const uint32_t m = rv ? min(rv, mx) : max(1u, min(mx, round_share(cv, M, W)));
+        const uint32_t m = rv ? min(rv, mx) : max(1u, min(mx, round_share(cv, M, W, rw2)));
         const uint32_t C = ceil_div<SMALL>(cv, m);
         maxC = max(maxC, C);
         sm += m;
-        A += (uint64_t)m * C;
+        a1 = (uint64_t)m * C;
       }
+      // m C < load + m < 2^21 for loads below 2^20: 64 of them sum below 2^27
+      A += SMALL ? (uint64_t)wave_sum((uint32_t)a1) : wave_sum64(a1);
       const uint64_t fl = __ballot(rl);
       if (rl) {
         const uint64_t bit = 1ull << (s & 63);
         atomicAnd((unsigned long long*)&relw[s >> 6], ~bit);
         atomicAnd((unsigned long long*)&segw[s >> 6], ~bit);
       }
-      release(fl, r1.z, r1.w);
+      if (base == k && (fl & ~3ull) == 0 && pd0 <= WAVE && pd1 <= WAVE) {
+        // the released members are among the first two: their lists are loaded
+        if ((fl & 1) && px0 >= 0) dec(px0);
+        if ((fl & 2) && px1 >= 0) dec(px1);
+      } else {
+        release(fl, r1.z, r1.w);
+      }
     }
     maxC = wave_max(maxC);
     sm = wave_sum(sm);
-    A = wave_sum64(A);
     wave_sync();
     // Eqs. 6-7: parallel nodes in sigma order take the spare units S; the
     // node at prefix P_i is reached while P_i < S and takes min(m, S - P_i);
@@ -1083,7 +1116,9 @@ hipError_t launch_eval_large(const SweepArgs& a, uint32_t* counter, hipStream_t 
   if (total == 0) return hipSuccess;
   if (a.max_n > LARGE_MAX_N || !a.t.mrec || !a.t.nrec) return hipErrorInvalidValue;
   unsigned long long* ctr = (unsigned long long*)counter;
-  const bool rs = a.alloc == nullptr;  // seeded bytes drawn where they are used
+  // seeded bytes are drawn where they are used: N bytes of LDS per
+  // wavefront would cost more in occupancy (measured) than the hashing
+  const bool rs = a.alloc == nullptr;
   if (a.small_loads)
     return rs ? launch_large_c<true, true>(a, ctr, total, stream) : launch_large_c<true, false>(a, ctr, total, stream);
   return rs ? launch_large_c<false, true>(a, ctr, total, stream) : launch_large_c<false, false>(a, ctr, total, stream);
