@@ -288,3 +288,43 @@ def test_large_compiler_full_size_sampled(torch_dev):
         assert cand[d, 0] == 0 and len(set(cand[d, 1:].tolist())) == top_k
         pos = int(np.argmin(want[i]))
         assert bb[d] == want[i, pos] and bi[d] == cand[d, pos], d
+
+
+def test_large_eval_in_a_captured_graph(torch_dev):
+    # the large-DAG launch (its work counter reset by a kernel) captured with
+    # the smaller classes on side streams; every replay equals the eager run
+    import paper_2602_20826_amd as db
+
+    torch, dev = torch_dev
+    batch = mixed_with_large()
+    M, K, seed = 256, 40, 31
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    st = torch.cuda.current_stream(dev)
+    b = db.create_batch(t(batch.node_off), t(batch.edge_off), t(batch.src), t(batch.dst), t(batch.wcet),
+                        t(batch.par), M, stream=st)
+    db.set_allocations(b, K, db.ALLOC_SEEDED, None, seed)
+    D = batch.num_dags
+    eager = torch.empty(D * K, dtype=torch.int64, device=dev)
+    db.eval_bounds(b, eager, stream=st)
+    torch.cuda.synchronize()
+    out = torch.zeros(D * K, dtype=torch.int64, device=dev)
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(st)
+    say("capturing eval_bounds with large DAGs")
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            db.eval_bounds(b, out, stream=s)
+    torch.cuda.synchronize()
+    ref = eager.cpu().numpy()
+    for rep in range(3):
+        out.fill_(-1)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        say("replay", rep)
+        assert np.array_equal(out.cpu().numpy(), ref), rep
+    want, _, _ = oracle.bounds_batch(batch, M, K, W.alloc_bytes(batch, M, K, seed=seed), threads=8)
+    assert np.array_equal(ref.reshape(D, K), want)
+    del g
+    b.close()
