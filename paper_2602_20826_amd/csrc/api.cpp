@@ -423,8 +423,12 @@ dagbound_status dagbound_create_batch(int32_t num_dags, const int64_t* node_off,
   PrepInputs in{edge_src, edge_dst, wcet, max_par};
   void* stage = nullptr;
   size_t stage_size = 0;
-  e = hipMemcpyAsync(d_no, no.data(), (D + 1) * 8, hipMemcpyHostToDevice, st);
-  if (e == hipSuccess) e = hipMemcpyAsync(d_eo, eo.data(), (D + 1) * 8, hipMemcpyHostToDevice, st);
+  // the offsets are already on the device when the caller passes device
+  // pointers: copy them there instead of back from the host copies
+  const hipMemcpyKind okind = ptr_kind == DAGBOUND_PTR_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  e = hipMemcpyAsync(d_no, ptr_kind == DAGBOUND_PTR_DEVICE ? (const void*)node_off : no.data(), (D + 1) * 8, okind, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(d_eo, ptr_kind == DAGBOUND_PTR_DEVICE ? (const void*)edge_off : eo.data(), (D + 1) * 8, okind, st);
   if (e == hipSuccess && D > 0)
     e = hipMemcpyAsync(b->order, b->order_host.data(), (size_t)D * 4, hipMemcpyHostToDevice, st);
   if (e == hipSuccess && ptr_kind == DAGBOUND_PTR_HOST && (tn + te) > 0) {
