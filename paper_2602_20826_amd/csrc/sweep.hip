@@ -524,7 +524,7 @@ __device__ bool eval_tile(const SweepArgs& a, int item, unsigned char* smem, uin
     uint32_t S = (W != 0 && sm < M) ? M - sm : 0u;
     uint64_t Q[NW], Lw[NW];
 #pragma unroll
-    for (int w = 0; w < NW; w++) { Q[w] = rel[w] & ~gm[w]; Lw[w] = Q[w]; }
+    for (int w = 0; w < NW; w++) Q[w] = rel[w] & ~gm[w];
     int cseg = -1;
     bool csg = false;
     uint32_t cleft = 0;
@@ -574,7 +574,7 @@ __device__ bool eval_tile(const SweepArgs& a, int item, unsigned char* smem, uin
     if (CURSOR) pq.rest(Q);
     if (cn >= 0) bit_set<NW>(Q, cn);  // read ahead, not launched
 #pragma unroll
-    for (int w = 0; w < NW; w++) Lw[w] &= ~Q[w];
+    for (int w = 0; w < NW; w++) Lw[w] = rel[w] & ~gm[w] & ~Q[w];  // taken from the walk's set
     if (cseg >= 0) bit_clear<NW>(Lw, cseg);
     if (cseg >= 0) {
       if (csg) {
@@ -692,17 +692,20 @@ __device__ bool eval_tile(const SweepArgs& a, int item, unsigned char* smem, uin
         }
       }
     } else {
-      while (bits_any<NW>(cand)) {  // four rows in flight
-        int u[4];
-        uint64_t pr[4][NW];
+      // rows in flight: two for four-word rows, one for eight-word rows (whose
+      // registers decide between one and two waves per SIMD)
+      constexpr int RIF = NW >= 8 ? 1 : 2;
+      while (bits_any<NW>(cand)) {
+        int u[RIF];
+        uint64_t pr[RIF][NW];
 #pragma unroll
-        for (int t = 0; t < 4; t++) u[t] = pop_first<NW>(cand);
+        for (int t = 0; t < RIF; t++) u[t] = pop_first<NW>(cand);
 #pragma unroll
-        for (int t = 0; t < 4; t++) {
+        for (int t = 0; t < RIF; t++) {
           if (u[t] >= 0) load_row<NW>(pr[t], s_pb + u[t] * NW);
         }
 #pragma unroll
-        for (int t = 0; t < 4; t++) {
+        for (int t = 0; t < RIF; t++) {
           if (u[t] >= 0) {
             uint64_t open = 0;
 #pragma unroll
@@ -773,8 +776,10 @@ __global__ __launch_bounds__(64) void k_eval(SweepArgs a, uint32_t* counters, ui
 // Persistent form of the first pass: as many workgroups as fit on the device
 // at once, each taking tiles from a work counter until all `total` are taken.
 // Every workgroup leaves the loop when the counter passes `total`.
+// At least two waves per SIMD: the eight-word-row class would otherwise take
+// one (a few spilled registers cost less than the lost latency hiding).
 template <int NW, bool SMALL, bool RS>
-__global__ __launch_bounds__(64) void k_eval_persistent(SweepArgs a, uint32_t* counters, uint32_t* list,
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_eval_persistent(SweepArgs a, uint32_t* counters, uint32_t* list,
                                                         int total) {
   extern __shared__ __align__(16) unsigned char smem[];
   uint64_t* grows = rows_of<NW>(a, blockIdx.x);
