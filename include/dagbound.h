@@ -170,6 +170,29 @@ dagbound_status dagbound_best_allocation(dagbound_batch* batch, uint32_t search,
                                          int64_t* best_bound, uint32_t ptr_kind, void* hip_stream);
 
 /*
+ * dagbound_get_schedule -- inspection of the schedule of DAG d under
+ * candidate c of the current allocation set (Algorithm 2 and Lemma 1 as the
+ * evaluation runs them), with the extra dependencies of Section 4.1 that
+ * the evaluation keeps implicit in the slot order.  Records of 8 int64,
+ * node ids DAG-local, a node's parts numbered from 0 in launch order:
+ *   PART {2, slot, node, part, kind (0 member, 1 parallel node launched
+ *         whole, 2 parallel segment), m, C, load}
+ *   SLOT {1, slot, members, maxC, sum m, A = sum m*C, R_j, v_R} after the
+ *         slot's parts (members 0 and v_R = -1 when every member finished
+ *         earlier)
+ *   EDGE {3, slot, from node, from part, to node, to part, 0, 0} after the
+ *         slot record: v_R to each parallel node not launched whole, and each
+ *         launched part to v_R's successors.
+ *   records  int64 [cap][8] host buffer (may be NULL when cap = 0); the first
+ *            min(cap, count) records are written.
+ *   count    receives the number of records of the schedule.
+ *   terms    int64 [3] or NULL: {bound, critical-path term, interference term}.
+ * Waits for the batch's work.  Errors: E_ARG, E_STATE, E_DEVICE.
+ */
+dagbound_status dagbound_get_schedule(dagbound_batch* batch, int32_t d, int32_t c, int64_t* records, int64_t cap,
+                                      int64_t* count, int64_t* terms);
+
+/*
  * dagbound_get_division -- inspection of DAG d's sub-graph division as the
  * GPU computed it (host outputs, each may be NULL).
  *   wanc       int64 [N_d]: W^anc of each local node (Eq. 2).

@@ -695,6 +695,41 @@ dagbound_status dagbound_get_division(dagbound_batch* b, int32_t d, int64_t* wan
   return DAGBOUND_OK;
 }
 
+dagbound_status dagbound_get_schedule(dagbound_batch* b, int32_t d, int32_t c, int64_t* records, int64_t cap,
+                                      int64_t* count, int64_t* terms) {
+  g_err.clear();
+  if (!b) return fail(DAGBOUND_E_ARG, "batch is NULL");
+  if (d < 0 || d >= b->D) return fail(DAGBOUND_E_ARG, "DAG index %d outside [0, %d)", d, b->D);
+  if (!b->has_alloc) return fail(DAGBOUND_E_STATE, "set_allocations has not been called");
+  if (c < 0 || c >= b->K) return fail(DAGBOUND_E_ARG, "candidate %d outside [0, %d)", c, b->K);
+  if (cap < 0 || (cap > 0 && !records)) return fail(DAGBOUND_E_ARG, "bad record buffer");
+  DeviceGuard g(b->device);
+  void* tmp = nullptr;
+  size_t tmp_size = 256 + 64 + (size_t)cap * 64;
+  hipError_t e = dev_alloc(&tmp, &tmp_size, b->device);
+  if (e != hipSuccess) return hip_fail(e, "allocating schedule records");
+  Carve cv(tmp);
+  int64_t* d_out = cv.take<int64_t>(4);
+  int64_t* d_rec = cv.take<int64_t>((size_t)cap * 8);
+  e = hipDeviceSynchronize();
+  if (e == hipSuccess)
+    e = launch_schedule(b->t, d, c, b->K, b->M, b->mode == DAGBOUND_ALLOC_EXPLICIT ? b->alloc : nullptr, b->seed,
+                        b->max_n, d_rec, cap, d_out, nullptr);
+  int64_t out[4] = {0, 0, 0, 0};
+  if (e == hipSuccess) e = hipMemcpy(out, d_out, sizeof out, hipMemcpyDeviceToHost);
+  if (e == hipSuccess && cap > 0 && out[0] > 0)
+    e = hipMemcpy(records, d_rec, (size_t)std::min<int64_t>(out[0], cap) * 64, hipMemcpyDeviceToHost);
+  dev_release(tmp, tmp_size, b->device);
+  if (e != hipSuccess) return hip_fail(e, "schedule dump");
+  if (count) *count = out[0];
+  if (terms) {
+    terms[0] = out[1];
+    terms[1] = out[2];
+    terms[2] = out[3];
+  }
+  return DAGBOUND_OK;
+}
+
 dagbound_status dagbound_set_tuning(dagbound_batch* b, const char* key, int64_t value) {
   g_err.clear();
   if (!b || !key) return fail(DAGBOUND_E_ARG, "batch or key is NULL");

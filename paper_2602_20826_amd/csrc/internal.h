@@ -167,6 +167,14 @@ hipError_t launch_sweep(const SweepArgs& a, hipStream_t stream, const SweepStrea
 hipError_t launch_best_final(const unsigned long long* best, int32_t D, int32_t* idx, int64_t* bound,
                              const int32_t* list, int32_t K, hipStream_t stream);
 
+// Schedule dump of DAG d under candidate c (schedule.hip): records of 8
+// int64 into rec[cap][8]; out = {records the schedule has, bound, critical-
+// path term, interference term}.  alloc = explicit bytes (K per DAG) or
+// nullptr for the seeded candidates of `seed`.
+hipError_t launch_schedule(const Tables& t, int32_t d, int32_t c, int32_t K, int32_t M, const uint8_t* alloc,
+                           uint64_t seed, int32_t max_n, int64_t* rec, int64_t cap, int64_t* out,
+                           hipStream_t stream);
+
 // ---------------------------------------------------------------------------
 // Learned candidate proposal (surrogate.hip).
 constexpr int SUR_FIN = 8, SUR_HID = 128, SUR_LAYERS = 3, SUR_OUT = 4;

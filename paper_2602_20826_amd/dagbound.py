@@ -28,7 +28,7 @@ MODEL_PARAMS = 100356
 # Every symbol include/dagbound.h declares.
 EXPORTS = (
     "dagbound_create_batch", "dagbound_set_allocations", "dagbound_eval_bounds",
-    "dagbound_best_allocation", "dagbound_get_division", "dagbound_set_tuning",
+    "dagbound_best_allocation", "dagbound_get_division", "dagbound_get_schedule", "dagbound_set_tuning",
     "dagbound_destroy_batch", "dagbound_model_create", "dagbound_model_destroy",
     "dagbound_model_params", "dagbound_model_forward", "dagbound_model_train_step",
     "dagbound_model_select",
@@ -64,6 +64,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.dagbound_best_allocation.argtypes = [P, U32, I32, P, P, P, U32, P]
     lib.dagbound_get_division.restype = I32
     lib.dagbound_get_division.argtypes = [P, I32, P, P, P, P]
+    lib.dagbound_get_schedule.restype = I32
+    lib.dagbound_get_schedule.argtypes = [P, I32, I32, P, ctypes.c_int64, P, P]
     lib.dagbound_set_tuning.restype = I32
     lib.dagbound_set_tuning.argtypes = [P, ctypes.c_char_p, ctypes.c_int64]
     lib.dagbound_destroy_batch.restype = None
@@ -306,6 +308,21 @@ def get_division(batch: Batch, d: int):
     _check(lib.dagbound_get_division(ctypes.c_void_p(batch.handle), int(d), wanc.ctypes.data,
                                      gof.ctypes.data, order.ctypes.data, ctypes.byref(ng)))
     return wanc[:n], gof[:n], order[:n], int(ng.value)
+
+
+def get_schedule(batch: Batch, d: int, c: int, cap: int = 4096):
+    """dagbound_get_schedule: (records [n][8] int64, (bound, cp, intf)) of DAG
+    d under candidate c; the buffer grows until every record fits."""
+    lib = load_library()
+    count = ctypes.c_int64(0)
+    terms = np.zeros(3, np.int64)
+    while True:
+        rec = np.zeros((max(cap, 1), 8), np.int64)
+        _check(lib.dagbound_get_schedule(ctypes.c_void_p(batch.handle), int(d), int(c), rec.ctypes.data,
+                                         int(cap), ctypes.byref(count), terms.ctypes.data))
+        if count.value <= cap:
+            return rec[:count.value].copy(), tuple(int(x) for x in terms)
+        cap = int(count.value)
 
 
 def set_tuning(batch: Batch, key: str, value: int) -> None:
