@@ -232,6 +232,12 @@ dagbound_status dagbound_get_division(dagbound_batch* batch, int32_t d, int64_t*
  *                     "persistent" and "class_streams" once, timed with
  *                     events on its stream (so that call synchronizes and must
  *                     not be captured in a graph), and keeps the fastest.
+ *   "graph"           0 (default); 1: eval_bounds on device pointers and a
+ *                     non-null stream records its launches (every class, the
+ *                     fork/join events of the side streams, the second pass)
+ *                     into a HIP graph on its first call and replays that graph
+ *                     while the output pointers, stream, allocation set and
+ *                     tuning stay the same (a change records a new one).
  * Errors: E_ARG (unknown key or value).
  */
 dagbound_status dagbound_set_tuning(dagbound_batch* batch, const char* key, int64_t value);

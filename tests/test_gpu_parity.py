@@ -352,7 +352,7 @@ def test_tuning_rejects_bad_keys(torch_dev):
     batch = W.generate_workload(1, count=2)
     b = db.create_batch(batch.node_off, batch.edge_off, batch.src, batch.dst, batch.wcet, batch.par, 8)
     for key, val in [("residual_slots", 0), ("residual_slots", 13), ("eval_path", 2), ("size_classes", 2), ("class_streams", 3), ("persistent", 2), ("autotune", -1),
-                     ("nope", 1)]:
+                     ("graph", 2), ("nope", 1)]:
         with pytest.raises(db.DagboundError):
             db.set_tuning(b, key, val)
     b.close()
@@ -561,4 +561,41 @@ def test_eval_bounds_in_a_captured_graph(torch_dev):
     want, _, _ = oracle.bounds_batch(batch, M, K, alloc, threads=8)
     assert np.array_equal(ref.reshape(D, K), want)
     del g
+    b.close()
+
+
+def test_library_graph_replays(torch_dev):
+    # set_tuning("graph", 1): eval_bounds records its launches once per
+    # (outputs, stream, allocation set, tuning) and replays the graph; every
+    # replay and the re-recorded graph after new allocations match the oracle
+    import paper_2602_20826_amd as db
+
+    torch, dev = torch_dev
+    batch = mixed_size_batch()
+    M, K = 256, 48
+    D = batch.num_dags
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    s = torch.cuda.Stream()
+    b = db.create_batch(t(batch.node_off), t(batch.edge_off), t(batch.src), t(batch.dst), t(batch.wcet),
+                        t(batch.par), M, stream=s)
+    db.set_tuning(b, "graph", 1)
+    out = torch.empty(D * K, dtype=torch.int64, device=dev)
+    cp = torch.empty(D * K, dtype=torch.int64, device=dev)
+    bi = torch.empty(D, dtype=torch.int32, device=dev)
+    bb = torch.empty(D, dtype=torch.int64, device=dev)
+    for seed in (5, 6):
+        db.set_allocations(b, K, db.ALLOC_SEEDED, None, seed)
+        want, wcp, _ = oracle.bounds_batch(batch, M, K, W.alloc_bytes(batch, M, K, seed=seed), threads=8)
+        for rep in range(3):
+            say("library graph: seed", seed, "replay", rep)
+            with torch.cuda.stream(s):
+                out.fill_(-1)
+                cp.fill_(-1)
+                db.eval_bounds(b, out, cp, stream=s)
+                db.best_allocation(b, bi, bb, stream=s)
+            torch.cuda.synchronize()
+            assert np.array_equal(out.cpu().numpy().reshape(D, K), want), (seed, rep)
+            assert np.array_equal(cp.cpu().numpy().reshape(D, K), wcp), (seed, rep)
+            assert np.array_equal(bb.cpu().numpy(), want.min(1))
+            assert np.array_equal(bi.cpu().numpy(), want.argmin(1))
     b.close()
