@@ -312,6 +312,8 @@ def main() -> int:
     ap.add_argument("--search-train", type=int, default=20000, help="training DAGs (x 256 labelled candidates)")
     ap.add_argument("--search-epochs", type=int, default=60, help="training epochs over those DAGs")
     ap.add_argument("--search-test", type=int, default=100000, help="held-out DAGs (x 4096 seeded candidates)")
+    ap.add_argument("--tuning", action="append", default=[], metavar="KEY=VALUE",
+                    help="dagbound_set_tuning option for the timed batches (repeatable)")
     ap.add_argument("--large-train", type=int, default=2000, help="large-compiler training DAGs (x 256)")
     ap.add_argument("--large-epochs", type=int, default=20, help="large-compiler training epochs")
     ap.add_argument("--surrogate-probe", type=int, default=0, metavar="DAGS",
@@ -364,8 +366,12 @@ def main() -> int:
     stream = torch.cuda.current_stream(dev)
     ev = []
 
+    tuning = [(kv.split("=")[0], int(kv.split("=")[1])) for kv in args.tuning]
+
     def step(record: bool):
         b = db.create_batch(*inputs, M, stream=stream)
+        for key, val in tuning:
+            db.set_tuning(b, key, val)
         if args.seeded:
             db.set_allocations(b, K, db.ALLOC_SEEDED, None, wl.seed)
         else:
@@ -425,6 +431,7 @@ def main() -> int:
             "workload": desc,
             "num_dags": D, "candidates": K, "num_cus": M,
             "total_nodes": int(batch.node_off[-1]), "total_edges": int(batch.edge_off[-1]),
+            **({"tuning": dict(tuning)} if tuning else {}),
         },
         "roofline": {
             "bound": "hbm",

@@ -227,9 +227,14 @@ dagbound_status dagbound_get_division(dagbound_batch* batch, int32_t d, int64_t*
  *   "persistent"      0 (default): one workgroup per 64-candidate tile;
  *                     1: as many workgroups as fit on the device, each taking
  *                     tiles from a work counter.
+ *   "node_lanes"      512 (default): DAGs above 512 nodes run one wavefront
+ *                     per (DAG, candidate) with lanes over nodes; 256: so do
+ *                     DAGs of 257-512 nodes (instead of one wavefront per
+ *                     (DAG, 64 candidates), lane per candidate).
  *   "autotune"        1: the next evaluation (eval_bounds, or the sweep of an
  *                     exhaustive best_allocation) runs each combination of
- *                     "persistent" and "class_streams" once, timed with
+ *                     "persistent", "class_streams" and, when the batch holds
+ *                     DAGs of 257-512 nodes, "node_lanes" once, timed with
  *                     events on its stream (so that call synchronizes and must
  *                     not be captured in a graph), and keeps the fastest.
  *   "graph"           0 (default); 1: eval_bounds on device pointers and a

@@ -183,6 +183,7 @@ struct dagbound_batch {
   bool size_classes = true;
   bool class_streams = true;           // class launches on side streams
   bool persistent = false;             // first pass as a persistent kernel
+  int32_t node_lanes_class = LARGE_CLASS;  // first class run by the lane-per-node kernel
   bool autotune_pending = false;       // time the launch plans on the next evaluation
   // "graph": the evaluation's launches recorded once into a HIP graph and
   // replayed while the outputs, stream, allocation set and tuning stay the same
@@ -191,7 +192,7 @@ struct dagbound_batch {
   const void* g_key[4] = {nullptr, nullptr, nullptr, nullptr};  // bounds, cp, intf, stream
   uint64_t g_gen = ~0ull, g_tune = ~0ull;
   uint64_t tune_gen = 0;
-  float plan_ms[4] = {0, 0, 0, 0};     // last autotune: (persistent, class_streams) = (p, s) at 2p + s
+  float plan_ms[8] = {};               // last autotune: (node lanes from 257 nodes, persistent, class_streams) = (l, p, s) at 4l + 2p + s
   size_t gres_off[NUM_CLASSES] = {};
   uint64_t* grows = nullptr;           // row regions for DAGs of 129-512 nodes
   size_t rows_off[NUM_CLASSES + 1] = {};
@@ -257,6 +258,7 @@ SweepArgs sweep_args(const dagbound_batch* b) {
   a.small_loads = b->small_loads ? 1 : 0;
   a.small_indeg = b->small_indeg ? 1 : 0;
   a.persistent = b->persistent ? 1 : 0;
+  a.node_lanes_class = b->node_lanes_class;
   return a;
 }
 
@@ -264,21 +266,26 @@ hipError_t run_sweep_plan(dagbound_batch* b, const SweepArgs& a, hipStream_t st)
 
 // One evaluation launch of a batch.  After set_tuning("autotune", 1) the
 // next call runs every launch plan (persistent first pass or not, class
-// launches concurrent or not) once, timed with events on `st`, and keeps the
-// fastest; the results of every plan are identical.
+// launches concurrent or not, and, when the batch holds DAGs of 257-512
+// nodes, their lane-per-candidate or lane-per-node kernel) once, timed with
+// events on `st`, and keeps the fastest; the results of every plan are
+// identical.
 hipError_t run_sweep(dagbound_batch* b, const SweepArgs& a, hipStream_t st) {
   if (!b->autotune_pending) return run_sweep_plan(b, a, st);
   b->autotune_pending = false;
   hipEvent_t t0 = nullptr, t1 = nullptr;
   hipError_t e = hipEventCreate(&t0);
   if (e == hipSuccess) e = hipEventCreate(&t1);
+  const int nplans = b->class_off[4] > b->class_off[3] ? 8 : 4;
   float best = -1.f;
-  int best_plan = (b->persistent ? 2 : 0) + (b->class_streams ? 1 : 0);
-  for (int plan = 0; plan < 4 && e == hipSuccess; plan++) {
-    b->persistent = plan >= 2;
+  int best_plan = (b->node_lanes_class == 3 ? 4 : 0) + (b->persistent ? 2 : 0) + (b->class_streams ? 1 : 0);
+  for (int plan = 0; plan < nplans && e == hipSuccess; plan++) {
+    b->persistent = plan & 2;
     b->class_streams = plan & 1;
+    b->node_lanes_class = plan & 4 ? 3 : LARGE_CLASS;
     SweepArgs ap = a;
     ap.persistent = b->persistent ? 1 : 0;
+    ap.node_lanes_class = b->node_lanes_class;
     e = hipEventRecord(t0, st);
     if (e == hipSuccess) e = run_sweep_plan(b, ap, st);
     if (e == hipSuccess) e = hipEventRecord(t1, st);
@@ -289,8 +296,10 @@ hipError_t run_sweep(dagbound_batch* b, const SweepArgs& a, hipStream_t st) {
     b->plan_ms[plan] = ms;
     if (best < 0.f || ms < best) { best = ms; best_plan = plan; }
   }
-  b->persistent = best_plan >= 2;
+  b->persistent = best_plan & 2;
   b->class_streams = best_plan & 1;
+  b->node_lanes_class = best_plan & 4 ? 3 : LARGE_CLASS;
+  b->tune_gen++;
   if (t0) (void)hipEventDestroy(t0);
   if (t1) (void)hipEventDestroy(t1);
   return e;
@@ -399,10 +408,10 @@ dagbound_status dagbound_create_batch(int32_t num_dags, const int64_t* node_off,
     b->order_host.resize((size_t)D);
     for (int64_t d = 0; d < D; d++) b->order_host[(size_t)cnt[class_of((int)(no[d + 1] - no[d]))]++] = (int32_t)d;
   }
-  const int32_t n_large = b->class_off[LARGE_CLASS + 1] - b->class_off[LARGE_CLASS];
+  const int32_t n_records = b->class_off[LARGE_CLASS + 1] - b->class_off[3];
   const size_t gres_words = sweep_gres_words(b->class_max_n, b->class_off, (int32_t)max_n, b->gres_off);
   const size_t rows_words = sweep_rows_words(b->class_max_n, b->class_off, (int32_t)max_n, b->rows_off);
-  b->block_size = table_bytes(D, tn, te, gres_words, n_large > 0) + rows_words * 8 + 256;
+  b->block_size = table_bytes(D, tn, te, gres_words, n_records > 0) + rows_words * 8 + 256;
   hipError_t e = dev_alloc(&b->block, &b->block_size, device);
   if (e != hipSuccess) {
     delete b;
@@ -427,7 +436,7 @@ dagbound_status dagbound_create_batch(int32_t num_dags, const int64_t* node_off,
   b->t.inv = cv.take<uint16_t>(tn);
   b->t.succ = cv.take<uint16_t>(te);
   b->order = cv.take<int32_t>(D);
-  if (n_large > 0) {
+  if (n_records > 0) {  // DAGs above 256 nodes may run the lane-per-node kernel
     b->t.nrec = cv.take<uint4>(tn);
     b->t.mrec = cv.take<uint4>(tn);
   }
@@ -796,6 +805,9 @@ dagbound_status dagbound_set_tuning(dagbound_batch* b, const char* key, int64_t 
   } else if (!strcmp(key, "autotune")) {
     if (value != 0 && value != 1) return fail(DAGBOUND_E_ARG, "autotune must be 0 or 1");
     b->autotune_pending = value != 0;
+  } else if (!strcmp(key, "node_lanes")) {
+    if (value != 256 && value != 512) return fail(DAGBOUND_E_ARG, "node_lanes must be 256 or 512");
+    b->node_lanes_class = value == 256 ? 3 : LARGE_CLASS;
   } else if (!strcmp(key, "graph")) {
     if (value != 0 && value != 1) return fail(DAGBOUND_E_ARG, "graph must be 0 or 1");
     b->use_graph = value != 0;

@@ -86,7 +86,7 @@ enum : int32_t { EVAL_PATH_AUTO = 0, EVAL_PATH_GLOBAL = 1 };
 // candidate) with its lanes over nodes.
 constexpr int NUM_CLASSES = 5;
 constexpr int LARGE_CLASS = 4;
-constexpr int COUNTERS_PER_CLASS = 3;
+constexpr int COUNTERS_PER_CLASS = 4;  // 16 bytes per class, so the lane-per-node kernel's 64-bit counter is aligned
 __host__ __device__ constexpr int class_of(int n) {
   return n <= 64 ? 0 : n <= 128 ? 1 : n <= 256 ? 2 : n <= 512 ? 3 : LARGE_CLASS;
 }
@@ -126,6 +126,7 @@ struct SweepArgs {
   int32_t small_loads;          // every C_hat < 2^20
   int32_t small_indeg;          // every in-degree < 256
   int32_t persistent;           // first pass as a persistent kernel over a work counter
+  int32_t node_lanes_class;     // classes from this one on run the lane-per-node kernel (3 or 4)
 };
 
 // Packing of the per-DAG minimum: bound < 2^42 (the summed load is < 2^40)

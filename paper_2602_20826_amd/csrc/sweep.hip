@@ -955,7 +955,7 @@ hipError_t launch_sweep(const SweepArgs& a, hipStream_t stream, const SweepStrea
     }
     uint32_t* counters = a.ovf_count + COUNTERS_PER_CLASS * c;
     uint32_t* list = a.ovf_list + (size_t)(a.order ? a.class_off[c] : 0) * ntile;
-    if (c == LARGE_CLASS) e = launch_eval_large(ac, counters, sc);
+    if (c >= a.node_lanes_class) e = launch_eval_large(ac, counters, sc);
     else e = a.small_loads ? launch_class<true>(c, ac, counters, list, sc)
                            : launch_class<false>(c, ac, counters, list, sc);
     if (e == hipSuccess && fork) {

@@ -328,3 +328,40 @@ def test_large_eval_in_a_captured_graph(torch_dev):
     assert np.array_equal(ref.reshape(D, K), want)
     del g
     b.close()
+
+
+@pytest.mark.parametrize("classes,seeded", [(1, 0), (1, 1), (0, 1)])
+def test_node_lanes_from_257_nodes(torch_dev, classes, seeded):
+    # node_lanes 256: DAGs of 257-512 nodes (and, with one launch, every DAG)
+    # run the lane-per-node kernel
+    batch = mixed_with_large()
+    sizes = np.diff(batch.node_off)
+    assert ((sizes > 256) & (sizes <= 512)).any()
+    K, M = 70, 256
+    alloc = W.alloc_bytes(batch, M, K, seed=19)
+    say("node_lanes 256: size_classes", classes, "seeded", seeded)
+    got = gpu_eval(torch_dev, batch, M, K, alloc, seed=19 if seeded else None,
+                   tuning={"size_classes": classes, "node_lanes": 256})
+    check_against_oracle(batch, M, K, alloc, got)
+
+
+def test_autotune_with_node_lanes(torch_dev):
+    import paper_2602_20826_amd as db
+
+    torch, dev = torch_dev
+    batch = mixed_with_large()
+    M, K = 256, 64
+    want, _, _ = oracle.bounds_batch(batch, M, K, W.alloc_bytes(batch, M, K, seed=23), threads=8)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    st = torch.cuda.current_stream(dev)
+    b = db.create_batch(t(batch.node_off), t(batch.edge_off), t(batch.src), t(batch.dst), t(batch.wcet),
+                        t(batch.par), M, stream=st)
+    db.set_allocations(b, K, db.ALLOC_SEEDED, None, 23)
+    db.set_tuning(b, "autotune", 1)
+    for rep in range(2):
+        out = torch.full((batch.num_dags * K,), -1, dtype=torch.int64, device=dev)
+        say("autotune with node lanes, evaluation", rep)
+        db.eval_bounds(b, out, stream=st)
+        torch.cuda.synchronize()
+        assert np.array_equal(out.cpu().numpy().reshape(batch.num_dags, K), want), rep
+    b.close()

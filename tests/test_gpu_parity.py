@@ -352,7 +352,7 @@ def test_tuning_rejects_bad_keys(torch_dev):
     batch = W.generate_workload(1, count=2)
     b = db.create_batch(batch.node_off, batch.edge_off, batch.src, batch.dst, batch.wcet, batch.par, 8)
     for key, val in [("residual_slots", 0), ("residual_slots", 13), ("eval_path", 2), ("size_classes", 2), ("class_streams", 3), ("persistent", 2), ("autotune", -1),
-                     ("graph", 2), ("nope", 1)]:
+                     ("graph", 2), ("node_lanes", 128), ("nope", 1)]:
         with pytest.raises(db.DagboundError):
             db.set_tuning(b, key, val)
     b.close()
