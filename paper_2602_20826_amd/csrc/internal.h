@@ -23,8 +23,8 @@ struct Tables {
   uint16_t* succ;           // [T_E] successor sigma ranks, DAG d at edge_off[d]
   int64_t* wanc;            // [T_N] W^anc by local node id (inspection)
   int32_t* ngroups;         // [D] |Pi|
-  // Node records for the large-DAG evaluation, written only when the batch
-  // holds a DAG above 512 nodes: {C_hat, min(p, M) | sigma << 16 | last << 31,
+  // Node records for the lane-per-node evaluation, written only when the
+  // batch holds a DAG above 256 nodes: {C_hat, min(p, M) | sigma << 16 | last << 31,
   // first successor (offset in the DAG's succ), local id | out-degree << 16}.
   uint4* nrec;              // [T_N] by sigma rank (last = 0)
   uint4* mrec;              // [T_N] in group order (last marks a group's last member)
