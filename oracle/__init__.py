@@ -54,6 +54,8 @@ def _load() -> ctypes.CDLL:
         lib.oracle_bounds_dag.restype = ctypes.c_int
         lib.oracle_bounds_dag.argtypes = [ctypes.c_int, ctypes.c_int, P, P, P, P, ctypes.c_int,
                                           ctypes.c_int, P, P, P, P]
+        lib.oracle_baselines.restype = ctypes.c_int
+        lib.oracle_baselines.argtypes = [ctypes.c_int, ctypes.c_int, P, P, P, P, ctypes.c_int, P]
         lib.oracle_worst_makespan.restype = ctypes.c_int64
         lib.oracle_worst_makespan.argtypes = [ctypes.c_int, ctypes.c_int, P, P, P, P, ctypes.c_int64]
         lib.oracle_random_makespan.restype = ctypes.c_int64
@@ -232,6 +234,40 @@ def bounds_batch(batch, M: int, K: int, alloc: np.ndarray, dags: Optional[Sequen
         with ThreadPoolExecutor(threads) as ex:
             list(ex.map(one, range(len(idx))))
     return out_b, out_c, out_i
+
+
+def baselines(n, src, dst, wcet, par, M) -> Tuple[int, int, int]:
+    """The comparison bounds of Section 6.2 for one DAG: (Greedy,
+    Greedy + unaware, Graham_para)."""
+    lib = _load()
+    s, sp = _arr(src, np.int32)
+    t, tp = _arr(dst, np.int32)
+    w, wp = _arr(wcet, np.int64)
+    p, pp = _arr(par, np.int32)
+    out = np.zeros(3, np.int64)
+    rc = lib.oracle_baselines(n, len(s), sp, tp, wp, pp, M, out.ctypes.data)
+    if rc != OK:
+        raise OracleError(rc)
+    return int(out[0]), int(out[1]), int(out[2])
+
+
+def baselines_batch(batch, M: int, dags: Optional[Sequence[int]] = None, threads: int = 1) -> np.ndarray:
+    """Comparison bounds of DAGs `dags` (default: all) of a workloads.DagBatch,
+    as an array [len(dags), 3] of (Greedy, Greedy + unaware, Graham_para)."""
+    idx = list(range(batch.num_dags)) if dags is None else list(dags)
+    out = np.zeros((len(idx), 3), np.int64)
+
+    def one(i):
+        n, s, t, w, p = batch.dag(idx[i])
+        out[i] = baselines(n, s, t, w, p, M)
+
+    if threads <= 1:
+        for i in range(len(idx)):
+            one(i)
+    else:
+        with ThreadPoolExecutor(threads) as ex:
+            list(ex.map(one, range(len(idx))))
+    return out
 
 
 def worst_makespan(parts_m, parts_C, preds: Sequence[Sequence[int]], M: int, node_limit: int = 0) -> int:

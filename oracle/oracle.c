@@ -18,6 +18,8 @@
  *   spare capacity, parallel nodes ........... Section 4.1, Eqs. 6-7
  *   node segmentation, extra dependencies .... Section 4.1, Algorithm 2
  *   group response and makespan bound ........ Section 4.2, Lemma 1, Theorem 1
+ *   comparison bounds (Greedy, Greedy +
+ *   unaware, Graham_para) .................... Section 6.2
  * with these readings of passages that are informal or inconsistent
  * (each one is listed with its reason in the design notes):
  *   - Theta is sorted by ASCENDING W^anc, ties by smaller id (the worked
@@ -560,6 +562,70 @@ int oracle_bounds_dag(int n, int e, const int32_t* src, const int32_t* dst, cons
 }
 
 /* ------------------------------------------------------------------ */
+/* Comparison bounds of the evaluation (Section 6.2).                  */
+/*                                                                     */
+/* With t_min = 1 the maximum useful parallelism of v is               */
+/* m^max = min(p_v, C_hat_v) (Section 2.2, with the input cap p_v).     */
+/*   Greedy: every node at m = min(m^max, M), nodes run one after       */
+/*     another: the sum of their Eq. 1 times.                          */
+/*   Greedy + unaware: m = m^max, ceil(m/M) waves in Eq. 1, summed.     */
+/*   Graham_para: node v becomes m^max unit-SM nodes of                 */
+/*     ceil(C_hat/m^max) ticks, all with v's dependencies; Graham's     */
+/*     list-scheduling bound on M SMs for that DAG is                  */
+/*     len + floor((vol - len) / M), len = the longest path in ticks,   */
+/*     vol = the SM-ticks of all unit nodes (floor: makespans are       */
+/*     whole ticks).                                                   */
+/* ------------------------------------------------------------------ */
+
+/* out3 = {Greedy, Greedy + unaware, Graham_para} of one DAG. */
+int oracle_baselines(int n, int e, const int32_t* src, const int32_t* dst, const int64_t* wcet,
+                     const int32_t* par, int M, int64_t* out3) {
+  odag g;
+  int rc = odag_init(&g, n, e, src, dst, wcet, par, M);
+  int64_t* len = NULL;
+  int* indeg = NULL;
+  int* order = NULL;
+  if (rc == O_OK) {
+    len = calloc((size_t)n + 1, sizeof(int64_t));
+    indeg = malloc(sizeof(int) * (size_t)(n + 1));
+    order = malloc(sizeof(int) * (size_t)(n + 1));
+    if (!len || !indeg || !order) rc = O_E_OOM;
+  }
+  if (rc == O_OK) {
+    int64_t greedy = 0, unaware = 0, vol = 0, longest = 0;
+    for (int v = 0; v < n; v++) {
+      int64_t mmax = min64(par[v], wcet[v]);
+      greedy += oracle_exec_time(wcet[v], min64(mmax, M), M);
+      unaware += oracle_exec_time(wcet[v], mmax, M);
+      vol += mmax * ceil_div(wcet[v], mmax);
+    }
+    /* longest path of the expanded DAG, in a topological order (Kahn) */
+    int qh = 0, qt = 0;
+    for (int v = 0; v < n; v++) {
+      indeg[v] = g.pred_off[v + 1] - g.pred_off[v];
+      if (!indeg[v]) order[qt++] = v;
+    }
+    while (qh < qt) {
+      int u = order[qh++];
+      int64_t mmax = min64(par[u], wcet[u]);
+      len[u] += ceil_div(wcet[u], mmax);  /* len[u] held the longest predecessor path */
+      longest = max64(longest, len[u]);
+      for (int a = g.succ_off[u]; a < g.succ_off[u + 1]; a++) {
+        int w = g.succ[a];
+        len[w] = max64(len[w], len[u]);
+        if (--indeg[w] == 0) order[qt++] = w;
+      }
+    }
+    out3[0] = greedy;
+    out3[1] = unaware;
+    out3[2] = n ? longest + (vol - longest) / M : 0;
+  }
+  free(len); free(indeg); free(order);
+  odag_free(&g);
+  return rc;
+}
+
+/* ------------------------------------------------------------------ */
 /* Block-level execution model, for safety checks of the bound.        */
 /*                                                                     */
 /* A launched part with parallelism m and execution time C is m thread  */
@@ -614,25 +680,29 @@ static void sim_dfs(sim_t* s, int64_t t, int minpart) {
     if (t > s->best) s->best = t;
     return;
   }
-  /* advance to the next completion */
+  /* advance to the next completion; the running list is put back exactly
+   * as it was, since the caller removes the block it added last */
   int64_t tn = INT64_MAX;
   for (int i = 0; i < s->nrun; i++) if (s->run_end[i] < tn) tn = s->run_end[i];
-  int64_t saved_end[64]; int saved_part[64]; int nsaved = 0;
-  for (int i = 0; i < s->nrun;) {
-    if (s->run_end[i] == tn) {
-      saved_end[nsaved] = s->run_end[i]; saved_part[nsaved] = s->run_part[i]; nsaved++;
-      s->finished[s->run_part[i]]++;
-      s->run_end[i] = s->run_end[s->nrun - 1]; s->run_part[i] = s->run_part[s->nrun - 1];
-      s->nrun--;
+  int64_t saved_end[64]; int saved_part[64];
+  const int nsaved = s->nrun;
+  memcpy(saved_end, s->run_end, sizeof(int64_t) * (size_t)nsaved);
+  memcpy(saved_part, s->run_part, sizeof(int) * (size_t)nsaved);
+  int k = 0;
+  for (int i = 0; i < nsaved; i++) {
+    if (saved_end[i] == tn) {
+      s->finished[saved_part[i]]++;
     } else {
-      i++;
+      s->run_end[k] = saved_end[i]; s->run_part[k] = saved_part[i]; k++;
     }
   }
+  s->nrun = k;
   sim_dfs(s, tn, 0);
-  for (int i = 0; i < nsaved; i++) {
-    s->finished[saved_part[i]]--;
-    s->run_end[s->nrun] = saved_end[i]; s->run_part[s->nrun] = saved_part[i]; s->nrun++;
-  }
+  for (int i = 0; i < nsaved; i++)
+    if (saved_end[i] == tn) s->finished[saved_part[i]]--;
+  memcpy(s->run_end, saved_end, sizeof(int64_t) * (size_t)nsaved);
+  memcpy(s->run_part, saved_part, sizeof(int) * (size_t)nsaved);
+  s->nrun = nsaved;
 }
 
 /* Worst makespan over all work-conserving dispatch orders of the parts

@@ -376,6 +376,55 @@ def _check_safe(n, src, dst, w, p, M, r, early_seeds=3):
     return worst
 
 
+def _worst_by_enumeration(m, C, preds, M):
+    """Worst makespan of the block model by plain enumeration (independent
+    of the oracle's search): at each instant the work-conserving dispatcher
+    starts ready blocks while an SM is free; simultaneous starts are taken
+    in nondecreasing part order."""
+    n = len(m)
+    best = 0
+
+    def dfs(t, started, finished, running, minpart):
+        nonlocal best
+        ready_any = False
+        if len(running) < M:
+            for x in range(n):
+                if started[x] >= m[x] or any(finished[u] < m[u] for u in preds[x]):
+                    continue
+                ready_any = True
+                if x < minpart:
+                    continue
+                st = list(started)
+                st[x] += 1
+                dfs(t, st, finished, running + [(t + C[x], x)], x)
+            if ready_any:
+                return
+        if not running:
+            best = max(best, t)
+            return
+        tn = min(e for e, _ in running)
+        fin = list(finished)
+        for e, x in running:
+            if e == tn:
+                fin[x] += 1
+        dfs(tn, started, fin, [(e, x) for e, x in running if e != tn], 0)
+
+    dfs(0, [0] * n, [0] * n, [], 0)
+    return best
+
+
+@pytest.mark.parametrize("seed", range(30))
+def test_dispatch_search_matches_enumeration(seed):
+    # the oracle's search over dispatch orders, against a plain enumeration
+    rng = np.random.default_rng(6300 + seed)
+    n = int(rng.integers(1, 6))
+    M = int(rng.integers(1, 4))
+    m = rng.integers(1, 4, n).tolist()
+    C = rng.integers(1, 4, n).tolist()
+    preds = [[u for u in range(v) if rng.random() < 0.4] for v in range(n)]
+    assert oracle.worst_makespan(m, C, preds, M) == _worst_by_enumeration(m, C, preds, M)
+
+
 @pytest.mark.parametrize("seed", range(60))
 def test_bound_safe_against_every_dispatch(seed):
     rng = np.random.default_rng(3000 + seed)
@@ -394,6 +443,84 @@ def test_bound_tight_on_oversubscribed_group():
     src, dst = edges_of(case)
     worst = _check_safe(case["n"], src, dst, case["wcet"], case["par"], case["M"], None)
     assert worst == case["expect"]["bound"]
+
+
+# ---------------------------------------------------------------- comparison bounds (Section 6.2)
+
+def test_baselines_worked_example():
+    # Derived by hand from Section 6.2's definitions (the paper prints no
+    # value for them on this DAG).  Paper mode p = C_hat and M = 6: every
+    # m^max = C_hat <= 6, so Greedy and Greedy + unaware run each node at
+    # m = C_hat with C = 1, and the sequential sum over 7 nodes is 7.
+    # Graham_para: every unit node takes one tick, the longest path
+    # v1 -> v3 -> v5 -> v7 has 4 nodes and vol = sum C_hat = 18, so the bound
+    # is 4 + floor(14 / 6) = 6.
+    ex = load("worked_example.json")
+    src, dst = edges_of(ex)
+    assert oracle.baselines(ex["n"], src, dst, ex["wcet"], ex["par"], ex["M"]) == (7, 7, 6)
+
+
+def test_baselines_single_node():
+    # C_hat = 100, p = 10, M = 4: Greedy takes m = 4, C = 25; unaware takes
+    # m = 10, ceil(10 / 4) = 3 waves, C = ceil(3 * 100 / 10) = 30; Graham_para
+    # has 10 unit nodes of 10 ticks: len 10, vol 100, 10 + floor(90 / 4) = 32.
+    assert oracle.baselines(1, [], [], [100], [10], 4) == (25, 30, 32)
+    # p above C_hat: with t_min = 1, m^max = C_hat = 3 unit nodes of one tick
+    assert oracle.baselines(1, [], [], [3], [8], 4) == (1, 1, 1)
+    # p = 1: one SM whatever M
+    assert oracle.baselines(1, [], [], [17], [1], 8) == (17, 17, 17)
+    # m^max above M in paper mode: C_hat = 9 = p on M = 4 SMs: Greedy m = 4,
+    # C = 3; unaware m = 9 in 3 waves of one tick, C = 3; Graham: 9 unit
+    # nodes of one tick, 1 + floor(8 / 4) = 3
+    assert oracle.baselines(1, [], [], [9], [9], 4) == (3, 3, 3)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_baselines_chain_and_antichain(seed):
+    rng = np.random.default_rng(6100 + seed)
+    # a chain with p = 1: every analysis runs the nodes one after another
+    k = int(rng.integers(1, 12))
+    w = rng.integers(1, 50, k).astype(np.int64)
+    src = np.arange(k - 1, dtype=np.int32)
+    dst = src + 1
+    total = int(w.sum())
+    assert oracle.baselines(k, src, dst, w, np.ones(k, np.int32), int(rng.integers(1, 9))) == (total,) * 3
+    # n independent unit nodes on M SMs: the sequential analyses give n;
+    # Graham's bound 1 + floor((n - 1) / M) = ceil(n / M), the optimum
+    n = int(rng.integers(1, 40))
+    M = int(rng.integers(1, 9))
+    got = oracle.baselines(n, [], [], np.ones(n, np.int64), np.ones(n, np.int32), M)
+    assert got == (n, n, -(-n // M))
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_graham_para_safe_against_every_dispatch(seed):
+    # Graham's theorem: no work-conserving dispatch of the expanded DAG (node
+    # v as m^max blocks of ceil(C_hat / m^max) ticks, Section 2.2's block
+    # model) ends after the bound; checked over every dispatch by brute
+    # force.  Greedy + unaware never beats Greedy (more waves, never fewer).
+    rng = np.random.default_rng(6200 + seed)
+    n = int(rng.integers(1, 7))
+    M = int(rng.integers(1, 5))
+    n, src, dst, w, p = W.random_small_dag(rng, n, float(rng.uniform(0.2, 0.6)), 5, 3)
+    greedy, unaware, graham = oracle.baselines(n, src, dst, w, p, M)
+    assert unaware >= greedy
+    mm = np.minimum(p, w)
+    C = -(-w // mm)
+    preds = [[] for _ in range(n)]
+    for a, b in zip(src, dst):
+        preds[int(b)].append(int(a))
+    worst = oracle.worst_makespan(mm, C, preds, M, node_limit=2_000_000)
+    if worst >= 0:
+        assert worst <= graham
+    for k in range(3):
+        assert oracle.random_makespan(mm, C, preds, M, seed=k, early=False) <= graham
+    # the bound is at least the longest path of the expanded DAG
+    L = np.zeros(n, np.int64)
+    R = reachability(n, src, dst)
+    for v in sorted(range(n), key=lambda v: R[v].sum()):
+        L[v] = C[v] + max([L[u] for u in preds[v]], default=0)
+    assert graham >= L.max()
 
 
 # ---------------------------------------------------------------- input checks
