@@ -294,6 +294,84 @@ def surrogate_probe(n_dags: int, reps: int = 5) -> int:
     return 0
 
 
+def baselines_bytes(batch) -> int:
+    """Bytes the comparison bounds must move: per node its load, m^max and
+    successor offset (12), per edge its successor id (2), per DAG its two
+    offsets and three outputs (40)."""
+    return 12 * int(batch.node_off[-1]) + 2 * int(batch.edge_off[-1]) + 40 * batch.num_dags
+
+
+def baselines_block(torch, db, batch, inputs, M, stream, reps: int = 5) -> dict:
+    """dagbound_baselines over the whole batch, timed with HIP events on the
+    launching stream."""
+    D = batch.num_dags
+    b = db.create_batch(*inputs, M, stream=stream)
+    dev = inputs[0].device
+    outs = [torch.empty(D, dtype=torch.int64, device=dev) for _ in range(3)]
+    db.baselines(b, *outs, stream=stream)
+    ms = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        db.baselines(b, *outs, stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms.append(e0.elapsed_time(e1))
+    b.close()
+    f = float(np.mean(ms))
+    nb = baselines_bytes(batch)
+    return {"kernel": "k_baselines (one dagbound_baselines launch)", "kernel_ms": f, "dags_per_s": D / f * 1e3,
+            "algorithmic_bytes_per_launch": nb, "achieved_gbs": nb / f / 1e6}
+
+
+# Setups of the evaluation's three sweeps (Section 6.2), 1,000 DAGs each,
+# average load 20: compute units, maximum layer width and layer count.
+PAPER_SWEEPS = {
+    "M": [dict(M=m, P=8, depth=(5, 8)) for m in (4, 8, 16, 32, 64, 128, 256)],
+    "P": [dict(M=32, P=p, depth=(5, 8)) for p in (4, 5, 6, 7, 8, 9, 10)],
+    "V": [dict(M=32, P=32, depth=(d, d)) for d in (4, 6, 8, 12, 16, 24, 32)],
+}
+
+
+def paper_sweep(count: int = 1000, c_avg: int = 20) -> int:
+    """The evaluation's sweeps on evaluation-style DAGs: per setup, the
+    paper's bound (candidate 0), Greedy and Graham_para, each normalised by
+    Greedy + unaware per DAG and averaged, all computed by the library."""
+    import torch
+
+    import paper_2602_20826_amd as db
+    import workloads as W
+
+    db.load_library()
+    dev = torch.device("cuda:0")
+    st = torch.cuda.current_stream(dev)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    rows = []
+    for sweep, setups in PAPER_SWEEPS.items():
+        for cfg in setups:
+            batch = W.paper_style(count, cfg["P"], c_avg, depth=cfg["depth"])
+            D = batch.num_dags
+            b = db.create_batch(t(batch.node_off), t(batch.edge_off), t(batch.src), t(batch.dst),
+                                t(batch.wcet), t(batch.par), cfg["M"], stream=st)
+            db.set_allocations(b, 1, db.ALLOC_SEEDED, None, 0)
+            prop = torch.empty(D, dtype=torch.int64, device=dev)
+            db.eval_bounds(b, prop, stream=st)
+            g, u, h = (torch.empty(D, dtype=torch.int64, device=dev) for _ in range(3))
+            db.baselines(b, g, u, h, stream=st)
+            torch.cuda.synchronize()
+            b.close()
+            prop, g, u, h = (x.cpu().numpy().astype(np.float64) for x in (prop, g, u, h))
+            row = {"sweep": sweep, "M": cfg["M"], "P": cfg["P"], "layers": list(cfg["depth"]),
+                   "mean_nodes": float(np.diff(batch.node_off).mean()),
+                   "proposed": float(np.mean(prop / u)), "greedy": float(np.mean(g / u)),
+                   "graham_para": float(np.mean(h / u)),
+                   "gain_vs_greedy": float(np.mean(1 - prop / g)),
+                   "gain_vs_graham_para": float(np.mean(1 - prop / h))}
+            rows.append(row)
+            print(json.dumps(row), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -318,6 +396,8 @@ def main() -> int:
     ap.add_argument("--large-epochs", type=int, default=20, help="large-compiler training epochs")
     ap.add_argument("--surrogate-probe", type=int, default=0, metavar="DAGS",
                     help="time the surrogate encoder's forward pass over DAGS learned-proposal DAGs")
+    ap.add_argument("--paper-sweep", action="store_true",
+                    help="the evaluation's sweeps over M, P and |V| (bound and comparison bounds), one JSON line each")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="one copy of known size plus one evaluation launch, for counter passes")
     ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -329,6 +409,8 @@ def main() -> int:
         return traffic_probe()
     if args.surrogate_probe:
         return surrogate_probe(args.surrogate_probe)
+    if args.paper_sweep:
+        return paper_sweep()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
               "(DAGs are independent: a multi-GPU run would shard the batch by DAG)", file=sys.stderr)
@@ -447,6 +529,8 @@ def main() -> int:
         },
         "best_gap": None,
     }
+    print("[bench] comparison bounds", file=sys.stderr, flush=True)
+    out["baselines"] = baselines_block(torch, db, batch, inputs, M, stream)
     if not args.no_search and wk == 5:
         print("[bench] large-compiler: label, train, surrogate against plain search", file=sys.stderr, flush=True)
         out["best_gap"] = large_block(torch, db, W, args.large_train, 0, batch, args.large_epochs)

@@ -170,6 +170,26 @@ dagbound_status dagbound_best_allocation(dagbound_batch* batch, uint32_t search,
                                          int64_t* best_bound, uint32_t ptr_kind, void* hip_stream);
 
 /*
+ * dagbound_baselines -- the comparison bounds of Section 6.2 for every DAG of
+ * the batch, independent of any allocation set.  With t_min = 1 a node's
+ * most useful parallelism is m^max = min(p_v, C_hat_v) (Section 2.2).
+ *   greedy          int64 [D] or NULL: Greedy, nodes run one after another
+ *                   at m = min(m^max, M): the sum of their Eq. 1 times.
+ *   greedy_unaware  int64 [D] or NULL: Greedy + unaware, the same at
+ *                   m = m^max (Eq. 1 with ceil(m/M) waves); the paper's
+ *                   normalisation reference.
+ *   graham_para     int64 [D] or NULL: Graham_para, each node as m^max
+ *                   unit-SM nodes of ceil(C_hat/m^max) ticks and Graham's
+ *                   list-scheduling bound on M SMs for that DAG,
+ *                   len + floor((vol - len) / M): len the longest path in
+ *                   ticks, vol the SM-ticks of all unit nodes.
+ * An empty DAG gives 0 for all three; all outputs NULL is a no-op.
+ * Errors: E_ARG, E_DEVICE.
+ */
+dagbound_status dagbound_baselines(dagbound_batch* batch, int64_t* greedy, int64_t* greedy_unaware,
+                                  int64_t* graham_para, uint32_t ptr_kind, void* hip_stream);
+
+/*
  * dagbound_get_schedule -- inspection of the schedule of DAG d under
  * candidate c of the current allocation set (Algorithm 2 and Lemma 1 as the
  * evaluation runs them), with the extra dependencies of Section 4.1 that

@@ -133,8 +133,8 @@ struct Carve {
 };
 
 size_t table_bytes(int64_t D, int64_t tn, int64_t te, size_t gres_words, bool mrec) {
-  return 20 * 256 + (size_t)(D + 1) * 8 * 2 + (size_t)tn * 8 + (size_t)D * 8 + 24 + (mrec ? (size_t)tn * 32 : 0) +
-         (size_t)tn * 4 + (size_t)(tn + D) * 4 + (size_t)D * 4 + (size_t)tn * 2 * 4 +
+  return 24 * 256 + (size_t)(D + 1) * 8 * 2 + (size_t)tn * 8 + (size_t)D * 8 + 24 + (mrec ? (size_t)tn * 32 : 0) +
+         (size_t)tn * 4 * 2 + (size_t)(tn + D) * 4 + (size_t)D * 4 + (size_t)tn * 2 * 4 +
          (size_t)te * 2 + gres_words * 4 + (size_t)D * 4;
 }
 
@@ -432,6 +432,7 @@ dagbound_status dagbound_create_batch(int32_t num_dags, const int64_t* node_off,
   b->t.ngroups = cv.take<int32_t>(D);
   b->t.gl = cv.take<uint16_t>(tn);
   b->t.pp = cv.take<uint16_t>(tn);
+  b->t.mx = cv.take<uint32_t>(tn);
   b->t.indeg = cv.take<uint16_t>(tn);
   b->t.inv = cv.take<uint16_t>(tn);
   b->t.succ = cv.take<uint16_t>(te);
@@ -781,6 +782,39 @@ dagbound_status dagbound_get_schedule(dagbound_batch* b, int32_t d, int32_t c, i
     terms[1] = out[2];
     terms[2] = out[3];
   }
+  return DAGBOUND_OK;
+}
+
+dagbound_status dagbound_baselines(dagbound_batch* b, int64_t* greedy, int64_t* greedy_unaware,
+                                  int64_t* graham_para, uint32_t ptr_kind, void* hip_stream) {
+  g_err.clear();
+  if (!b) return fail(DAGBOUND_E_ARG, "batch is NULL");
+  if (ptr_kind > DAGBOUND_PTR_DEVICE) return fail(DAGBOUND_E_ARG, "bad ptr_kind %u", ptr_kind);
+  const size_t n = (size_t)b->D;
+  int64_t* out[3] = {greedy, greedy_unaware, graham_para};
+  if (n == 0 || (!greedy && !greedy_unaware && !graham_para)) return DAGBOUND_OK;
+  DeviceGuard g(b->device);
+  hipStream_t st = (hipStream_t)hip_stream;
+  int64_t* dv[3] = {greedy, greedy_unaware, graham_para};
+  void* tmp = nullptr;
+  size_t tmp_size = 0;
+  hipError_t e = hipSuccess;
+  if (ptr_kind == DAGBOUND_PTR_HOST) {
+    tmp_size = 3 * 256 + 3 * n * 8;
+    e = dev_alloc(&tmp, &tmp_size, b->device);
+    if (e != hipSuccess) return hip_fail(e, "allocating output staging");
+    Carve c(tmp);
+    for (int i = 0; i < 3; i++) dv[i] = out[i] ? c.take<int64_t>(n) : nullptr;
+  }
+  e = launch_baselines(b->t, b->D, b->M, b->max_n, dv[0], dv[1], dv[2], st);
+  for (int i = 0; i < 3 && e == hipSuccess && ptr_kind == DAGBOUND_PTR_HOST; i++)
+    if (out[i]) e = hipMemcpyAsync(out[i], dv[i], n * 8, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess && (ptr_kind == DAGBOUND_PTR_HOST || !st)) e = hipStreamSynchronize(st);
+  if (tmp) {
+    if (e != hipSuccess) (void)hipDeviceSynchronize();
+    dev_release(tmp, tmp_size, b->device);
+  }
+  if (e != hipSuccess) return hip_fail(e, "comparison bounds");
   return DAGBOUND_OK;
 }
 

@@ -17,6 +17,7 @@ struct Tables {
   uint16_t* gl;             // [T_N] sigma ranks in group order; bit 15 marks a group's last member
   uint32_t* wc;             // [T_N] load C_hat by sigma rank
   uint16_t* pp;             // [T_N] min(p, M) by sigma rank
+  uint32_t* mx;             // [T_N] m^max = min(p, C_hat) by sigma rank (t_min = 1)
   uint16_t* indeg;          // [T_N] predecessor count by sigma rank
   uint16_t* inv;            // [T_N] sigma rank of each local node id
   uint32_t* soff;           // [T_N + D] successor offsets by sigma rank, N_d + 1 per DAG at node_off[d] + d
@@ -67,6 +68,11 @@ size_t prep_large_scratch_bytes(int32_t count, int32_t max_n, int32_t max_e);
 hipError_t launch_prep_large(const Tables& t, const PrepInputs& in, int32_t count, int32_t M, const int32_t* list,
                              unsigned long long* err, void* scratch, int32_t max_n, int32_t max_e,
                              hipStream_t stream);
+
+// Comparison bounds of Section 6.2 (Greedy, Greedy+unaware, Graham_para)
+// per DAG into the non-null outputs ([D] each); max_n sizes the LDS.
+hipError_t launch_baselines(const Tables& t, int32_t D, int32_t M, int32_t max_n, int64_t* greedy,
+                            int64_t* unaware, int64_t* graham, hipStream_t stream);
 
 // Slots of the per-lane table of segmented residuals in the first
 // evaluation pass; a tile that needs more goes to the global-memory pass.

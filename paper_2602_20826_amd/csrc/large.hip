@@ -604,6 +604,7 @@ __device__ void prep_one(const Tables& t, const PrepInputs& in, int32_t M, int d
     const int v = S.perm[s];
     t.wc[n0 + s] = wcl[v];
     t.pp[n0 + s] = (uint16_t)min(S.par[v], (uint32_t)M);
+    t.mx[n0 + s] = min(S.par[v], wcl[v]);
     t.indeg[n0 + s] = (uint16_t)(S.predoff[v + 1] - S.predoff[v]);
   }
   uint32_t* soff = t.soff + n0 + d;

@@ -439,6 +439,7 @@ __global__ __launch_bounds__(64) void k_prep(Tables t, PrepInputs in, int32_t M,
     const int v = s_perm[s];
     t.wc[n0 + s] = s_wcet[v];
     t.pp[n0 + s] = (uint16_t)min(s_par[v], (uint32_t)M);
+    t.mx[n0 + s] = min(s_par[v], s_wcet[v]);
     t.indeg[n0 + s] = (uint16_t)s_indeg[v];
   }
   for (int v = lane; v < N; v += WAVE) {

@@ -28,7 +28,8 @@ MODEL_PARAMS = 100356
 # Every symbol include/dagbound.h declares.
 EXPORTS = (
     "dagbound_create_batch", "dagbound_set_allocations", "dagbound_eval_bounds",
-    "dagbound_best_allocation", "dagbound_get_division", "dagbound_get_schedule", "dagbound_set_tuning",
+    "dagbound_best_allocation", "dagbound_get_division", "dagbound_get_schedule", "dagbound_baselines",
+    "dagbound_set_tuning",
     "dagbound_destroy_batch", "dagbound_model_create", "dagbound_model_destroy",
     "dagbound_model_params", "dagbound_model_forward", "dagbound_model_train_step",
     "dagbound_model_select",
@@ -66,6 +67,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.dagbound_get_division.argtypes = [P, I32, P, P, P, P]
     lib.dagbound_get_schedule.restype = I32
     lib.dagbound_get_schedule.argtypes = [P, I32, I32, P, ctypes.c_int64, P, P]
+    lib.dagbound_baselines.restype = I32
+    lib.dagbound_baselines.argtypes = [P, P, P, P, U32, P]
     lib.dagbound_set_tuning.restype = I32
     lib.dagbound_set_tuning.argtypes = [P, ctypes.c_char_p, ctypes.c_int64]
     lib.dagbound_destroy_batch.restype = None
@@ -214,6 +217,19 @@ def eval_bounds(batch: Batch, bounds, cp_term=None, intf_term=None, stream=None)
     (p_b, p_c, p_i), kind, keep = _marshal([(bounds, "int64"), (cp_term, "int64"), (intf_term, "int64")])
     _check(lib.dagbound_eval_bounds(ctypes.c_void_p(batch.handle), p_b, p_c, p_i, kind,
                                     _stream_ptr(stream)))
+
+
+def baselines(batch: Batch, greedy=None, greedy_unaware=None, graham_para=None, stream=None):
+    """dagbound_baselines: the comparison bounds of Section 6.2 per DAG,
+    written in place into the given [D] int64 arrays; with none given, host
+    arrays are allocated and returned as (greedy, greedy_unaware, graham_para)."""
+    lib = load_library()
+    if greedy is None and greedy_unaware is None and graham_para is None:
+        greedy, greedy_unaware, graham_para = (np.zeros(batch.num_dags, np.int64) for _ in range(3))
+    (p_g, p_u, p_h), kind, keep = _marshal([(greedy, "int64"), (greedy_unaware, "int64"),
+                                            (graham_para, "int64")])
+    _check(lib.dagbound_baselines(ctypes.c_void_p(batch.handle), p_g, p_u, p_h, kind, _stream_ptr(stream)))
+    return greedy, greedy_unaware, graham_para
 
 
 def best_allocation(batch: Batch, best_idx, best_bound, search: int = SEARCH_EXHAUSTIVE,

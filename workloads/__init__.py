@@ -253,6 +253,49 @@ def from_dags(dags) -> DagBatch:
                     cat([d[3] for d in dags], np.int64), cat([d[4] for d in dags], np.int32))
 
 
+# Seed of the evaluation-style workloads (Section 6.1's setups).
+PAPER_STYLE_SEED = BASE_SEED + 6
+
+
+def paper_style(count: int, P: int, c_avg: int, depth=(5, 8), p_adj: float = 0.3,
+                seed: int = PAPER_STYLE_SEED) -> DagBatch:
+    """DAGs shaped like the evaluation's synthetic setups (Section 6.1): the
+    number of layers is drawn in depth[0]..depth[1], the first layer is one
+    source node and every later layer has U{2..P} nodes; each node of a layer
+    takes one predecessor drawn from the layer before and every other pair of
+    adjacent-layer nodes is an edge with probability p_adj; one sink follows
+    every node left without a successor.  Loads are uniform in
+    1..2*c_avg - 1 (mean c_avg) and the maximum parallelism is the load
+    itself (t_min = 1, so m^max = C_hat).  DAG d draws from its own stream
+    (seed, d); ids are in layer order."""
+    dags = []
+    for d in range(count):
+        rng = np.random.default_rng([seed & (2**63 - 1), P, c_avg, depth[0], depth[1], d])
+        layers = int(rng.integers(depth[0], depth[1] + 1))
+        widths = [1] + [int(x) for x in rng.integers(2, P + 1, layers - 1)]
+        first = np.cumsum([0] + widths)
+        src, dst = [], []
+        for l in range(1, layers):
+            prev = np.arange(first[l - 1], first[l])
+            for v in range(first[l], first[l + 1]):
+                parent = int(prev[rng.integers(0, len(prev))])
+                for u in prev:
+                    if u == parent or rng.random() < p_adj:
+                        src.append(int(u))
+                        dst.append(v)
+        n = int(first[-1]) + 1
+        sink = n - 1
+        has_succ = np.zeros(n, bool)
+        has_succ[np.asarray(src, np.int64)] = True
+        for u in range(sink):
+            if not has_succ[u]:
+                src.append(u)
+                dst.append(sink)
+        wcet = rng.integers(1, 2 * c_avg, n).astype(np.int64)
+        dags.append((n, np.asarray(src, np.int32), np.asarray(dst, np.int32), wcet, wcet.astype(np.int32)))
+    return from_dags(dags)
+
+
 def random_small_dag(rng: np.random.Generator, n: int, p_edge: float, wmax: int, pmax: int):
     """A tiny random DAG for brute-force tests: edges follow a random order."""
     order = rng.permutation(n)
