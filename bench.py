@@ -372,6 +372,38 @@ def paper_sweep(count: int = 1000, c_avg: int = 20) -> int:
     return 0
 
 
+def realize(count: int = 10, tick_ns: int = 200_000, reps: int = 10) -> int:
+    """Schedules run on the GPU as HIP graphs (dagbound_run_schedule) for
+    evaluation-style DAGs: per setup, the measured makespan against the
+    bound (in ticks of tick_ns), with one barrier per slot boundary and with
+    the DAG's edges and the extra dependencies only."""
+    import paper_2602_20826_amd as db
+    import workloads as W
+
+    db.load_library()
+    for M, P in ((8, 8), (32, 8), (32, 32)):
+        batch = W.paper_style(count, P, 20)
+        b = db.create_batch(batch.node_off, batch.edge_off, batch.src, batch.dst, batch.wcet, batch.par, M)
+        db.set_allocations(b, 2, db.ALLOC_SEEDED, None, 0)
+        row = {"M": M, "P": P, "dags": count, "tick_ns": tick_ns, "reps": reps}
+        for barriers in (True, False):
+            ratio, over, worst = [], [], []
+            for d in range(count):
+                recs, _ = db.get_schedule(b, d, 0)
+                slots = int((recs[:, 0] == 1).sum())
+                out, (bound, cp, intf, parts) = db.run_schedule(b, d, 0, tick_ns, barriers=barriers, reps=reps)
+                med = float(np.median(out))
+                ratio.append(med / (bound * tick_ns))
+                over.append((med - cp * tick_ns) / max(1, slots))
+                worst.append(float(out.max()) / (bound * tick_ns))
+            key = "barriers" if barriers else "edges_only"
+            row[key] = {"median_over_bound": float(np.mean(ratio)), "max_over_bound": float(np.max(worst)),
+                        "overhead_ns_per_slot": float(np.mean(over))}
+        b.close()
+        print(json.dumps(row), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -398,6 +430,8 @@ def main() -> int:
                     help="time the surrogate encoder's forward pass over DAGS learned-proposal DAGs")
     ap.add_argument("--paper-sweep", action="store_true",
                     help="the evaluation's sweeps over M, P and |V| (bound and comparison bounds), one JSON line each")
+    ap.add_argument("--realize", action="store_true",
+                    help="schedules run as HIP graphs of busy kernels: measured makespan against the bound")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="one copy of known size plus one evaluation launch, for counter passes")
     ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -411,6 +445,8 @@ def main() -> int:
         return surrogate_probe(args.surrogate_probe)
     if args.paper_sweep:
         return paper_sweep()
+    if args.realize:
+        return realize()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
               "(DAGs are independent: a multi-GPU run would shard the batch by DAG)", file=sys.stderr)

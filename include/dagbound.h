@@ -170,6 +170,32 @@ dagbound_status dagbound_best_allocation(dagbound_batch* batch, uint32_t search,
                                          int64_t* best_bound, uint32_t ptr_kind, void* hip_stream);
 
 /*
+ * dagbound_run_schedule -- runs the schedule of DAG d under candidate c on
+ * this GPU as a HIP graph, the counterpart of the paper's case study
+ * (Section 6.1: one busy kernel, m_i set through the launch shape, the DAG
+ * as a graph) in the execution model of Section 2.2: every launched part
+ * (member, parallel node, segment) is m workgroups, each holding one compute
+ * unit alone for C ticks of tick_ns nanoseconds on the GPU's constant-rate
+ * clock.
+ *   barriers     1: a barrier at every slot boundary, the realization the
+ *                bound covers: each slot is one launch of the blocks of all
+ *                its parts, after the slot before; 0: each part is its own
+ *                kernel node, after the DAG's edges (last part before first
+ *                part), the chain of a segmented node's parts and the extra
+ *                dependencies of Section 4.1 only.
+ *   reps         runs timed after one warm-up run (1..100000).
+ *   makespan_ns  int64 [reps] host: each run's time from graph launch to
+ *                completion (HIP events), launch overhead included.
+ *   terms        int64 [4] or NULL: {bound, critical-path term,
+ *                interference term, parts}; the bound in ticks.
+ * Requires M <= the device's compute units (a device with more can only
+ * finish earlier), tick_ns in [1000, 1e7], and bound x tick x (reps + 1)
+ * within two minutes.  Blocks until done.  Errors: E_ARG, E_STATE, E_DEVICE.
+ */
+dagbound_status dagbound_run_schedule(dagbound_batch* batch, int32_t d, int32_t c, int64_t tick_ns,
+                                      int32_t barriers, int32_t reps, int64_t* makespan_ns, int64_t* terms);
+
+/*
  * dagbound_baselines -- the comparison bounds of Section 6.2 for every DAG of
  * the batch, independent of any allocation set.  With t_min = 1 a node's
  * most useful parallelism is m^max = min(p_v, C_hat_v) (Section 2.2).

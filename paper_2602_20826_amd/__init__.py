@@ -7,6 +7,7 @@ The C-ABI library (``libdagbound.so``, HIP kernels for gfx950) does the work;
 from .dagbound import (  # noqa: F401
     ALLOC_EXPLICIT, ALLOC_SEEDED, PTR_DEVICE, PTR_HOST, SEARCH_EXHAUSTIVE, SEARCH_SURROGATE,
     Batch, DagboundError, best_allocation, create_batch, destroy_batch, eval_bounds,
-    baselines, get_division, get_schedule, last_error, load_library, set_allocations, set_tuning, version,
+    baselines, get_division, get_schedule, last_error, load_library, run_schedule, set_allocations, set_tuning,
+    version,
     Model, model_forward, model_select, model_train_step,
 )

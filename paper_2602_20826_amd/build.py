@@ -11,7 +11,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libdagbound.so")
-SOURCES = ["api.cpp", "prep.hip", "sweep.hip", "large.hip", "schedule.hip", "baselines.hip", "surrogate.hip"]
+SOURCES = ["api.cpp", "prep.hip", "sweep.hip", "large.hip", "schedule.hip", "baselines.hip", "realize.hip", "surrogate.hip"]
 ARCH = os.environ.get("DAGBOUND_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

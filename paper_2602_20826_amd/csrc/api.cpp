@@ -750,6 +750,91 @@ dagbound_status dagbound_get_division(dagbound_batch* b, int32_t d, int64_t* wan
   return DAGBOUND_OK;
 }
 
+// Every record of the schedule of (d, c) into `rec` (host), and its terms.
+static hipError_t schedule_all(dagbound_batch* b, int32_t d, int32_t c, std::vector<int64_t>& rec,
+                               int64_t terms[3]) {
+  int64_t cap = 4096;
+  for (int attempt = 0; attempt < 2; attempt++) {
+    void* tmp = nullptr;
+    size_t tmp_size = 256 + 64 + (size_t)cap * 64;
+    hipError_t e = dev_alloc(&tmp, &tmp_size, b->device);
+    if (e != hipSuccess) return e;
+    Carve cv(tmp);
+    int64_t* d_out = cv.take<int64_t>(4);
+    int64_t* d_rec = cv.take<int64_t>((size_t)cap * 8);
+    e = hipDeviceSynchronize();
+    if (e == hipSuccess)
+      e = launch_schedule(b->t, d, c, b->K, b->M, b->mode == DAGBOUND_ALLOC_EXPLICIT ? b->alloc : nullptr, b->seed,
+                          b->max_n, d_rec, cap, d_out, nullptr);
+    int64_t out[4] = {0, 0, 0, 0};
+    if (e == hipSuccess) e = hipMemcpy(out, d_out, sizeof out, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && out[0] <= cap) {
+      rec.resize((size_t)out[0] * 8);
+      if (out[0] > 0) e = hipMemcpy(rec.data(), d_rec, (size_t)out[0] * 64, hipMemcpyDeviceToHost);
+      for (int i = 0; i < 3; i++) terms[i] = out[i + 1];
+      dev_release(tmp, tmp_size, b->device);
+      return e;
+    }
+    dev_release(tmp, tmp_size, b->device);
+    if (e != hipSuccess) return e;
+    cap = out[0];
+  }
+  return hipErrorUnknown;
+}
+
+dagbound_status dagbound_run_schedule(dagbound_batch* b, int32_t d, int32_t c, int64_t tick_ns, int32_t barriers,
+                                      int32_t reps, int64_t* makespan_ns, int64_t* terms) {
+  g_err.clear();
+  if (!b) return fail(DAGBOUND_E_ARG, "batch is NULL");
+  if (d < 0 || d >= b->D) return fail(DAGBOUND_E_ARG, "DAG index %d outside [0, %d)", d, b->D);
+  if (!b->has_alloc) return fail(DAGBOUND_E_STATE, "set_allocations has not been called");
+  if (c < 0 || c >= b->K) return fail(DAGBOUND_E_ARG, "candidate %d outside [0, %d)", c, b->K);
+  if (tick_ns < 1000 || tick_ns > 10000000) return fail(DAGBOUND_E_ARG, "tick_ns %lld outside [1000, 1e7]", (long long)tick_ns);
+  if (reps < 1 || reps > 100000 || !makespan_ns) return fail(DAGBOUND_E_ARG, "bad reps or makespan buffer");
+  if (barriers != 0 && barriers != 1) return fail(DAGBOUND_E_ARG, "barriers must be 0 or 1");
+  DeviceGuard g(b->device);
+  int cus = 0;
+  hipError_t e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device);
+  if (e != hipSuccess) return hip_fail(e, "device attributes");
+  if (b->M > cus) return fail(DAGBOUND_E_ARG, "M = %d exceeds the device's %d compute units", b->M, cus);
+  std::vector<int64_t> rec;
+  int64_t t3[3] = {0, 0, 0};
+  e = schedule_all(b, d, c, rec, t3);
+  if (e != hipSuccess) return hip_fail(e, "schedule dump");
+  // the expected run time, bound x tick per run, stays within two minutes
+  if ((double)t3[0] * (double)tick_ns * (double)(reps + 1) > 120e9)
+    return fail(DAGBOUND_E_ARG, "bound %lld x tick x runs exceeds two minutes", (long long)t3[0]);
+  const int64_t n0 = b->node_off[d], n1 = b->node_off[d + 1];
+  const int32_t N = (int32_t)(n1 - n0);
+  std::vector<int32_t> es, ed;
+  if (!barriers && N > 0) {
+    // the DAG's edges in local ids, from the tables by sigma rank
+    const int64_t e0 = b->edge_off[d], e1 = b->edge_off[d + 1];
+    std::vector<uint32_t> soff((size_t)N + 1);
+    std::vector<uint16_t> succ((size_t)(e1 - e0) + 1), inv((size_t)N);
+    e = hipMemcpy(soff.data(), b->t.soff + n0 + d, ((size_t)N + 1) * 4, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && e1 > e0) e = hipMemcpy(succ.data(), b->t.succ + e0, (size_t)(e1 - e0) * 2, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(inv.data(), b->t.inv + n0, (size_t)N * 2, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "reading the DAG's tables");
+    std::vector<int32_t> perm((size_t)N, 0);
+    for (int32_t v = 0; v < N; v++) perm[inv[v]] = v;
+    for (int32_t s = 0; s < N; s++)
+      for (uint32_t k = soff[s]; k < soff[s + 1]; k++) {
+        es.push_back(perm[s]);
+        ed.push_back(perm[succ[k]]);
+      }
+  }
+  int32_t nparts = 0;
+  e = realize_schedule(rec.data(), (int64_t)(rec.size() / 8), N, es.data(), ed.data(), (int32_t)es.size(), tick_ns,
+                       barriers != 0, reps, makespan_ns, &nparts);
+  if (e != hipSuccess) return hip_fail(e, "running the schedule's graph");
+  if (terms) {
+    for (int i = 0; i < 3; i++) terms[i] = t3[i];
+    terms[3] = nparts;
+  }
+  return DAGBOUND_OK;
+}
+
 dagbound_status dagbound_get_schedule(dagbound_batch* b, int32_t d, int32_t c, int64_t* records, int64_t cap,
                                       int64_t* count, int64_t* terms) {
   g_err.clear();

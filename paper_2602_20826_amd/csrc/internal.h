@@ -74,6 +74,14 @@ hipError_t launch_prep_large(const Tables& t, const PrepInputs& in, int32_t coun
 hipError_t launch_baselines(const Tables& t, int32_t D, int32_t M, int32_t max_n, int64_t* greedy,
                             int64_t* unaware, int64_t* graham, hipStream_t stream);
 
+// Runs the part graph of one schedule (records of the schedule dump; edges
+// esrc -> edst of the DAG, local ids, used without barriers) `reps` times
+// after one warm-up, with parts of C ticks of tick_ns nanoseconds; writes
+// each run's makespan.  Blocks until done.
+hipError_t realize_schedule(const int64_t* rec, int64_t nrec, int32_t n, const int32_t* esrc,
+                            const int32_t* edst, int32_t ne, int64_t tick_ns, bool barriers, int32_t reps,
+                            int64_t* makespan_ns, int32_t* nparts_out);
+
 // Slots of the per-lane table of segmented residuals in the first
 // evaluation pass; a tile that needs more goes to the global-memory pass.
 constexpr int RES_SLOTS = 12;

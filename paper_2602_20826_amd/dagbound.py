@@ -28,7 +28,7 @@ MODEL_PARAMS = 100356
 # Every symbol include/dagbound.h declares.
 EXPORTS = (
     "dagbound_create_batch", "dagbound_set_allocations", "dagbound_eval_bounds",
-    "dagbound_best_allocation", "dagbound_get_division", "dagbound_get_schedule", "dagbound_baselines",
+    "dagbound_best_allocation", "dagbound_get_division", "dagbound_get_schedule", "dagbound_baselines", "dagbound_run_schedule",
     "dagbound_set_tuning",
     "dagbound_destroy_batch", "dagbound_model_create", "dagbound_model_destroy",
     "dagbound_model_params", "dagbound_model_forward", "dagbound_model_train_step",
@@ -67,6 +67,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.dagbound_get_division.argtypes = [P, I32, P, P, P, P]
     lib.dagbound_get_schedule.restype = I32
     lib.dagbound_get_schedule.argtypes = [P, I32, I32, P, ctypes.c_int64, P, P]
+    lib.dagbound_run_schedule.restype = I32
+    lib.dagbound_run_schedule.argtypes = [P, I32, I32, ctypes.c_int64, I32, I32, P, P]
     lib.dagbound_baselines.restype = I32
     lib.dagbound_baselines.argtypes = [P, P, P, P, U32, P]
     lib.dagbound_set_tuning.restype = I32
@@ -230,6 +232,16 @@ def baselines(batch: Batch, greedy=None, greedy_unaware=None, graham_para=None, 
                                             (graham_para, "int64")])
     _check(lib.dagbound_baselines(ctypes.c_void_p(batch.handle), p_g, p_u, p_h, kind, _stream_ptr(stream)))
     return greedy, greedy_unaware, graham_para
+
+
+def run_schedule(batch: Batch, d: int, c: int, tick_ns: int, barriers: bool = True, reps: int = 10):
+    """dagbound_run_schedule: (makespan_ns [reps] int64, (bound, cp, intf,
+    parts)) of DAG d's schedule under candidate c run as a HIP graph."""
+    out = np.zeros(reps, np.int64)
+    terms = np.zeros(4, np.int64)
+    _check(load_library().dagbound_run_schedule(ctypes.c_void_p(batch.handle), int(d), int(c), int(tick_ns),
+                                                int(bool(barriers)), int(reps), out.ctypes.data, terms.ctypes.data))
+    return out, tuple(int(x) for x in terms)
 
 
 def best_allocation(batch: Batch, best_idx, best_bound, search: int = SEARCH_EXHAUSTIVE,
