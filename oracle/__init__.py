@@ -50,10 +50,10 @@ def _load() -> ctypes.CDLL:
         lib.oracle_division.argtypes = [ctypes.c_int, ctypes.c_int, P, P, P, P, ctypes.c_int] + [P] * 7
         lib.oracle_bound.restype = ctypes.c_int
         lib.oracle_bound.argtypes = [ctypes.c_int, ctypes.c_int, P, P, P, P, ctypes.c_int, P, P, P,
-                                     ctypes.c_int64, P]
+                                     ctypes.c_int64, P, ctypes.c_int]
         lib.oracle_bounds_dag.restype = ctypes.c_int
         lib.oracle_bounds_dag.argtypes = [ctypes.c_int, ctypes.c_int, P, P, P, P, ctypes.c_int,
-                                          ctypes.c_int, P, P, P, P]
+                                          ctypes.c_int, P, P, P, P, ctypes.c_int]
         lib.oracle_baselines.restype = ctypes.c_int
         lib.oracle_baselines.argtypes = [ctypes.c_int, ctypes.c_int, P, P, P, P, ctypes.c_int, P]
         lib.oracle_worst_makespan.restype = ctypes.c_int64
@@ -145,9 +145,15 @@ class Schedule:
     edges: List[Tuple[int, int, int, int, int]]  # (slot, from node, from part, to node, to part)
 
 
-def bound(n, src, dst, wcet, par, M, r=None, trace: bool = False):
+SPATIAL, TEMPORAL = 0, 1
+
+
+def bound(n, src, dst, wcet, par, M, r=None, trace: bool = False, para_mode: int = SPATIAL):
     """Bound of one DAG under candidate r (None: the paper's rule for all
-    nodes).  Returns (bound, cp, intf), or a Schedule when trace=True."""
+    nodes).  Returns (bound, cp, intf), or a Schedule when trace=True.
+    para_mode: SPATIAL (the launching loop's spare SMs shrink per node) or
+    TEMPORAL (the launched nodes run one after another on the spare SMs
+    within the slot's time)."""
     lib = _load()
     s, sp = _arr(src, np.int32)
     t, tp = _arr(dst, np.int32)
@@ -165,7 +171,7 @@ def bound(n, src, dst, wcet, par, M, r=None, trace: bool = False):
         cap = 64 * (n + 4) * (n + 4) + 1024
         buf = np.zeros(cap * 8, np.int64)
     rc = lib.oracle_bound(n, len(s), sp, tp, wp, pp, M, rp, out.ctypes.data,
-                          buf.ctypes.data if buf is not None else None, cap, ntr.ctypes.data)
+                          buf.ctypes.data if buf is not None else None, cap, ntr.ctypes.data, int(para_mode))
     if rc != OK:
         raise OracleError(rc)
     if not trace:
@@ -191,7 +197,8 @@ def bound(n, src, dst, wcet, par, M, r=None, trace: bool = False):
     return Schedule(int(out[0]), int(out[1]), int(out[2]), slots, edges)
 
 
-def bounds_dag(n, src, dst, wcet, par, M, K, alloc_dag) -> Tuple[np.ndarray, np.ndarray, np.ndarray]:
+def bounds_dag(n, src, dst, wcet, par, M, K, alloc_dag,
+               para_mode: int = SPATIAL) -> Tuple[np.ndarray, np.ndarray, np.ndarray]:
     """All K candidates of one DAG; alloc_dag holds K*n bytes ((c, v) at
     c*n + v), candidate 0's bytes ignored."""
     lib = _load()
@@ -204,14 +211,14 @@ def bounds_dag(n, src, dst, wcet, par, M, K, alloc_dag) -> Tuple[np.ndarray, np.
     cp = np.zeros(K, np.int64)
     it = np.zeros(K, np.int64)
     rc = lib.oracle_bounds_dag(n, len(s), sp, tp, wp, pp, M, K, ap, b.ctypes.data,
-                               cp.ctypes.data, it.ctypes.data)
+                               cp.ctypes.data, it.ctypes.data, int(para_mode))
     if rc != OK:
         raise OracleError(rc)
     return b, cp, it
 
 
 def bounds_batch(batch, M: int, K: int, alloc: np.ndarray, dags: Optional[Sequence[int]] = None,
-                 threads: int = 1):
+                 threads: int = 1, para_mode: int = SPATIAL):
     """Bounds of DAGs `dags` (default: all) of a workloads.DagBatch with the
     explicit candidate bytes `alloc` (layout K*node_off[d] + c*N_d + v).
     Returns (bounds, cp, intf), each [len(dags), K]."""
@@ -225,7 +232,7 @@ def bounds_batch(batch, M: int, K: int, alloc: np.ndarray, dags: Optional[Sequen
         n, s, t, w, p = batch.dag(d)
         n0 = int(batch.node_off[d])
         a = alloc[K * n0: K * n0 + K * n]
-        out_b[i], out_c[i], out_i[i] = bounds_dag(n, s, t, w, p, M, K, a)
+        out_b[i], out_c[i], out_i[i] = bounds_dag(n, s, t, w, p, M, K, a, para_mode)
 
     if threads <= 1:
         for i in range(len(idx)):
@@ -304,7 +311,8 @@ def schedule_parts(sched: Schedule, barriers: bool = True, src=None, dst=None):
     """Turn a traced schedule into the part DAG of the block model.
 
     With barriers, every part of slot j waits for every part of slot j-1
-    (one barrier per slot boundary).  Without them, the parts keep only the
+    (one barrier per slot boundary), and the recorded dependencies inside a
+    slot (the chain of the temporal reading) are kept.  Without them, the parts keep only the
     original edges (mapped to the first/last part of each node), the chain
     between consecutive parts of a segmented node and the extra dependencies
     of Section 4.1.  Returns (m, C, preds)."""
@@ -321,6 +329,12 @@ def schedule_parts(sched: Schedule, barriers: bool = True, src=None, dst=None):
         for a, b in zip(slots, slots[1:]):
             for x in by_slot[b]:
                 preds[x].update(by_slot[a])
+        # dependencies inside one slot: the chain of the temporal reading
+        for (_, a, ap, b, bp) in sched.edges:
+            if (a, ap) in index and (b, bp) in index:
+                ia, ib = index[(a, ap)], index[(b, bp)]
+                if parts[ia].slot == parts[ib].slot:
+                    preds[ib].add(ia)
     else:
         last = {}
         first = {}

@@ -389,8 +389,13 @@ static void trace_put(trace_t* t, int64_t a0, int64_t a1, int64_t a2, int64_t a3
 }
 
 /* Runs Algorithm 2 under candidate r (r may be NULL: the paper's rule for
- * every node).  out3 = {bound, critical-path term, interference term}. */
-static int oracle_schedule(const odag* g, const uint8_t* r, int64_t* out3, trace_t* tr) {
+ * every node).  out3 = {bound, critical-path term, interference term}.
+ * temporal selects the other reading of the launching loop (Eqs. 6-7 with
+ * WS_j as an area): the S spare SMs stay S for every parallel node, the
+ * launched nodes run one after another on them (chain edges), and the
+ * budget is the slot's time maxC; a node that does not fit in the time left
+ * is segmented at (time left) * m_c and the launching stops. */
+static int oracle_schedule(const odag* g, const uint8_t* r, int64_t* out3, trace_t* tr, int temporal) {
   int n = g->n;
   int64_t M = g->M;
   int64_t* cur = malloc(sizeof(int64_t) * (size_t)(n + 1));       /* remaining load, \hat C */
@@ -458,6 +463,34 @@ static int oracle_schedule(const odag* g, const uint8_t* r, int64_t* out3, trace
     int64_t S = M - sum_m;
     if (S < 0) S = 0;
     int nl = 0, seg_node = -1;
+    if (temporal) {
+      int64_t T = maxC, peak = 0;     /* time left on the spare SMs */
+      for (int i = 0; i < npara && S > 0 && T > 0; i++) {
+        int c = para[i];
+        int64_t mmax = min64(g->par[c], cur[c]);
+        int64_t target = (r && r[c] > 0) ? min64(r[c], mmax) : mmax;
+        int64_t mc = min64(target, S);
+        int64_t cap = T * mc;
+        peak = max64(peak, mc);
+        if (cur[c] > cap) {
+          trace_put(tr, 2, j, c, nparts[c], 2, mc, T, cap);
+          launched_part[nl++] = c;
+          nparts[c]++;
+          cur[c] -= cap;
+          A += mc * T;
+          seg_node = c;
+          break;
+        }
+        int64_t Cc = ceil_div(cur[c], mc);
+        trace_put(tr, 2, j, c, nparts[c], 1, mc, Cc, cur[c]);
+        launched_whole[c] = 1;
+        launched_part[nl++] = c;
+        A += mc * Cc;
+        T -= Cc;
+      }
+      sum_m += peak;
+      S = 0;
+    }
     for (int i = 0; i < npara && S > 0; i++) {
       int c = para[i];
       int64_t mmax = min64(g->par[c], cur[c]);
@@ -502,6 +535,11 @@ static int oracle_schedule(const odag* g, const uint8_t* r, int64_t* out3, trace
       for (int a = g->succ_off[vR]; a < g->succ_off[vR + 1]; a++)
         trace_put(tr, 3, j, c, part, g->succ[a], 0, 0, 0);
     }
+    for (int i = 1; temporal && i < nl; i++) {
+      /* the chain: each launched part after the one launched before it */
+      int q = launched_part[i - 1], c = launched_part[i];
+      trace_put(tr, 3, j, q, nparts[q], c, launched_whole[c] ? nparts[c] : nparts[c] - 1, 0, 0);
+    }
     (void)seg_node;
     /* completion and release (Algorithm 2, "Update Released_nodes") */
     int nd = 0;
@@ -527,15 +565,16 @@ static int oracle_schedule(const odag* g, const uint8_t* r, int64_t* out3, trace
 
 /* Bound of one DAG under one candidate (r may be NULL).  out3 = {bound,
  * critical-path term, interference term}.  trace/trace_cap optional; the
- * number of records the schedule produced is stored in *trace_n. */
+ * number of records the schedule produced is stored in *trace_n.
+ * para_mode 0: spatial launching loop, 1: temporal (chained) reading. */
 int oracle_bound(int n, int e, const int32_t* src, const int32_t* dst, const int64_t* wcet,
                  const int32_t* par, int M, const uint8_t* r, int64_t* out3, int64_t* trace,
-                 int64_t trace_cap, int64_t* trace_n) {
+                 int64_t trace_cap, int64_t* trace_n, int para_mode) {
   odag g;
   int rc = oracle_prepare(&g, n, e, src, dst, wcet, par, M);
   if (rc == O_OK) {
     trace_t t = { trace, trace_cap, 0 };
-    rc = oracle_schedule(&g, r, out3, &t);
+    rc = oracle_schedule(&g, r, out3, &t, para_mode);
     if (trace_n) *trace_n = t.n;
   }
   odag_free(&g);
@@ -547,12 +586,12 @@ int oracle_bound(int n, int e, const int32_t* src, const int32_t* dst, const int
  * bounds/cp/intf [K] (cp and intf may be NULL). */
 int oracle_bounds_dag(int n, int e, const int32_t* src, const int32_t* dst, const int64_t* wcet,
                       const int32_t* par, int M, int K, const uint8_t* r, int64_t* bounds,
-                      int64_t* cp, int64_t* intf) {
+                      int64_t* cp, int64_t* intf, int para_mode) {
   odag g;
   int rc = oracle_prepare(&g, n, e, src, dst, wcet, par, M);
   for (int c = 0; c < K && rc == O_OK; c++) {
     int64_t o[3];
-    rc = oracle_schedule(&g, c == 0 ? NULL : r + (int64_t)c * n, o, NULL);
+    rc = oracle_schedule(&g, c == 0 ? NULL : r + (int64_t)c * n, o, NULL, para_mode);
     bounds[c] = o[0];
     if (cp) cp[c] = o[1];
     if (intf) intf[c] = o[2];

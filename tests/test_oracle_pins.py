@@ -359,8 +359,8 @@ def test_lower_bounds(seed):
 
 # ---------------------------------------------------------------- brute force
 
-def _check_safe(n, src, dst, w, p, M, r, early_seeds=3):
-    s = oracle.bound(n, src, dst, w, p, M, r, trace=True)
+def _check_safe(n, src, dst, w, p, M, r, early_seeds=3, para_mode=oracle.SPATIAL):
+    s = oracle.bound(n, src, dst, w, p, M, r, trace=True, para_mode=para_mode)
     m, C, preds = oracle.schedule_parts(s, barriers=True)
     worst = oracle.worst_makespan(m, C, preds, M, node_limit=2_000_000)
     if worst < 0:
@@ -434,6 +434,57 @@ def test_bound_safe_against_every_dispatch(seed):
     r = W.random_alloc(rng, p, 255, zero_frac=float(rng.uniform(0, 1)))
     _check_safe(n, src, dst, w, p, M, r)
     _check_safe(n, src, dst, w, p, M, None)
+
+
+@pytest.mark.parametrize("seed", range(60))
+def test_temporal_bound_safe_against_every_dispatch(seed):
+    # the temporal reading of the launching loop, its chain edges kept inside
+    # each slot: no dispatch order ends after the bound
+    rng = np.random.default_rng(3500 + seed)
+    n = int(rng.integers(2, 8))
+    M = int(rng.integers(1, 7))
+    n, src, dst, w, p = W.random_small_dag(rng, n, float(rng.uniform(0.15, 0.6)), 6, 6)
+    r = W.random_alloc(rng, p, 255, zero_frac=float(rng.uniform(0, 1)))
+    _check_safe(n, src, dst, w, p, M, r, para_mode=oracle.TEMPORAL)
+    _check_safe(n, src, dst, w, p, M, None, para_mode=oracle.TEMPORAL)
+
+
+def test_temporal_hand_case():
+    case = load("temporal_cases.json")["cases"][0]
+    src, dst = edges_of(case)
+    args = (case["n"], src, dst, case["wcet"], case["par"], case["M"], np.asarray(case["r"], np.uint8))
+    assert list(oracle.bound(*args)) == case["expect"]["spatial"]
+    assert list(oracle.bound(*args, para_mode=oracle.TEMPORAL)) == case["expect"]["temporal"]
+    s = oracle.bound(*args, trace=True, para_mode=oracle.TEMPORAL)
+    chain = sorted([a, b] for (_, a, ap, b, bp) in s.edges if a != 1 and b != 5)
+    assert chain == case["expect"]["temporal_chain"]
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_temporal_structure(seed):
+    # the temporal reading: parallel parts use at most S SMs each, their C
+    # add up to at most the group's maxC, and at most one of them is a
+    # segment, the last; with M = 1 there are no spare SMs and both readings
+    # agree
+    rng = np.random.default_rng(3600 + seed)
+    for k in (2, 3):
+        batch = W.generate_workload(k, count=6, first=int(rng.integers(0, 1000)))
+        M = W.WORKLOADS[k].num_cus
+        for d in range(batch.num_dags):
+            n, src, dst, w, p = batch.dag(d)
+            r = W.random_alloc(rng, p, M, zero_frac=0.5)
+            s = oracle.bound(n, src, dst, w, p, M, r, trace=True, para_mode=oracle.TEMPORAL)
+            for sl in s.slots:
+                members = [q for q in sl.parts if q.kind == 0]
+                par = [q for q in sl.parts if q.kind != 0]
+                if not par:
+                    continue
+                S = M - sum(q.m for q in members)
+                assert all(q.m <= S for q in par)
+                assert sum(q.C for q in par) <= sl.maxC
+                assert all(q.kind == 1 for q in par[:-1])
+            assert oracle.bound(n, src, dst, w, p, 1, r, para_mode=oracle.TEMPORAL) == \
+                oracle.bound(n, src, dst, w, p, 1, r)
 
 
 def test_bound_tight_on_oversubscribed_group():
