@@ -156,7 +156,7 @@ def write_traffic(fetch_csv: str, write_csv: str) -> int:
     return 0
 
 
-def cpu_baseline(batch, M, K, seed, gpu_bounds, max_seconds: float = 30.0):
+def cpu_baseline(batch, M, K, seed, gpu_bounds, max_seconds: float = 30.0, para_mode: int = 0):
     """Time the CPU oracle (as it stands) on the host cores over the same
     workload (the first DAGs of the batch with the same candidate bytes), DAG
     by DAG across a thread pool, and count mismatches."""
@@ -170,13 +170,13 @@ def cpu_baseline(batch, M, K, seed, gpu_bounds, max_seconds: float = 30.0):
     probe = batch.subset(range(probe_n))
     pa = W.alloc_bytes(probe, M, K, seed=seed)
     t0 = time.perf_counter()
-    oracle.bounds_batch(probe, M, K, pa, threads=threads)
+    oracle.bounds_batch(probe, M, K, pa, threads=threads, para_mode=para_mode)
     per_dag = (time.perf_counter() - t0) / probe_n
     count = int(min(D, max(probe_n, max_seconds * 0.8 / max(per_dag, 1e-9))))
     sample = batch if count == D else batch.subset(range(count))
     alloc = W.alloc_bytes(sample, M, K, seed=seed)
     t0 = time.perf_counter()
-    wb, _, _ = oracle.bounds_batch(sample, M, K, alloc, threads=threads)
+    wb, _, _ = oracle.bounds_batch(sample, M, K, alloc, threads=threads, para_mode=para_mode)
     dt = time.perf_counter() - t0
     mism = int(np.count_nonzero(wb != gpu_bounds[:count].cpu().numpy()))
     return {
@@ -358,15 +358,20 @@ def paper_sweep(count: int = 1000, c_avg: int = 20) -> int:
             db.eval_bounds(b, prop, stream=st)
             g, u, h = (torch.empty(D, dtype=torch.int64, device=dev) for _ in range(3))
             db.baselines(b, g, u, h, stream=st)
+            tprop = torch.empty(D, dtype=torch.int64, device=dev)
+            db.set_para_launch(b, db.PARA_TEMPORAL)
+            db.eval_bounds(b, tprop, stream=st)
             torch.cuda.synchronize()
             b.close()
-            prop, g, u, h = (x.cpu().numpy().astype(np.float64) for x in (prop, g, u, h))
+            prop, g, u, h, tprop = (x.cpu().numpy().astype(np.float64) for x in (prop, g, u, h, tprop))
             row = {"sweep": sweep, "M": cfg["M"], "P": cfg["P"], "layers": list(cfg["depth"]),
                    "mean_nodes": float(np.diff(batch.node_off).mean()),
                    "proposed": float(np.mean(prop / u)), "greedy": float(np.mean(g / u)),
                    "graham_para": float(np.mean(h / u)),
                    "gain_vs_greedy": float(np.mean(1 - prop / g)),
-                   "gain_vs_graham_para": float(np.mean(1 - prop / h))}
+                   "gain_vs_graham_para": float(np.mean(1 - prop / h)),
+                   "proposed_temporal": float(np.mean(tprop / u)),
+                   "temporal_over_spatial": float(np.mean(tprop / prop))}
             rows.append(row)
             print(json.dumps(row), flush=True)
     return 0
@@ -422,6 +427,8 @@ def main() -> int:
     ap.add_argument("--search-train", type=int, default=20000, help="training DAGs (x 256 labelled candidates)")
     ap.add_argument("--search-epochs", type=int, default=60, help="training epochs over those DAGs")
     ap.add_argument("--search-test", type=int, default=100000, help="held-out DAGs (x 4096 seeded candidates)")
+    ap.add_argument("--para", choices=["spatial", "temporal"], default="spatial",
+                    help="reading of the launching loop (the headline is the spatial one)")
     ap.add_argument("--tuning", action="append", default=[], metavar="KEY=VALUE",
                     help="dagbound_set_tuning option for the timed batches (repeatable)")
     ap.add_argument("--large-train", type=int, default=2000, help="large-compiler training DAGs (x 256)")
@@ -488,6 +495,8 @@ def main() -> int:
 
     def step(record: bool):
         b = db.create_batch(*inputs, M, stream=stream)
+        if args.para == "temporal":
+            db.set_para_launch(b, db.PARA_TEMPORAL)
         for key, val in tuning:
             db.set_tuning(b, key, val)
         if args.seeded:
@@ -550,6 +559,7 @@ def main() -> int:
             "num_dags": D, "candidates": K, "num_cus": M,
             "total_nodes": int(batch.node_off[-1]), "total_edges": int(batch.edge_off[-1]),
             **({"tuning": dict(tuning)} if tuning else {}),
+            **({"para_launch": "temporal"} if args.para == "temporal" else {}),
         },
         "roofline": {
             "bound": "hbm",
@@ -576,7 +586,8 @@ def main() -> int:
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         torch.cuda.synchronize()
-        out["cpu_baseline"] = cpu_baseline(batch, M, K, wl.seed, bounds.view(D, K))
+        out["cpu_baseline"] = cpu_baseline(batch, M, K, wl.seed, bounds.view(D, K),
+                                           para_mode=1 if args.para == "temporal" else 0)
     print(json.dumps(out), flush=True)
     return 0
 

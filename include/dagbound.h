@@ -67,6 +67,7 @@ enum {
 enum { DAGBOUND_PTR_HOST = 0, DAGBOUND_PTR_DEVICE = 1 };
 enum { DAGBOUND_ALLOC_EXPLICIT = 0, DAGBOUND_ALLOC_SEEDED = 1 };
 enum { DAGBOUND_SEARCH_EXHAUSTIVE = 0, DAGBOUND_SEARCH_SURROGATE = 1 };
+enum { DAGBOUND_PARA_SPATIAL = 0, DAGBOUND_PARA_TEMPORAL = 1 };
 
 /* Limits of this build. */
 #define DAGBOUND_MAX_NODES_PER_DAG 8000  /* N_d, source and sink included */
@@ -168,6 +169,24 @@ dagbound_status dagbound_eval_bounds(dagbound_batch* batch, int64_t* bounds, int
 dagbound_status dagbound_best_allocation(dagbound_batch* batch, uint32_t search, int32_t top_k,
                                          const dagbound_model* model, int32_t* best_idx,
                                          int64_t* best_bound, uint32_t ptr_kind, void* hip_stream);
+
+/*
+ * dagbound_set_para_launch -- the reading of the launching loop of
+ * Section 4.1 (Eqs. 6-7, Algorithm 2) used by every later evaluation of the
+ * batch (eval_bounds, best_allocation, get_schedule, run_schedule).
+ *   DAGBOUND_PARA_SPATIAL (default): the spare SMs S shrink by each launched
+ *     parallel node's m; a node that does not fit in maxC * m is segmented
+ *     there and launching stops.
+ *   DAGBOUND_PARA_TEMPORAL: WS_j read as an area of S SMs for the slot's
+ *     time maxC; every parallel node takes m = min(its target, S), the
+ *     launched nodes run one after another on those SMs (chain edges, in
+ *     the schedule dump as EDGE records inside the slot), and the budget is
+ *     the time left; a node that does not fit in (time left) * m is
+ *     segmented there and launching stops.  Both readings keep every slot
+ *     within M SMs, so Lemma 1 holds for either.
+ * Errors: E_ARG.
+ */
+dagbound_status dagbound_set_para_launch(dagbound_batch* batch, uint32_t mode);
 
 /*
  * dagbound_run_schedule -- runs the schedule of DAG d under candidate c on

@@ -209,6 +209,7 @@ struct dagbound_batch {
   bool has_alloc = false;
   int32_t K = 0;
   uint32_t mode = DAGBOUND_ALLOC_EXPLICIT;
+  int32_t para_mode = DAGBOUND_PARA_SPATIAL;  // reading of the launching loop
   const uint8_t* alloc = nullptr;
   void* alloc_owned = nullptr;
   size_t alloc_owned_size = 0;
@@ -242,6 +243,7 @@ SweepArgs sweep_args(const dagbound_batch* b) {
   a.K = b->K;
   a.alloc = b->mode == DAGBOUND_ALLOC_EXPLICIT ? b->alloc : nullptr;
   a.seed = b->seed;
+  a.temporal = b->para_mode;
   a.max_n = b->max_n;
   a.max_e = b->max_e;
   a.order = b->size_classes ? b->order : nullptr;
@@ -765,7 +767,7 @@ static hipError_t schedule_all(dagbound_batch* b, int32_t d, int32_t c, std::vec
     e = hipDeviceSynchronize();
     if (e == hipSuccess)
       e = launch_schedule(b->t, d, c, b->K, b->M, b->mode == DAGBOUND_ALLOC_EXPLICIT ? b->alloc : nullptr, b->seed,
-                          b->max_n, d_rec, cap, d_out, nullptr);
+                          b->max_n, d_rec, cap, d_out, b->para_mode, nullptr);
     int64_t out[4] = {0, 0, 0, 0};
     if (e == hipSuccess) e = hipMemcpy(out, d_out, sizeof out, hipMemcpyDeviceToHost);
     if (e == hipSuccess && out[0] <= cap) {
@@ -854,7 +856,7 @@ dagbound_status dagbound_get_schedule(dagbound_batch* b, int32_t d, int32_t c, i
   e = hipDeviceSynchronize();
   if (e == hipSuccess)
     e = launch_schedule(b->t, d, c, b->K, b->M, b->mode == DAGBOUND_ALLOC_EXPLICIT ? b->alloc : nullptr, b->seed,
-                        b->max_n, d_rec, cap, d_out, nullptr);
+                        b->max_n, d_rec, cap, d_out, b->para_mode, nullptr);
   int64_t out[4] = {0, 0, 0, 0};
   if (e == hipSuccess) e = hipMemcpy(out, d_out, sizeof out, hipMemcpyDeviceToHost);
   if (e == hipSuccess && cap > 0 && out[0] > 0)
@@ -900,6 +902,18 @@ dagbound_status dagbound_baselines(dagbound_batch* b, int64_t* greedy, int64_t* 
     dev_release(tmp, tmp_size, b->device);
   }
   if (e != hipSuccess) return hip_fail(e, "comparison bounds");
+  return DAGBOUND_OK;
+}
+
+dagbound_status dagbound_set_para_launch(dagbound_batch* b, uint32_t mode) {
+  g_err.clear();
+  if (!b) return fail(DAGBOUND_E_ARG, "batch is NULL");
+  if (mode != DAGBOUND_PARA_SPATIAL && mode != DAGBOUND_PARA_TEMPORAL) return fail(DAGBOUND_E_ARG, "bad mode %u", mode);
+  if (b->para_mode != (int32_t)mode) {
+    b->para_mode = (int32_t)mode;
+    b->best_gen = ~0ull;  // results change: the cached minimum and any recorded graph are stale
+    b->tune_gen++;
+  }
   return DAGBOUND_OK;
 }
 

@@ -118,6 +118,7 @@ struct SweepArgs {
   int32_t list_len;             // DAGs in the launch
   const uint8_t* alloc;         // explicit bytes, or nullptr when seeded
   uint64_t seed;
+  int32_t temporal;             // launching loop (Eqs. 6-7): 0 spatial, 1 temporal (chained) reading
   int64_t* bounds;              // [D*K] or nullptr
   int64_t* cp;                  // [D*K] or nullptr
   int64_t* intf;                // [D*K] or nullptr
@@ -185,9 +186,10 @@ hipError_t launch_best_final(const unsigned long long* best, int32_t D, int32_t*
 // Schedule dump of DAG d under candidate c (schedule.hip): records of 8
 // int64 into rec[cap][8]; out = {records the schedule has, bound, critical-
 // path term, interference term}.  alloc = explicit bytes (K per DAG) or
-// nullptr for the seeded candidates of `seed`.
+// nullptr for the seeded candidates of `seed`; temporal selects the chained
+// reading of the launching loop.
 hipError_t launch_schedule(const Tables& t, int32_t d, int32_t c, int32_t K, int32_t M, const uint8_t* alloc,
-                           uint64_t seed, int32_t max_n, int64_t* rec, int64_t cap, int64_t* out,
+                           uint64_t seed, int32_t max_n, int64_t* rec, int64_t cap, int64_t* out, int32_t temporal,
                            hipStream_t stream);
 
 // ---------------------------------------------------------------------------

@@ -718,7 +718,7 @@ __device__ inline void wave_sync() {
   __builtin_amdgcn_wave_barrier();
 }
 
-template <bool SMALL, bool RS, bool C8>
+template <bool SMALL, bool RS, bool C8, bool TP>
 __device__ void eval_one(const SweepArgs& a, uint64_t item, unsigned char* smem, uint32_t* res) {
   const int lane = threadIdx.x;
   const uint64_t li = item / (uint64_t)a.K;
@@ -960,7 +960,69 @@ __device__ void eval_one(const SweepArgs& a, uint64_t item, unsigned char* smem,
     // the first reached node that does not fit in maxC * m is segmented and
     // the launching stops.
     const uint32_t S = sm < M ? M - sm : 0u;
-    if (S > 0 && j0 >= 0) {
+    if (TP && S > 0 && j0 >= 0) {
+      // temporal reading: every node keeps the S spare units and the launched
+      // nodes run one after another; the node whose time prefix T_i is below
+      // maxC is reached, fits if its C = ceil(load / m) ends by maxC, and the
+      // first reached node that does not is segmented at (maxC - T_i) * m
+      uint32_t Tc = 0;
+      bool stop = false;
+      for (int h = j0 >> 6; h < 2 && !stop; h++) {
+        const uint64_t pw = h ? pw1 : pw0;
+        uint64_t nz = h ? nz1 : nz0;
+        while (nz && !stop) {
+          const int jl = __builtin_ctzll(nz);
+          nz &= nz - 1;
+          const int j = h * WAVE + jl;
+          const uint64_t word = readlane64(pw, jl);
+          const bool on = (word >> lane) & 1;
+          const int s = j * WAVE + lane;
+          uint4 r = pre;
+          if (j != j0 && on) r = nrec[s];
+          const uint64_t sw = segw[j];
+          uint32_t cc = 0, mc = 1, ct = 0;
+          if (on) {
+            cc = ((sw >> lane) & 1) ? res[s] : r.x;
+            const uint32_t pp = r.y & 0xFFFFu;
+            const uint32_t mx = min(pp, cc);
+            const uint32_t rr = r_of(s, r.w & 0xFFFFu, pp);
+            mc = min(rr ? min(rr, mx) : mx, S);
+            ct = ceil_div<SMALL>(cc, mc);
+          }
+          // time prefixes saturate at maxC (no node past it is reached), so
+          // the sums stay in range for any load
+          const uint32_t incl = wave_scan<uint32_t>(min(ct, maxC), 0u, [maxC](uint32_t p, uint32_t q) {
+            return min(p + q, maxC);
+          });
+          // the prefix of the lanes below: a whole-wave shift right by one
+          // lane (DPP, every lane active; lane 0 takes 0)
+          const uint32_t excl = dpp32<0x138, 0xf>(incl, 0u);
+          const uint32_t Ti = min(Tc + excl, maxC);
+          const bool reached = on && Ti < maxC;
+          const uint64_t cap = (uint64_t)(reached ? maxC - Ti : 0u) * mc;
+          const bool fits = (uint64_t)cc <= cap;
+          const uint64_t nofit = __ballot(reached && !fits);
+          uint64_t launched = __ballot(reached && fits);
+          uint64_t segbit = 0;
+          if (nofit) {
+            const int f = __builtin_ctzll(nofit);
+            launched &= lanes_below(f);
+            if (lane == f) res[s] = cc - (uint32_t)cap;
+            segbit = 1ull << f;
+            stop = true;
+          } else {
+            Tc = min(Tc + lane63(incl), maxC);
+            stop = Tc >= maxC;
+          }
+          if (lane == 0) {
+            relw[j] &= ~launched;
+            segw[j] = (sw & ~launched) | segbit;
+          }
+          release(launched, r.z, r.w);
+        }
+      }
+    }
+    if (!TP && S > 0 && j0 >= 0) {
       uint32_t Pc = 0;
       bool stop = false;
       for (int h = j0 >> 6; h < 2 && !stop; h++) {
@@ -1037,7 +1099,7 @@ __device__ void eval_one(const SweepArgs& a, uint64_t item, unsigned char* smem,
   }
 }
 
-template <bool SMALL, bool RS, bool C8>
+template <bool SMALL, bool RS, bool C8, bool TP>
 __global__ __launch_bounds__(64) void k_eval_large(SweepArgs a, unsigned long long* counter, uint64_t total) {
   extern __shared__ __align__(16) unsigned char smem[];
   uint32_t* res = a.gres + (size_t)blockIdx.x * (size_t)a.max_n;
@@ -1046,15 +1108,15 @@ __global__ __launch_bounds__(64) void k_eval_large(SweepArgs a, unsigned long lo
     if (threadIdx.x == 0) item = atomicAdd(counter, 1ull);
     item = ((uint64_t)uni((uint32_t)(item >> 32)) << 32) | uni((uint32_t)item);  // lane 0's
     if (item >= total) break;
-    eval_one<SMALL, RS, C8>(a, item, smem, res);
+    eval_one<SMALL, RS, C8, TP>(a, item, smem, res);
     wave_sync();
   }
 }
 
-template <bool SMALL, bool RS, bool C8>
+template <bool SMALL, bool RS, bool C8, bool TP>
 hipError_t launch_large_v(const SweepArgs& a, unsigned long long* counter, uint64_t total, hipStream_t stream) {
   const size_t lds = eval_lds(a.max_n, C8, RS).total;
-  const void* fn = (const void*)k_eval_large<SMALL, RS, C8>;
+  const void* fn = (const void*)k_eval_large<SMALL, RS, C8, TP>;
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   int per_cu = 0, dev = 0, cus = 0;
@@ -1065,14 +1127,17 @@ hipError_t launch_large_v(const SweepArgs& a, unsigned long long* counter, uint6
   const uint64_t cap = (uint64_t)max(1, per_cu) * (uint64_t)max(1, cus);
   uint64_t g = total < cap ? total : cap;
   if (g > (uint64_t)LARGE_SLOTS) g = LARGE_SLOTS;
-  hipLaunchKernelGGL((k_eval_large<SMALL, RS, C8>), dim3((unsigned)g), dim3(WAVE), lds, stream, a, counter, total);
+  hipLaunchKernelGGL((k_eval_large<SMALL, RS, C8, TP>), dim3((unsigned)g), dim3(WAVE), lds, stream, a, counter, total);
   return hipGetLastError();
 }
 
 template <bool SMALL, bool RS>
 hipError_t launch_large_c(const SweepArgs& a, unsigned long long* counter, uint64_t total, hipStream_t stream) {
-  return a.small_indeg ? launch_large_v<SMALL, RS, true>(a, counter, total, stream)
-                       : launch_large_v<SMALL, RS, false>(a, counter, total, stream);
+  if (a.temporal)
+    return a.small_indeg ? launch_large_v<SMALL, RS, true, true>(a, counter, total, stream)
+                         : launch_large_v<SMALL, RS, false, true>(a, counter, total, stream);
+  return a.small_indeg ? launch_large_v<SMALL, RS, true, false>(a, counter, total, stream)
+                       : launch_large_v<SMALL, RS, false, false>(a, counter, total, stream);
 }
 
 }  // namespace

@@ -51,6 +51,7 @@ struct SchedArgs {
   int64_t* rec;          // [cap][8]
   int64_t cap;
   int64_t* out;          // {records, bound, critical-path term, interference term}
+  int32_t temporal;      // launching loop: 0 spatial, 1 temporal (chained) reading
 };
 
 __global__ __launch_bounds__(64) void k_schedule(SchedArgs a) {
@@ -162,6 +163,39 @@ __global__ __launch_bounds__(64) void k_schedule(SchedArgs a) {
     // one that does not fit in maxC * m is segmented there and launching stops
     int64_t S = M - sum_m > 0 ? M - sum_m : 0;
     int nl = 0;
+    if (a.temporal && S > 0) {
+      // temporal reading: every node keeps the S spare units, the launched
+      // nodes run one after another within the slot's time maxC
+      int64_t T = maxC, peak = 0;
+      for (int w = 0; w < NW && T > 0; w++) {
+        uint64_t bits = relw[w];
+        while (bits && T > 0) {
+          const int s = w * WAVE + __builtin_ctzll(bits);
+          bits &= bits - 1;
+          if (flags[s] & F_INP) continue;
+          const int64_t mmax = min((int64_t)pp[s], (int64_t)cur[s]);
+          const int64_t mc = min(rb[s] ? min((int64_t)rb[s], mmax) : mmax, S);
+          const int64_t capc = T * mc;
+          peak = max(peak, mc);
+          llist[nl++] = (uint16_t)s;
+          if ((int64_t)cur[s] > capc) {
+            put(2, j, perm[s], nparts[s], 2, mc, T, capc);
+            nparts[s]++;
+            cur[s] -= (uint32_t)capc;
+            A += mc * T;
+            T = 0;
+            break;
+          }
+          const int64_t Cc = cdiv(cur[s], mc);
+          put(2, j, perm[s], nparts[s], 1, mc, Cc, cur[s]);
+          flags[s] |= F_WHOLE;
+          A += mc * Cc;
+          T -= Cc;
+        }
+      }
+      sum_m += peak;
+      S = 0;
+    }
     for (int w = 0; w < NW && S > 0; w++) {
       uint64_t bits = relw[w];
       while (bits && S > 0) {
@@ -210,6 +244,11 @@ __global__ __launch_bounds__(64) void k_schedule(SchedArgs a) {
       const int part = (flags[s] & F_WHOLE) ? nparts[s] : nparts[s] - 1;
       for (uint32_t e = soff[vRs]; e < soff[vRs + 1]; e++) put(3, j, perm[s], part, perm[succ[e]], 0, 0, 0);
     }
+    for (int i = 1; a.temporal && i < nl; i++) {
+      // the chain of the temporal reading: each launched part after the one before
+      const int q = llist[i - 1], s = llist[i];
+      put(3, j, perm[q], nparts[q], perm[s], (flags[s] & F_WHOLE) ? nparts[s] : nparts[s] - 1, 0, 0);
+    }
     // completion: the members and the nodes launched whole; then releases
     for (int pass = 0; pass < 2; pass++) {
       const int cnt = pass ? nl : nP;
@@ -249,10 +288,10 @@ __global__ __launch_bounds__(64) void k_schedule(SchedArgs a) {
 }  // namespace
 
 hipError_t launch_schedule(const Tables& t, int32_t d, int32_t c, int32_t K, int32_t M, const uint8_t* alloc,
-                           uint64_t seed, int32_t max_n, int64_t* rec, int64_t cap, int64_t* out,
+                           uint64_t seed, int32_t max_n, int64_t* rec, int64_t cap, int64_t* out, int32_t temporal,
                            hipStream_t stream) {
   if (max_n > LARGE_MAX_N) return hipErrorInvalidValue;
-  SchedArgs a{t, d, c, K, M, alloc, seed, rec, cap, out};
+  SchedArgs a{t, d, c, K, M, alloc, seed, rec, cap, out, temporal};
   const size_t lds = sched_lds(max_n > 0 ? max_n : 1).total;
   hipError_t e = hipFuncSetAttribute((const void*)k_schedule, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;

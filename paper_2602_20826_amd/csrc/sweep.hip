@@ -286,7 +286,7 @@ __device__ inline uint32_t round_share_small(uint32_t cv, uint32_t M, uint32_t W
 // One (DAG, 64-candidate tile).  Returns true if a lane's residual table
 // overflowed (nothing was written; the tile must be redone by the
 // global-table pass).
-template <int NW, bool BIG, bool SMALL, bool RS>
+template <int NW, bool BIG, bool SMALL, bool RS, bool TP>
 __device__ bool eval_tile(const SweepArgs& a, int item, unsigned char* smem, uint32_t* gres, uint64_t* grows) {
   constexpr bool REG = RowsInRegs<NW, RS>::value;
   constexpr bool GROWS = RowsInGlobal<NW, RS>::value;
@@ -537,6 +537,9 @@ __device__ bool eval_tile(const SweepArgs& a, int item, unsigned char* smem, uin
     uint32_t rc = RS ? 0u : s_r[ci * WAVE + lane];
     uint32_t mw = BIG ? 0u : s_map[(ci >> 3) * WAVE + lane];
     bool go = cn >= 0;
+    // temporal reading: S stays for every node, the launched nodes run one
+    // after another and spend the slot's time maxC
+    uint32_t T = maxC;
     while (go) {
       const int cur = cn;
       const uint2 ndc = nd;
@@ -561,15 +564,20 @@ __device__ bool eval_tile(const SweepArgs& a, int item, unsigned char* smem, uin
       if (!BIG) mw = s_map[(ci >> 3) * WAVE + lane];
       const uint32_t mx = min(ndc.y & 0xFFFFu, cc);
       const uint32_t mc = min(rcc ? min(rcc, mx) : mx, S);
-      const uint64_t cap = (uint64_t)maxC * mc;
+      const uint64_t cap = (uint64_t)(TP ? T : maxC) * mc;
       const bool fits = (uint64_t)cc <= cap;
       if (!fits) {
         cseg = cur;
         csg = sg;
         cleft = cc - (uint32_t)cap;
       }
-      S -= fits ? mc : 0u;
-      go = fits && S != 0 && cn >= 0;
+      if (TP) {
+        T -= fits ? ceil_div<SMALL>(cc, mc) : 0u;
+        go = fits && T != 0 && cn >= 0;
+      } else {
+        S -= fits ? mc : 0u;
+        go = fits && S != 0 && cn >= 0;
+      }
     }
     if (CURSOR) pq.rest(Q);
     if (cn >= 0) bit_set<NW>(Q, cn);  // read ahead, not launched
@@ -742,16 +750,16 @@ __device__ bool eval_tile(const SweepArgs& a, int item, unsigned char* smem, uin
 // First pass: one tile per workgroup, residual table in LDS.  A tile that
 // overflows it restarts at once with one of the global-memory tables, or,
 // when all are taken, is listed for the second pass.
-template <int NW, bool SMALL, bool RS>
+template <int NW, bool SMALL, bool RS, bool TP>
 __device__ void first_pass_tile(const SweepArgs& a, int item, unsigned char* smem, uint32_t* counters,
                                 uint32_t* list, uint64_t* grows) {
-  if (eval_tile<NW, false, SMALL, RS>(a, item, smem, nullptr, grows)) {
+  if (eval_tile<NW, false, SMALL, RS, TP>(a, item, smem, nullptr, grows)) {
     uint32_t g = 0;
     if (threadIdx.x == 0) g = atomicAdd(&counters[1], 1u);
     g = __shfl(g, 0);
     __syncthreads();
     if (g < (uint32_t)GLOBAL_PASS_GRID) {
-      eval_tile<NW, true, SMALL, RS>(a, item, smem, a.gres + (size_t)g * (size_t)a.max_n * WAVE, grows);
+      eval_tile<NW, true, SMALL, RS, TP>(a, item, smem, a.gres + (size_t)g * (size_t)a.max_n * WAVE, grows);
     } else if (threadIdx.x == 0) {
       list[atomicAdd(&counters[0], 1u)] = (uint32_t)item;
     }
@@ -764,13 +772,13 @@ __device__ inline uint64_t* rows_of(const SweepArgs& a, int slot) {
   return a.grows ? a.grows + (size_t)slot * 2 * (size_t)a.max_n * NW : nullptr;
 }
 
-template <int NW, bool SMALL, bool RS>
+template <int NW, bool SMALL, bool RS, bool TP>
 __global__ __launch_bounds__(64) void k_eval(SweepArgs a, uint32_t* counters, uint32_t* list) {
   extern __shared__ __align__(16) unsigned char smem[];
   // rows in global memory run the persistent form only (their row regions
   // are per running workgroup)
   if constexpr (!RowsInGlobal<NW, RS>::value)
-    first_pass_tile<NW, SMALL, RS>(a, blockIdx.x, smem, counters, list, nullptr);
+    first_pass_tile<NW, SMALL, RS, TP>(a, blockIdx.x, smem, counters, list, nullptr);
 }
 
 // Persistent form of the first pass: as many workgroups as fit on the device
@@ -778,7 +786,7 @@ __global__ __launch_bounds__(64) void k_eval(SweepArgs a, uint32_t* counters, ui
 // Every workgroup leaves the loop when the counter passes `total`.
 // At least two waves per SIMD: the eight-word-row class would otherwise take
 // one (a few spilled registers cost less than the lost latency hiding).
-template <int NW, bool SMALL, bool RS>
+template <int NW, bool SMALL, bool RS, bool TP>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_eval_persistent(SweepArgs a, uint32_t* counters, uint32_t* list,
                                                         int total) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -788,14 +796,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
     if (threadIdx.x == 0) item = atomicAdd(&counters[2], 1u);
     item = __shfl(item, 0);
     if (item >= (uint32_t)total) break;
-    first_pass_tile<NW, SMALL, RS>(a, (int)item, smem, counters, list, grows);
+    first_pass_tile<NW, SMALL, RS, TP>(a, (int)item, smem, counters, list, grows);
     __syncthreads();
   }
 }
 
 // Second pass: the tiles the first pass listed (or every tile when
 // `direct`), residual tables in global memory sized to hold every node.
-template <int NW, bool SMALL, bool RS>
+template <int NW, bool SMALL, bool RS, bool TP>
 __global__ __launch_bounds__(64) void k_eval_global(SweepArgs a, const uint32_t* counters, const uint32_t* list,
                                                     int direct, int total) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -804,7 +812,7 @@ __global__ __launch_bounds__(64) void k_eval_global(SweepArgs a, const uint32_t*
   uint64_t* grows = rows_of<NW>(a, blockIdx.x);
   for (int q = blockIdx.x; q < count; q += gridDim.x) {
     const int item = direct ? q : (int)list[q];
-    eval_tile<NW, true, SMALL, RS>(a, item, smem, gres, grows);
+    eval_tile<NW, true, SMALL, RS, TP>(a, item, smem, gres, grows);
     __syncthreads();
   }
 }
@@ -826,7 +834,7 @@ __global__ void k_best_final(const unsigned long long* best, int32_t D, int32_t*
   }
 }
 
-template <int NW, bool SMALL, bool RS>
+template <int NW, bool SMALL, bool RS, bool TP>
 hipError_t launch_nw(const SweepArgs& a, uint32_t* counters, uint32_t* list, hipStream_t stream) {
   const int ntile = (a.K + WAVE - 1) / WAVE;
   const int total = a.list_len * ntile;
@@ -836,7 +844,7 @@ hipError_t launch_nw(const SweepArgs& a, uint32_t* counters, uint32_t* list, hip
   // rows in global memory need a row region per running workgroup: persistent only
   if (a.path != EVAL_PATH_GLOBAL && (a.persistent || GROWS)) {
     const size_t lds = lds_layout(a.max_n, NW, false, RS).total;
-    const void* fn = (const void*)k_eval_persistent<NW, SMALL, RS>;
+    const void* fn = (const void*)k_eval_persistent<NW, SMALL, RS, TP>;
     e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     int per_cu = 0, dev = 0, cus = 0;
@@ -846,40 +854,48 @@ hipError_t launch_nw(const SweepArgs& a, uint32_t* counters, uint32_t* list, hip
     if (e != hipSuccess) return e;
     int grid = max(1, min(total, max(1, per_cu) * max(1, cus)));
     if (GROWS) grid = min(grid, ROW_REGIONS);
-    hipLaunchKernelGGL((k_eval_persistent<NW, SMALL, RS>), dim3(grid), dim3(WAVE), lds, stream, a, counters, list,
+    hipLaunchKernelGGL((k_eval_persistent<NW, SMALL, RS, TP>), dim3(grid), dim3(WAVE), lds, stream, a, counters, list,
                        total);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   } else if (a.path != EVAL_PATH_GLOBAL) {
     const size_t lds = lds_layout(a.max_n, NW, false, RS).total;
-    e = hipFuncSetAttribute((const void*)k_eval<NW, SMALL, RS>,
+    e = hipFuncSetAttribute((const void*)k_eval<NW, SMALL, RS, TP>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_eval<NW, SMALL, RS>), dim3(total), dim3(WAVE), lds, stream, a, counters, list);
+    hipLaunchKernelGGL((k_eval<NW, SMALL, RS, TP>), dim3(total), dim3(WAVE), lds, stream, a, counters, list);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   const size_t lds = lds_layout(a.max_n, NW, true, RS).total;
-  e = hipFuncSetAttribute((const void*)k_eval_global<NW, SMALL, RS>,
+  e = hipFuncSetAttribute((const void*)k_eval_global<NW, SMALL, RS, TP>,
                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   const int grid = a.path == EVAL_PATH_GLOBAL ? min(total, GLOBAL_PASS_GRID) : GLOBAL_PASS_GRID;
-  hipLaunchKernelGGL((k_eval_global<NW, SMALL, RS>), dim3(grid), dim3(WAVE), lds, stream, a, counters, list,
+  hipLaunchKernelGGL((k_eval_global<NW, SMALL, RS, TP>), dim3(grid), dim3(WAVE), lds, stream, a, counters, list,
                      a.path == EVAL_PATH_GLOBAL ? 1 : 0, total);
   return hipGetLastError();
 }
 
 // Seeded candidates of DAGs above 128 nodes are drawn where they are used
 // (no LDS for the bytes); smaller DAGs keep them in LDS.
-template <bool SMALL>
-hipError_t launch_class(int cls, const SweepArgs& a, uint32_t* counters, uint32_t* list, hipStream_t stream) {
+template <bool SMALL, bool TP>
+hipError_t launch_class_tp(int cls, const SweepArgs& a, uint32_t* counters, uint32_t* list, hipStream_t stream) {
   const bool rs = a.alloc == nullptr;
   switch (cls) {
-    case 0: return launch_nw<1, SMALL, false>(a, counters, list, stream);
-    case 1: return launch_nw<2, SMALL, false>(a, counters, list, stream);
-    case 2: return rs ? launch_nw<4, SMALL, true>(a, counters, list, stream)
-                      : launch_nw<4, SMALL, false>(a, counters, list, stream);
-    default: return rs ? launch_nw<8, SMALL, true>(a, counters, list, stream)
-                       : launch_nw<8, SMALL, false>(a, counters, list, stream);
+    case 0: return launch_nw<1, SMALL, false, TP>(a, counters, list, stream);
+    case 1: return launch_nw<2, SMALL, false, TP>(a, counters, list, stream);
+    case 2: return rs ? launch_nw<4, SMALL, true, TP>(a, counters, list, stream)
+                      : launch_nw<4, SMALL, false, TP>(a, counters, list, stream);
+    default: return rs ? launch_nw<8, SMALL, true, TP>(a, counters, list, stream)
+                       : launch_nw<8, SMALL, false, TP>(a, counters, list, stream);
   }
+}
+
+// The two readings of the launching loop are separate kernels, so the
+// spatial one keeps its code and registers.
+template <bool SMALL>
+hipError_t launch_class(int cls, const SweepArgs& a, uint32_t* counters, uint32_t* list, hipStream_t stream) {
+  return a.temporal ? launch_class_tp<SMALL, true>(cls, a, counters, list, stream)
+                    : launch_class_tp<SMALL, false>(cls, a, counters, list, stream);
 }
 
 }  // namespace

@@ -21,6 +21,7 @@ OK, E_ARG, E_CYCLE, E_RANGE, E_DUP_EDGE, E_OOM, E_DEVICE, E_STATE, E_OVERFLOW, E
 PTR_HOST, PTR_DEVICE = 0, 1
 ALLOC_EXPLICIT, ALLOC_SEEDED = 0, 1
 SEARCH_EXHAUSTIVE, SEARCH_SURROGATE = 0, 1
+PARA_SPATIAL, PARA_TEMPORAL = 0, 1
 MAX_NODES_PER_DAG = 8000
 MAX_CANDIDATES = 1 << 22
 MODEL_PARAMS = 100356
@@ -29,6 +30,7 @@ MODEL_PARAMS = 100356
 EXPORTS = (
     "dagbound_create_batch", "dagbound_set_allocations", "dagbound_eval_bounds",
     "dagbound_best_allocation", "dagbound_get_division", "dagbound_get_schedule", "dagbound_baselines", "dagbound_run_schedule",
+    "dagbound_set_para_launch",
     "dagbound_set_tuning",
     "dagbound_destroy_batch", "dagbound_model_create", "dagbound_model_destroy",
     "dagbound_model_params", "dagbound_model_forward", "dagbound_model_train_step",
@@ -67,6 +69,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.dagbound_get_division.argtypes = [P, I32, P, P, P, P]
     lib.dagbound_get_schedule.restype = I32
     lib.dagbound_get_schedule.argtypes = [P, I32, I32, P, ctypes.c_int64, P, P]
+    lib.dagbound_set_para_launch.restype = I32
+    lib.dagbound_set_para_launch.argtypes = [P, U32]
     lib.dagbound_run_schedule.restype = I32
     lib.dagbound_run_schedule.argtypes = [P, I32, I32, ctypes.c_int64, I32, I32, P, P]
     lib.dagbound_baselines.restype = I32
@@ -232,6 +236,12 @@ def baselines(batch: Batch, greedy=None, greedy_unaware=None, graham_para=None, 
                                             (graham_para, "int64")])
     _check(lib.dagbound_baselines(ctypes.c_void_p(batch.handle), p_g, p_u, p_h, kind, _stream_ptr(stream)))
     return greedy, greedy_unaware, graham_para
+
+
+def set_para_launch(batch: Batch, mode: int) -> None:
+    """dagbound_set_para_launch: PARA_SPATIAL or PARA_TEMPORAL reading of the
+    launching loop for the batch's later evaluations."""
+    _check(load_library().dagbound_set_para_launch(ctypes.c_void_p(batch.handle), int(mode)))
 
 
 def run_schedule(batch: Batch, d: int, c: int, tick_ns: int, barriers: bool = True, reps: int = 10):

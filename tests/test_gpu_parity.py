@@ -34,7 +34,8 @@ def say(*a):
     print(*a, flush=True)
 
 
-def gpu_eval(torch_dev, batch, M, K, alloc=None, seed=None, device_ptrs=True, terms=True, tuning=None):
+def gpu_eval(torch_dev, batch, M, K, alloc=None, seed=None, device_ptrs=True, terms=True, tuning=None,
+             para_mode=None):
     """Run create_batch / set_allocations / eval_bounds / best_allocation."""
     import paper_2602_20826_amd as db
 
@@ -45,6 +46,8 @@ def gpu_eval(torch_dev, batch, M, K, alloc=None, seed=None, device_ptrs=True, te
         stream = torch.cuda.current_stream(dev)
         b = db.create_batch(t(batch.node_off), t(batch.edge_off), t(batch.src), t(batch.dst),
                             t(batch.wcet), t(batch.par), M, stream=stream)
+        if para_mode is not None:
+            db.set_para_launch(b, para_mode)
         for key, val in (tuning or {}).items():
             db.set_tuning(b, key, val)
         if seed is None:
@@ -64,6 +67,8 @@ def gpu_eval(torch_dev, batch, M, K, alloc=None, seed=None, device_ptrs=True, te
     else:
         b = db.create_batch(batch.node_off, batch.edge_off, batch.src, batch.dst, batch.wcet,
                             batch.par, M)
+        if para_mode is not None:
+            db.set_para_launch(b, para_mode)
         for key, val in (tuning or {}).items():
             db.set_tuning(b, key, val)
         if seed is None:
@@ -84,10 +89,10 @@ def gpu_eval(torch_dev, batch, M, K, alloc=None, seed=None, device_ptrs=True, te
     return rs(bounds), rs(cp), rs(it), bi, bb
 
 
-def check_against_oracle(batch, M, K, alloc, got, dags=None, threads=8):
+def check_against_oracle(batch, M, K, alloc, got, dags=None, threads=8, para_mode=oracle.SPATIAL):
     bounds, cp, it, bi, bb = got
     idx = np.arange(batch.num_dags) if dags is None else np.asarray(dags)
-    wb, wc, wi = oracle.bounds_batch(batch, M, K, alloc, dags=idx, threads=threads)
+    wb, wc, wi = oracle.bounds_batch(batch, M, K, alloc, dags=idx, threads=threads, para_mode=para_mode)
     bad = np.argwhere(bounds[idx] != wb)
     assert bad.size == 0, f"{len(bad)} mismatches, first (dag, cand) = {idx[bad[0][0]]}, {bad[0][1]}: " \
                           f"gpu {bounds[idx][tuple(bad[0])]} oracle {wb[tuple(bad[0])]}"
