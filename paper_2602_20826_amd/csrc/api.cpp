@@ -220,6 +220,39 @@ struct dagbound_batch {
 
 namespace {
 
+// Host arrays of released batches, kept for the next batch: a fresh array
+// of a few MB is paged in on first touch, which would cost more than
+// create_batch's own host work.
+std::mutex g_host_mu;
+std::vector<std::vector<int64_t>> g_host64;
+std::vector<std::vector<int32_t>> g_host32;
+constexpr size_t HOST_POOL = 8;
+
+template <class T>
+std::vector<T> host_take(std::vector<std::vector<T>>& pool, size_t n) {
+  std::vector<T> v;
+  {
+    std::lock_guard<std::mutex> lk(g_host_mu);
+    int best = -1;
+    for (size_t i = 0; i < pool.size(); i++)
+      if (pool[i].capacity() >= n && (best < 0 || pool[i].capacity() < pool[best].capacity())) best = (int)i;
+    if (best >= 0) {
+      v = std::move(pool[best]);
+      pool.erase(pool.begin() + best);
+    }
+  }
+  v.resize(n);
+  return v;
+}
+
+template <class T>
+void host_give(std::vector<std::vector<T>>& pool, std::vector<T>&& v) {
+  if (v.capacity() == 0) return;
+  v.clear();
+  std::lock_guard<std::mutex> lk(g_host_mu);
+  if (pool.size() < HOST_POOL) pool.push_back(std::move(v));
+}
+
 void batch_free(dagbound_batch* b) {
   if (!b) return;
   {
@@ -232,6 +265,9 @@ void batch_free(dagbound_batch* b) {
   for (hipEvent_t ev : b->ev)
     if (ev) (void)hipEventDestroy(ev);
   if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+  host_give(g_host64, std::move(b->node_off));
+  host_give(g_host64, std::move(b->edge_off));
+  host_give(g_host32, std::move(b->order_host));
   delete b;
 }
 
@@ -361,7 +397,7 @@ dagbound_status dagbound_create_batch(int32_t num_dags, const int64_t* node_off,
   hipStream_t st = (hipStream_t)hip_stream;
   const int64_t D = num_dags;
 
-  std::vector<int64_t> no(D + 1), eo(D + 1);
+  std::vector<int64_t> no = host_take(g_host64, (size_t)D + 1), eo = host_take(g_host64, (size_t)D + 1);
   if (ptr_kind == DAGBOUND_PTR_HOST) {
     memcpy(no.data(), node_off, (D + 1) * sizeof(int64_t));
     memcpy(eo.data(), edge_off, (D + 1) * sizeof(int64_t));
@@ -394,21 +430,51 @@ dagbound_status dagbound_create_batch(int32_t num_dags, const int64_t* node_off,
   b->te = te;
   b->max_n = (int32_t)max_n;
   b->max_e = (int32_t)std::min<int64_t>(max_e, INT32_MAX);
-  b->node_off = no;
-  b->edge_off = eo;
+  b->node_off = std::move(no);
+  b->edge_off = std::move(eo);
+  const int64_t* nh = b->node_off.data();
+  const int64_t* eh = b->edge_off.data();
   int32_t class_max_e[NUM_CLASSES] = {};  // most edges of a DAG of each class
   {
-    std::vector<int32_t> cnt(NUM_CLASSES + 1, 0);
+    // DAG ids grouped by size class, in id order within a class: a
+    // counting sort over a class byte per DAG (four interleaved counters,
+    // so no counter waits on its own last store), then the largest DAG of
+    // each class from its own range
+    static_assert(NUM_CLASSES == 5 && LARGE_CLASS == 4, "class bounds 64, 128, 256, 512");
+    static thread_local std::vector<uint8_t> cls;
+    cls.resize((size_t)D);
     for (int64_t d = 0; d < D; d++) {
-      const int cls = class_of((int)(no[d + 1] - no[d]));
-      cnt[cls + 1]++;
-      b->class_max_n[cls] = std::max<int32_t>(b->class_max_n[cls], (int32_t)(no[d + 1] - no[d]));
-      class_max_e[cls] = std::max<int32_t>(class_max_e[cls], (int32_t)std::min<int64_t>(eo[d + 1] - eo[d], INT32_MAX));
+      const int64_t n = nh[d + 1] - nh[d];
+      cls[(size_t)d] = (uint8_t)((n > 64) + (n > 128) + (n > 256) + (n > 512));
     }
-    for (int c = 0; c < NUM_CLASSES; c++) cnt[c + 1] += cnt[c];
-    for (int c = 0; c <= NUM_CLASSES; c++) b->class_off[c] = cnt[c];
-    b->order_host.resize((size_t)D);
-    for (int64_t d = 0; d < D; d++) b->order_host[(size_t)cnt[class_of((int)(no[d + 1] - no[d]))]++] = (int32_t)d;
+    int64_t c4[4][NUM_CLASSES] = {};
+    const int64_t D4 = D & ~(int64_t)3;
+    for (int64_t d = 0; d < D4; d += 4) {
+      c4[0][cls[(size_t)d]]++;
+      c4[1][cls[(size_t)d + 1]]++;
+      c4[2][cls[(size_t)d + 2]]++;
+      c4[3][cls[(size_t)d + 3]]++;
+    }
+    for (int64_t d = D4; d < D; d++) c4[0][cls[(size_t)d]]++;
+    int64_t pos[NUM_CLASSES];
+    b->class_off[0] = 0;
+    for (int c = 0; c < NUM_CLASSES; c++) {
+      pos[c] = b->class_off[c];
+      b->class_off[c + 1] = (int32_t)(b->class_off[c] + c4[0][c] + c4[1][c] + c4[2][c] + c4[3][c]);
+    }
+    b->order_host = host_take(g_host32, (size_t)D);
+    int32_t* ord = b->order_host.data();
+    for (int64_t d = 0; d < D; d++) ord[pos[cls[(size_t)d]]++] = (int32_t)d;
+    for (int c = 0; c < NUM_CLASSES; c++) {
+      int64_t mn = 0, me = 0;
+      for (int64_t i = b->class_off[c]; i < b->class_off[c + 1]; i++) {
+        const int32_t d = ord[i];
+        mn = std::max(mn, nh[d + 1] - nh[d]);
+        me = std::max(me, eh[d + 1] - eh[d]);
+      }
+      b->class_max_n[c] = (int32_t)mn;
+      class_max_e[c] = (int32_t)std::min<int64_t>(me, INT32_MAX);
+    }
   }
   const int32_t n_records = b->class_off[LARGE_CLASS + 1] - b->class_off[3];
   const size_t gres_words = sweep_gres_words(b->class_max_n, b->class_off, (int32_t)max_n, b->gres_off);
@@ -452,9 +518,9 @@ dagbound_status dagbound_create_batch(int32_t num_dags, const int64_t* node_off,
   // the offsets are already on the device when the caller passes device
   // pointers: copy them there instead of back from the host copies
   const hipMemcpyKind okind = ptr_kind == DAGBOUND_PTR_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
-  e = hipMemcpyAsync(d_no, ptr_kind == DAGBOUND_PTR_DEVICE ? (const void*)node_off : no.data(), (D + 1) * 8, okind, st);
+  e = hipMemcpyAsync(d_no, ptr_kind == DAGBOUND_PTR_DEVICE ? (const void*)node_off : (const void*)nh, (D + 1) * 8, okind, st);
   if (e == hipSuccess)
-    e = hipMemcpyAsync(d_eo, ptr_kind == DAGBOUND_PTR_DEVICE ? (const void*)edge_off : eo.data(), (D + 1) * 8, okind, st);
+    e = hipMemcpyAsync(d_eo, ptr_kind == DAGBOUND_PTR_DEVICE ? (const void*)edge_off : (const void*)eh, (D + 1) * 8, okind, st);
   if (e == hipSuccess && D > 0)
     e = hipMemcpyAsync(b->order, b->order_host.data(), (size_t)D * 4, hipMemcpyHostToDevice, st);
   if (e == hipSuccess && ptr_kind == DAGBOUND_PTR_HOST && (tn + te) > 0) {
