@@ -959,7 +959,7 @@ dagbound_status dagbound_baselines(dagbound_batch* b, int64_t* greedy, int64_t* 
     Carve c(tmp);
     for (int i = 0; i < 3; i++) dv[i] = out[i] ? c.take<int64_t>(n) : nullptr;
   }
-  e = launch_baselines(b->t, b->D, b->M, b->max_n, dv[0], dv[1], dv[2], st);
+  e = launch_baselines(b->t, b->D, b->M, b->max_n, b->max_e, dv[0], dv[1], dv[2], st);
   for (int i = 0; i < 3 && e == hipSuccess && ptr_kind == DAGBOUND_PTR_HOST; i++)
     if (out[i]) e = hipMemcpyAsync(out[i], dv[i], n * 8, hipMemcpyDeviceToHost, st);
   if (e == hipSuccess && (ptr_kind == DAGBOUND_PTR_HOST || !st)) e = hipStreamSynchronize(st);

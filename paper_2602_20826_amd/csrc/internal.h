@@ -70,8 +70,9 @@ hipError_t launch_prep_large(const Tables& t, const PrepInputs& in, int32_t coun
                              hipStream_t stream);
 
 // Comparison bounds of Section 6.2 (Greedy, Greedy+unaware, Graham_para)
-// per DAG into the non-null outputs ([D] each); max_n sizes the LDS.
-hipError_t launch_baselines(const Tables& t, int32_t D, int32_t M, int32_t max_n, int64_t* greedy,
+// per DAG into the non-null outputs ([D] each); the largest DAG's nodes and
+// edges size the LDS.
+hipError_t launch_baselines(const Tables& t, int32_t D, int32_t M, int32_t max_n, int32_t max_e, int64_t* greedy,
                             int64_t* unaware, int64_t* graham, hipStream_t stream);
 
 // Runs the part graph of one schedule (records of the schedule dump; edges
