@@ -408,6 +408,11 @@ dagbound_status dagbound_create_batch(int32_t num_dags, const int64_t* node_off,
     if (e != hipSuccess) return hip_fail(e, "reading node_off/edge_off");
   }
   if (no[0] != 0 || eo[0] != 0) return fail(DAGBOUND_E_ARG, "node_off[0] and edge_off[0] must be 0");
+  // checks, largest sizes, and the size class of each DAG (a byte per DAG
+  // for the grouping below) in one pass
+  static_assert(NUM_CLASSES == 5 && LARGE_CLASS == 4, "class bounds 64, 128, 256, 512");
+  static thread_local std::vector<uint8_t> cls;
+  cls.resize((size_t)D);
   int64_t max_n = 0, max_e = 0;
   for (int64_t d = 0; d < D; d++) {
     const int64_t n = no[d + 1] - no[d], e = eo[d + 1] - eo[d];
@@ -417,6 +422,7 @@ dagbound_status dagbound_create_batch(int32_t num_dags, const int64_t* node_off,
                   (long long)d, (long long)n, DAGBOUND_MAX_NODES_PER_DAG);
     max_n = std::max(max_n, n);
     max_e = std::max(max_e, e);
+    cls[(size_t)d] = (uint8_t)((n > 64) + (n > 128) + (n > 256) + (n > 512));
   }
   const int64_t tn = no[D], te = eo[D];
   if (tn > 0 && (!wcet || !max_par)) return fail(DAGBOUND_E_ARG, "wcet/max_par is NULL");
@@ -437,16 +443,9 @@ dagbound_status dagbound_create_batch(int32_t num_dags, const int64_t* node_off,
   int32_t class_max_e[NUM_CLASSES] = {};  // most edges of a DAG of each class
   {
     // DAG ids grouped by size class, in id order within a class: a
-    // counting sort over a class byte per DAG (four interleaved counters,
-    // so no counter waits on its own last store), then the largest DAG of
-    // each class from its own range
-    static_assert(NUM_CLASSES == 5 && LARGE_CLASS == 4, "class bounds 64, 128, 256, 512");
-    static thread_local std::vector<uint8_t> cls;
-    cls.resize((size_t)D);
-    for (int64_t d = 0; d < D; d++) {
-      const int64_t n = nh[d + 1] - nh[d];
-      cls[(size_t)d] = (uint8_t)((n > 64) + (n > 128) + (n > 256) + (n > 512));
-    }
+    // counting sort over the class bytes (four interleaved counters, so no
+    // counter waits on its own last store), then the largest DAG of each
+    // class from its own range
     int64_t c4[4][NUM_CLASSES] = {};
     const int64_t D4 = D & ~(int64_t)3;
     for (int64_t d = 0; d < D4; d += 4) {

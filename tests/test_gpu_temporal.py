@@ -132,3 +132,17 @@ def test_switching_reading(torch_dev):
     with pytest.raises(db.DagboundError):
         db.set_para_launch(b, 2)
     b.close()
+
+
+def test_temporal_full_size_sampled(torch_dev):
+    # the whole batched-layered workload (100,000 DAGs x 64 explicit
+    # candidates) in the temporal reading, a seeded sample of DAGs (and the
+    # first and last) on the oracle
+    wl = W.WORKLOADS[2]
+    batch = W.generate_workload(2)
+    alloc = W.alloc_bytes(batch, wl.num_cus, wl.K, seed=wl.seed)
+    say("temporal: batched-layered full size", batch.num_dags, "DAGs x", wl.K)
+    got = gpu_eval(torch_dev, batch, wl.num_cus, wl.K, alloc, terms=False, para_mode=T)
+    rng = np.random.default_rng(29)
+    sample = np.unique(np.r_[0, rng.integers(0, batch.num_dags, 1500), batch.num_dags - 1])
+    check_against_oracle(batch, wl.num_cus, wl.K, alloc, got, dags=sample, para_mode=T)
