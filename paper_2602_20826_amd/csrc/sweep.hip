@@ -463,6 +463,7 @@ __device__ bool eval_tile(const SweepArgs& a, int item, unsigned char* smem, uin
 #pragma unroll
     for (int w = 0; w < NW; w++) gm[w] = 0;
     uint64_t W = 0;
+    uint32_t W32 = 0;  // loads below 2^20: up to 512 of them sum below 2^29
     for (int base = k; base < kend; base += WAVE) {
       uint2 rec = rec0;
       if (base != k && base + lane < kend) rec = s_mem[base + lane];
@@ -473,17 +474,22 @@ __device__ bool eval_tile(const SweepArgs& a, int item, unsigned char* smem, uin
         if (bit_get_u<NW>(rel, s)) {
           uint32_t cv = (uint32_t)__builtin_amdgcn_readlane((int)rec.x, i);
           if (bit_get_u<NW>(seg, s)) cv = *res_at(s);
-          W += cv;
+          if (SMALL) W32 += cv;
+          else W += cv;
         }
       }
     }
+    if (SMALL) W = W32;
     if (!__ballot(W != 0)) { k = kend; continue; }  // every member finished earlier
     // Pass 2: parallelism of each unfinished member (Eq. 5, or the candidate
     // byte) and its execution time (Eq. 1, t_min = 1, m <= M).  The byte of
     // the next member is read one step ahead.
     const float rw2 = SMALL ? __builtin_amdgcn_rcpf((float)(2ull * W)) : 0.0f;
     uint32_t maxC = 0, sm = 0;
+    // with loads below 2^20, m C < load + m < 2^21 per member and the sums
+    // of up to 512 members stay below 2^30: 32-bit arithmetic
     uint64_t A = 0;
+    uint32_t A32 = 0;
     for (int base = k; base < kend; base += WAVE) {
       uint2 rec = rec0;
       if (base != k && base + lane < kend) rec = s_mem[base + lane];
@@ -513,7 +519,8 @@ __device__ bool eval_tile(const SweepArgs& a, int item, unsigned char* smem, uin
         const uint32_t C = ceil_div<SMALL>(cv, m);
         maxC = max(maxC, C);
         sm += m;
-        A += (uint64_t)m * C;
+        if (SMALL) A32 += __umul24(m, C);
+        else A += (uint64_t)m * C;
       }
     }
     // Eqs. 6-7: parallel nodes (released, outside the group) take the S spare
@@ -605,7 +612,7 @@ __device__ bool eval_tile(const SweepArgs& a, int item, unsigned char* smem, uin
     // Lemma 1, plus the list-scheduling term if the members oversubscribe.
     if (W != 0) {
       uint64_t R = maxC;
-      if (sm > M) R += (A - maxC) / M;
+      if (sm > M) R += SMALL ? (uint64_t)((A32 - maxC) / M) : (A - maxC) / M;
       bound += R;
       cp += maxC;
     }
