@@ -517,19 +517,18 @@ hipError_t launch_prep(const Tables& t, const PrepInputs& in, int32_t D, int32_t
     }
   }
   // DAGs above 256 nodes go to the workgroup-per-DAG kernel (large.hip), one
-  // launch per class, largest first; those of 129-256 nodes get a launch of
-  // their own, and the rest share one launch sized for 128 nodes
+  // launch per class, largest first; each smaller class gets a launch sized
+  // for its own bitset width (one-word rows for DAGs up to 64 nodes)
   hipError_t e = hipSuccess;
   for (int c = LARGE_CLASS; c >= 3 && e == hipSuccess; c--)
     e = launch_prep_large(t, in, class_off[c + 1] - class_off[c], M, order + class_off[c], err, lscratch,
                           class_max_n[c], class_max_e[c], stream);
   if (e == hipSuccess)
     e = launch_prep_nw<4>(t, in, class_off[3] - class_off[2], M, order + class_off[2], err, stream);
-  if (e == hipSuccess) {
-    const int32_t n = class_off[2] - class_off[0];
-    e = class_off[2] > class_off[1] ? launch_prep_nw<2>(t, in, n, M, order, err, stream)
-                                    : launch_prep_nw<1>(t, in, n, M, order, err, stream);
-  }
+  if (e == hipSuccess)
+    e = launch_prep_nw<2>(t, in, class_off[2] - class_off[1], M, order + class_off[1], err, stream);
+  if (e == hipSuccess)
+    e = launch_prep_nw<1>(t, in, class_off[1] - class_off[0], M, order, err, stream);
   return e;
 }
 
