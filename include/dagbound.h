@@ -62,14 +62,14 @@ enum {
   DAGBOUND_E_DEVICE = -6,     /* HIP runtime error, or no usable device */
   DAGBOUND_E_STATE = -7,      /* call out of order (e.g. eval before set_allocations) */
   DAGBOUND_E_OVERFLOW = -8,   /* a DAG's summed load reaches 2^40 */
-  DAGBOUND_E_UNSUPPORTED = -9 /* valid input this build does not handle */
+  DAGBOUND_E_UNSUPPORTED = -9 /* valid input the library does not handle */
 };
 enum { DAGBOUND_PTR_HOST = 0, DAGBOUND_PTR_DEVICE = 1 };
 enum { DAGBOUND_ALLOC_EXPLICIT = 0, DAGBOUND_ALLOC_SEEDED = 1 };
 enum { DAGBOUND_SEARCH_EXHAUSTIVE = 0, DAGBOUND_SEARCH_SURROGATE = 1 };
 enum { DAGBOUND_PARA_SPATIAL = 0, DAGBOUND_PARA_TEMPORAL = 1 };
 
-/* Limits of this build. */
+/* Limits of the library. */
 #define DAGBOUND_MAX_NODES_PER_DAG 8000  /* N_d, source and sink included */
 #define DAGBOUND_MAX_CANDIDATES (1 << 22)
 

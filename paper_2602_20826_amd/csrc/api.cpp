@@ -418,7 +418,7 @@ dagbound_status dagbound_create_batch(int32_t num_dags, const int64_t* node_off,
     const int64_t n = no[d + 1] - no[d], e = eo[d + 1] - eo[d];
     if (n < 0 || e < 0) return fail(DAGBOUND_E_ARG, "DAG %lld: offsets decrease", (long long)d);
     if (n > DAGBOUND_MAX_NODES_PER_DAG)
-      return fail(DAGBOUND_E_UNSUPPORTED, "DAG %lld has %lld nodes; this build handles at most %d",
+      return fail(DAGBOUND_E_UNSUPPORTED, "DAG %lld has %lld nodes; the library handles at most %d",
                   (long long)d, (long long)n, DAGBOUND_MAX_NODES_PER_DAG);
     max_n = std::max(max_n, n);
     max_e = std::max(max_e, e);
