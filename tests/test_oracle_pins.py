@@ -458,6 +458,9 @@ def test_temporal_hand_case():
     s = oracle.bound(*args, trace=True, para_mode=oracle.TEMPORAL)
     chain = sorted([a, b] for (_, a, ap, b, bp) in s.edges if a != 1 and b != 5)
     assert chain == case["expect"]["temporal_chain"]
+    sl = s.slots[1]
+    want = case["expect"]["temporal_slot2"]
+    assert (sl.sum_m, sl.A, sl.maxC, sl.R) == (want["sum_m"], want["A"], want["maxC"], want["R"])
 
 
 @pytest.mark.parametrize("seed", range(10))
@@ -481,6 +484,11 @@ def test_temporal_structure(seed):
                     continue
                 S = M - sum(q.m for q in members)
                 assert all(q.m <= S for q in par)
+                # each takes its target: the candidate byte, else m^max
+                for q in par:
+                    assert q.m <= p[q.node] and (r[q.node] == 0 or q.m <= r[q.node])
+                    assert q.m == S or q.m == min(int(p[q.node]), int(r[q.node]) or int(p[q.node]), q.load) \
+                        or q.kind == 2
                 assert sum(q.C for q in par) <= sl.maxC
                 assert all(q.kind == 1 for q in par[:-1])
             assert oracle.bound(n, src, dst, w, p, 1, r, para_mode=oracle.TEMPORAL) == \
