@@ -106,8 +106,9 @@ __host__ __device__ constexpr int class_of(int n) {
   return n <= 64 ? 0 : n <= 128 ? 1 : n <= 256 ? 2 : n <= 512 ? 3 : LARGE_CLASS;
 }
 // Residual-load regions of the large-DAG evaluation (one per running
-// wavefront, class_max_n words each).
-constexpr int LARGE_SLOTS = 4096;
+// wavefront, class_max_n words each); the persistent grid is the smaller of
+// this and what the occupancy allows (about 19 wavefronts per compute unit).
+constexpr int LARGE_SLOTS = 8192;
 
 struct SweepArgs {
   Tables t;
