@@ -90,9 +90,11 @@ constexpr int RES_SLOTS = 12;
 // that overflows its LDS table takes one and finishes at once; the second
 // pass (one workgroup per table) takes the tiles left when all are taken.
 constexpr int GLOBAL_PASS_GRID = 256;
-// Global row regions for eight-word bitsets: one per workgroup of the
-// persistent first pass (at most this many) and of the second pass.
-constexpr int ROW_REGIONS = 1024;
+// Global row regions for bitsets kept in global memory: one per workgroup
+// of the persistent first pass (at most this many) and of the second pass;
+// enough that the persistent grid reaches the occupancy limit (about 5
+// wavefronts per CU for eight-word rows, 10 for four-word rows).
+constexpr int ROW_REGIONS = 4096;
 enum : int32_t { EVAL_PATH_AUTO = 0, EVAL_PATH_GLOBAL = 1 };
 
 // DAGs are evaluated in size classes (up to 64, 128, 256, 512 nodes, and
