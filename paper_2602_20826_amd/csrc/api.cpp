@@ -551,9 +551,17 @@ dagbound_status dagbound_create_batch(int32_t num_dags, const int64_t* node_off,
     e = dev_alloc(&lscratch, &lscratch_size, device);
     if (e != hipSuccess) lscratch = nullptr;
   }
+  // the size classes' preprocessing launches run beside each other on the
+  // side streams (their events are the batch's, later used by the evaluation)
+  hipStream_t side[NUM_CLASSES] = {};
+  bool fork_ok = e == hipSuccess && side_streams(device, side) == hipSuccess;
+  for (int i = 0; i <= NUM_CLASSES && fork_ok; i++)
+    if (!b->ev[i]) fork_ok = hipEventCreateWithFlags(&b->ev[i], hipEventDisableTiming) == hipSuccess;
+  if (!fork_ok) (void)hipGetLastError();
   if (e == hipSuccess)
     e = launch_prep(b->t, in, num_dags, num_cus, (int32_t)max_n, b->order, b->class_off, b->err, lscratch,
-                    b->class_max_n, class_max_e, st);
+                    b->class_max_n, class_max_e, fork_ok ? side : nullptr, fork_ok ? b->ev[0] : nullptr,
+                    fork_ok ? b->ev + 1 : nullptr, st);
   unsigned long long errw[2] = {~0ull, 0};
   if (e == hipSuccess) e = hipMemcpyAsync(errw, b->err, sizeof errw, hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);

@@ -51,10 +51,13 @@ enum : uint32_t { PREP_E_CYCLE = 2, PREP_E_RANGE = 3, PREP_E_DUP = 4, PREP_E_OVE
 // 512 nodes use `lscratch` (prep_large_scratch_bytes of their largest size).
 // DAGs above 256 nodes (classes 3 and 4, one launch each) use `lscratch`,
 // which holds the larger of the two classes' prep_large_scratch_bytes.
+// With `side` (NUM_CLASSES streams, a fork event and one join event per
+// class), the launches of DAGs up to 256 nodes run on their own streams,
+// forked from and joined back to `stream`.
 hipError_t launch_prep(const Tables& t, const PrepInputs& in, int32_t D, int32_t M, int32_t max_n,
                        const int32_t* order, const int32_t* class_off, unsigned long long* err,
                        void* lscratch, const int32_t* class_max_n, const int32_t* class_max_e,
-                       hipStream_t stream);
+                       const hipStream_t* side, hipEvent_t fork, const hipEvent_t* join, hipStream_t stream);
 
 // Largest DAG the large-DAG kernels take, and the most workgroups of a
 // workgroup-per-DAG preprocessing launch (each with its own scratch region).

@@ -504,7 +504,7 @@ hipError_t launch_prep_nw(const Tables& t, const PrepInputs& in, int32_t count, 
 hipError_t launch_prep(const Tables& t, const PrepInputs& in, int32_t D, int32_t M, int32_t max_n,
                        const int32_t* order, const int32_t* class_off, unsigned long long* err,
                        void* lscratch, const int32_t* class_max_n, const int32_t* class_max_e,
-                       hipStream_t stream) {
+                       const hipStream_t* side, hipEvent_t fork, const hipEvent_t* join, hipStream_t stream) {
   if (D <= 0) return hipSuccess;
   if (max_n > LARGE_MAX_N) return hipErrorInvalidValue;
   if (!order) {  // one launch sized for the largest DAG
@@ -520,15 +520,36 @@ hipError_t launch_prep(const Tables& t, const PrepInputs& in, int32_t D, int32_t
   // launch per class, largest first; each smaller class gets a launch sized
   // for its own bitset width (one-word rows for DAGs up to 64 nodes)
   hipError_t e = hipSuccess;
+  // the small classes' launches touch only the failure words (atomics), so
+  // they may run beside each other and beside the large classes, which stay
+  // in order on `stream` (they share the work counter err[2])
+  bool forked[3] = {false, false, false};
+  if (side && fork && join) e = hipEventRecord(fork, stream);
+  for (int c = 2; c >= 0 && e == hipSuccess; c--) {
+    const int32_t n = class_off[c + 1] - class_off[c];
+    if (n <= 0) continue;
+    hipStream_t sc = stream;
+    if (side && fork && join) {
+      sc = side[c];
+      e = hipStreamWaitEvent(sc, fork, 0);
+      if (e != hipSuccess) break;
+    }
+    const int32_t* list = order + class_off[c];
+    e = c == 2 ? launch_prep_nw<4>(t, in, n, M, list, err, sc)
+               : c == 1 ? launch_prep_nw<2>(t, in, n, M, list, err, sc) : launch_prep_nw<1>(t, in, n, M, list, err, sc);
+    if (e == hipSuccess && sc != stream) {
+      e = hipEventRecord(join[c], sc);
+      forked[c] = e == hipSuccess;
+    }
+  }
   for (int c = LARGE_CLASS; c >= 3 && e == hipSuccess; c--)
     e = launch_prep_large(t, in, class_off[c + 1] - class_off[c], M, order + class_off[c], err, lscratch,
                           class_max_n[c], class_max_e[c], stream);
-  if (e == hipSuccess)
-    e = launch_prep_nw<4>(t, in, class_off[3] - class_off[2], M, order + class_off[2], err, stream);
-  if (e == hipSuccess)
-    e = launch_prep_nw<2>(t, in, class_off[2] - class_off[1], M, order + class_off[1], err, stream);
-  if (e == hipSuccess)
-    e = launch_prep_nw<1>(t, in, class_off[1] - class_off[0], M, order, err, stream);
+  for (int c = 0; c < 3; c++) {  // join every forked stream, even after an error
+    if (!forked[c]) continue;
+    const hipError_t w = hipStreamWaitEvent(stream, join[c], 0);
+    if (e == hipSuccess) e = w;
+  }
   return e;
 }
 
