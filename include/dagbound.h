@@ -25,6 +25,12 @@
  *
  * All results are exact int64, bit-identical to the plain CPU definition.
  *
+ * Beyond the bound: the comparison bounds of the evaluation (Section 6.2:
+ * Greedy, Greedy + unaware, Graham_para; dagbound_baselines), the other
+ * reading of the launching loop (WS_j as an area, launched nodes chained;
+ * dagbound_set_para_launch), and a schedule run on this GPU as a HIP graph
+ * (the case study of Section 6.1; dagbound_run_schedule).
+ *
  * Conventions shared by every call:
  *   - Status: 0 on success, a negative DAGBOUND_E_* code on failure;
  *     dagbound_last_error() then returns a message (per thread).  On failure
