@@ -232,9 +232,19 @@ __host__ __device__ inline Lds lds_layout(int maxn, int nw, bool big, bool rs) {
   size_t o = 0;
   l.mem = o;  o += (size_t)maxn * 8;            // members in group order
   l.node = o; o += (size_t)maxn * 8;            // node info by sigma rank
-  l.ppv = o;  o += ((size_t)maxn * 2 + 15) & ~(size_t)15;  // min(p, M) by local id
-  l.inv = o;  o += ((size_t)maxn * 2 + 15) & ~(size_t)15;  // sigma rank by local id
-  l.res = o;  o += big ? 0 : (size_t)RES_SLOTS * WAVE * 4;  // residual table [slot][lane]
+  const size_t idb = ((size_t)maxn * 2 + 15) & ~(size_t)15;
+  if (big) {
+    l.ppv = o;  o += idb;                       // min(p, M) by local id
+    l.inv = o;  o += idb;                       // sigma rank by local id
+    l.res = o;
+  } else {
+    // the two id tables serve the set-up only, before the residual table
+    // is first written: they share its space (12 * 64 words >= 2 * 512 ids)
+    l.res = o;  o += (size_t)RES_SLOTS * WAVE * 4;  // residual table [slot][lane]
+    l.ppv = l.res;
+    l.inv = l.res + idb;
+    static_assert(RES_SLOTS * WAVE * 4 >= 2 * 512 * 2, "id tables fit in the residual table");
+  }
   l.r = o;    o += rs ? 0 : (size_t)maxn * WAVE;  // candidate bytes [sigma][lane] (none when drawn on the fly)
   l.map = o;  o += big ? 0 : (size_t)((maxn + 7) / 8) * WAVE * 4;  // residual slot of a node, 4 bits
   if (regs) {
