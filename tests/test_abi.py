@@ -3,6 +3,8 @@ argument checks that need no device answer on any machine."""
 import ctypes
 import os
 import re
+import subprocess
+import sys
 
 import numpy as np
 import pytest
@@ -78,3 +80,23 @@ def test_null_arguments_rejected():
 def test_binding_dtype_checks():
     with pytest.raises(TypeError):
         binding._marshal([(np.zeros(2, np.int32), "int64")])
+
+
+def test_missing_library_fails_loudly():
+    # with the shared library absent the binding raises on first use; there
+    # is no other path that could compute a bound
+    code = (
+        "import numpy as np, workloads as W\n"
+        "import paper_2602_20826_amd.dagbound as d\n"
+        "d._lib = None\n"
+        "d.load_library.__defaults__ = ('/nonexistent/libdagbound.so',)\n"
+        "b = W.from_dags([(2, [0], [1], [3, 4], [1, 2])])\n"
+        "try:\n"
+        "    d.create_batch(b.node_off, b.edge_off, b.src, b.dst, b.wcet, b.par, 4)\n"
+        "except ImportError as e:\n"
+        "    print('raised', 'is not built' in str(e))\n"
+    )
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=120, cwd=root)
+    assert r.returncode == 0, r.stderr
+    assert r.stdout.strip() == "raised True"
