@@ -68,7 +68,9 @@ enum {
   DAGBOUND_E_DEVICE = -6,     /* HIP runtime error, or no usable device */
   DAGBOUND_E_STATE = -7,      /* call out of order (e.g. eval before set_allocations) */
   DAGBOUND_E_OVERFLOW = -8,   /* a DAG's summed load reaches 2^40 */
-  DAGBOUND_E_UNSUPPORTED = -9 /* valid input the library does not handle */
+  DAGBOUND_E_UNSUPPORTED = -9, /* valid input the library does not handle */
+  DAGBOUND_E_IO = -10          /* a model file cannot be opened, read or written, or is not a
+                                  model file of this version and architecture */
 };
 enum { DAGBOUND_PTR_HOST = 0, DAGBOUND_PTR_DEVICE = 1 };
 enum { DAGBOUND_ALLOC_EXPLICIT = 0, DAGBOUND_ALLOC_SEEDED = 1 };
@@ -175,6 +177,25 @@ dagbound_status dagbound_eval_bounds(dagbound_batch* batch, int64_t* bounds, int
 dagbound_status dagbound_best_allocation(dagbound_batch* batch, uint32_t search, int32_t top_k,
                                          const dagbound_model* model, int32_t* best_idx,
                                          int64_t* best_bound, uint32_t ptr_kind, void* hip_stream);
+
+/*
+ * dagbound_eval_listed -- the bounds of listed candidates of the current
+ * allocation set: for each DAG d, the L candidate ids cand[d * L + i] in
+ * [0, K) (repeats allowed), evaluated exactly as dagbound_eval_bounds
+ * evaluates them (Algorithm 2, Lemma 1 / Theorem 1).  This is the exact
+ * verification step of a proposal that picked a few candidates per DAG.
+ *   L          entries per DAG, 1 <= L <= DAGBOUND_MAX_CANDIDATES.
+ *   cand       int32 [D * L] candidate ids (same memory kind as the outputs).
+ *   bounds     int64 [D * L]: bounds[d * L + i] is the bound of candidate
+ *              cand[d * L + i] of DAG d; cp_term / intf_term as for
+ *              dagbound_eval_bounds (each may be NULL).
+ * An id outside [0, K) is E_ARG (device lists are checked on the device
+ * before anything is evaluated).  The call waits for its work.  A later
+ * exhaustive best_allocation evaluates the whole set again.
+ * Errors: E_ARG, E_STATE (no allocations set), E_OOM, E_DEVICE.
+ */
+dagbound_status dagbound_eval_listed(dagbound_batch* batch, int32_t L, const int32_t* cand, int64_t* bounds,
+                                     int64_t* cp_term, int64_t* intf_term, uint32_t ptr_kind, void* hip_stream);
 
 /*
  * dagbound_set_para_launch -- the reading of the launching loop of
@@ -350,6 +371,18 @@ void dagbound_model_destroy(dagbound_model* model);
 dagbound_status dagbound_model_params(dagbound_model* model, float* get, const float* set, float* grad,
                                       int64_t* step);
 
+/* Checkpoint of a model: dagbound_model_save writes its FP32 parameters,
+ * both Adam moments and its optimizer step count to the file `path`
+ * (versioned header with the architecture, FNV-1a checksum; written under
+ * `path`.tmp and renamed, so a failed save leaves an earlier file intact);
+ * dagbound_model_load replaces a model's parameters, moments and step by a
+ * file's (gradient cleared), so training resumes exactly where the saved
+ * model stopped.  Both wait for the model's work.
+ * Errors: E_ARG (NULL), E_IO (cannot open / read / write; not a model file;
+ * other version, architecture or size; checksum mismatch), E_DEVICE. */
+dagbound_status dagbound_model_save(const dagbound_model* model, const char* path);
+dagbound_status dagbound_model_load(dagbound_model* model, const char* path);
+
 /* Per-node head coefficients a_v (float [node_off[D]][3], the batch's node
  * numbering).  Waits for its work. */
 dagbound_status dagbound_model_forward(dagbound_model* model, dagbound_batch* batch, float* node_out,
@@ -376,6 +409,13 @@ dagbound_status dagbound_model_select(dagbound_model* model, dagbound_batch* bat
 /* Release the batch and its device memory (waits for its work).  NULL is a
  * no-op. */
 void dagbound_destroy_batch(dagbound_batch* batch);
+
+/* Releases the library's process-wide device resources: freed device
+ * blocks it keeps for reuse and its per-device side streams (after waiting
+ * for their work).  Call after every batch and model is destroyed, while the
+ * HIP runtime is still up (the Python binding calls it at interpreter exit);
+ * later calls recreate what they need. */
+void dagbound_shutdown(void);
 
 /* Message of the last failing call on this thread ("" if none). */
 const char* dagbound_last_error(void);

@@ -277,6 +277,7 @@ SweepArgs sweep_args(const dagbound_batch* b) {
   a.D = b->D;
   a.M = b->M;
   a.K = b->K;
+  a.kalloc = b->K;
   a.alloc = b->mode == DAGBOUND_ALLOC_EXPLICIT ? b->alloc : nullptr;
   a.seed = b->seed;
   a.temporal = b->para_mode;
@@ -1025,7 +1026,96 @@ dagbound_status dagbound_set_tuning(dagbound_batch* b, const char* key, int64_t 
   return DAGBOUND_OK;
 }
 
+dagbound_status dagbound_eval_listed(dagbound_batch* b, int32_t L, const int32_t* cand, int64_t* bounds,
+                                     int64_t* cp_term, int64_t* intf_term, uint32_t ptr_kind, void* hip_stream) {
+  g_err.clear();
+  if (!b) return fail(DAGBOUND_E_ARG, "batch is NULL");
+  if (ptr_kind > DAGBOUND_PTR_DEVICE) return fail(DAGBOUND_E_ARG, "bad ptr_kind %u", ptr_kind);
+  if (!b->has_alloc) return fail(DAGBOUND_E_STATE, "set_allocations has not been called");
+  if (L < 1 || L > DAGBOUND_MAX_CANDIDATES) return fail(DAGBOUND_E_ARG, "L = %d outside [1, %d]", L, DAGBOUND_MAX_CANDIDATES);
+  const size_t n = (size_t)b->D * (size_t)L;
+  if (n > 0 && (!cand || !bounds)) return fail(DAGBOUND_E_ARG, "cand/bounds is NULL");
+  if (n == 0) return DAGBOUND_OK;
+  DeviceGuard g(b->device);
+  hipStream_t st = (hipStream_t)hip_stream;
+  const bool host = ptr_kind == DAGBOUND_PTR_HOST;
+  if (host) {
+    for (size_t i = 0; i < n; i++)
+      if (cand[i] < 0 || cand[i] >= b->K)
+        return fail(DAGBOUND_E_ARG, "cand[%zu] = %d outside [0, %d)", i, cand[i], b->K);
+  }
+  void* tmp = nullptr;
+  size_t tmp_size = 5 * 256 + n * 4 + 4 + (host ? n * 8 * (1 + (cp_term != nullptr) + (intf_term != nullptr)) : 0);
+  hipError_t e = dev_alloc(&tmp, &tmp_size, b->device);
+  if (e != hipSuccess) return hip_fail(e, "allocating list scratch");
+  Carve c(tmp);
+  uint32_t* bad = c.take<uint32_t>(1);
+  SweepArgs a = sweep_args(b);
+  a.K = L;
+  a.best = b->best;
+  if (host) {
+    int32_t* dl = c.take<int32_t>(n);
+    e = hipMemcpyAsync(dl, cand, n * 4, hipMemcpyHostToDevice, st);
+    a.cand_list = dl;
+    a.bounds = c.take<int64_t>(n);
+    a.cp = cp_term ? c.take<int64_t>(n) : nullptr;
+    a.intf = intf_term ? c.take<int64_t>(n) : nullptr;
+  } else {
+    // ids out of range are an argument error: checked on the device first
+    uint32_t nbad = 0;
+    e = launch_check_list(cand, (int64_t)n, b->K, bad, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(&nbad, bad, 4, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e == hipSuccess && nbad) {
+      dev_release(tmp, tmp_size, b->device);
+      return fail(DAGBOUND_E_ARG, "%u entries of cand outside [0, %d)", nbad, b->K);
+    }
+    a.cand_list = cand;
+    a.bounds = bounds;
+    a.cp = cp_term;
+    a.intf = intf_term;
+  }
+  if (e == hipSuccess) e = run_sweep(b, a, st);
+  b->best_gen = ~0ull;  // the per-DAG minimum now holds list positions
+  if (e == hipSuccess && host) {
+    e = hipMemcpyAsync(bounds, a.bounds, n * 8, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess && cp_term) e = hipMemcpyAsync(cp_term, a.cp, n * 8, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess && intf_term) e = hipMemcpyAsync(intf_term, a.intf, n * 8, hipMemcpyDeviceToHost, st);
+  }
+  // the list scratch is released below, so the work is waited for
+  const hipError_t es = hipStreamSynchronize(st);
+  if (e == hipSuccess) e = es;
+  dev_release(tmp, tmp_size, b->device);
+  if (e != hipSuccess) return hip_fail(e, "evaluating listed candidates");
+  return DAGBOUND_OK;
+}
+
 void dagbound_destroy_batch(dagbound_batch* b) { batch_free(b); }
+
+void dagbound_shutdown(void) {
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    cache_trim_locked(0);
+  }
+  std::lock_guard<std::mutex> lk(g_stream_mu);
+  int cur = -1;
+  (void)hipGetDevice(&cur);
+  for (size_t dev = 0; dev < g_side.size(); dev++) {
+    bool any = false;
+    for (hipStream_t s : g_side[dev]) any = any || s;
+    if (!any) continue;
+    (void)hipSetDevice((int)dev);
+    for (hipStream_t& s : g_side[dev]) {
+      if (s) {
+        (void)hipStreamSynchronize(s);
+        (void)hipStreamDestroy(s);
+        s = nullptr;
+      }
+    }
+  }
+  if (cur >= 0) (void)hipSetDevice(cur);
+  g_side.clear();
+}
 
 }  // extern "C"
 
@@ -1203,6 +1293,115 @@ dagbound_status dagbound_model_params(dagbound_model* m, float* get, const float
   }
   if (e != hipSuccess) return hip_fail(e, "model parameters");
   if (step) *step = m->step;
+  return DAGBOUND_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Checkpoint file: a fixed header, then the FP32 parameters and both Adam
+// moments (DAGBOUND_MODEL_PARAMS floats each, little-endian as in memory).
+// The checksum is FNV-1a (64-bit) over the three arrays.
+constexpr char MODEL_MAGIC[8] = {'D', 'A', 'G', 'B', 'M', 'D', 'L', '\0'};
+constexpr uint32_t MODEL_FILE_VERSION = 1;
+struct ModelFileHeader {
+  char magic[8];
+  uint32_t version;
+  uint32_t header_bytes;
+  int64_t params;
+  int64_t step;
+  int32_t fin, hid, layers, out;
+  uint64_t checksum;
+};
+static_assert(sizeof(ModelFileHeader) == 56, "checkpoint header layout");
+
+uint64_t fnv1a(const void* p, size_t n, uint64_t h) {
+  const unsigned char* c = (const unsigned char*)p;
+  for (size_t i = 0; i < n; i++) {
+    h ^= c[i];
+    h *= 0x100000001B3ull;
+  }
+  return h;
+}
+
+}  // namespace
+
+extern "C" {
+
+dagbound_status dagbound_model_save(const dagbound_model* m, const char* path) {
+  g_err.clear();
+  if (!m || !path) return fail(DAGBOUND_E_ARG, "model or path is NULL");
+  DeviceGuard g(m->device);
+  std::vector<float> buf((size_t)SUR_PARAMS * 3);
+  hipError_t e = hipDeviceSynchronize();
+  if (e == hipSuccess) e = hipMemcpy(buf.data(), m->p, (size_t)SUR_PARAMS * 4, hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = hipMemcpy(buf.data() + SUR_PARAMS, m->m1, (size_t)SUR_PARAMS * 4, hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = hipMemcpy(buf.data() + 2 * SUR_PARAMS, m->m2, (size_t)SUR_PARAMS * 4, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e, "reading the model");
+  ModelFileHeader h{};
+  memcpy(h.magic, MODEL_MAGIC, 8);
+  h.version = MODEL_FILE_VERSION;
+  h.header_bytes = (uint32_t)sizeof h;
+  h.params = SUR_PARAMS;
+  h.step = m->step;
+  h.fin = SUR_FIN;
+  h.hid = SUR_HID;
+  h.layers = SUR_LAYERS;
+  h.out = SUR_OUT;
+  h.checksum = fnv1a(buf.data(), buf.size() * 4, 0xCBF29CE484222325ull);
+  // written under a temporary name and renamed, so a failed save leaves any
+  // earlier file at `path` intact
+  const std::string tmp = std::string(path) + ".tmp";
+  FILE* f = fopen(tmp.c_str(), "wb");
+  if (!f) return fail(DAGBOUND_E_IO, "cannot open %s for writing", tmp.c_str());
+  bool ok = fwrite(&h, sizeof h, 1, f) == 1 && fwrite(buf.data(), 4, buf.size(), f) == buf.size();
+  ok = (fclose(f) == 0) && ok;
+  if (!ok || rename(tmp.c_str(), path) != 0) {
+    (void)remove(tmp.c_str());
+    return fail(DAGBOUND_E_IO, "writing %s failed", path);
+  }
+  return DAGBOUND_OK;
+}
+
+dagbound_status dagbound_model_load(dagbound_model* m, const char* path) {
+  g_err.clear();
+  if (!m || !path) return fail(DAGBOUND_E_ARG, "model or path is NULL");
+  FILE* f = fopen(path, "rb");
+  if (!f) return fail(DAGBOUND_E_IO, "cannot open %s", path);
+  ModelFileHeader h{};
+  std::vector<float> buf((size_t)SUR_PARAMS * 3);
+  const bool head = fread(&h, sizeof h, 1, f) == 1;
+  bool body = false;
+  if (head && !memcmp(h.magic, MODEL_MAGIC, 8) && h.version == MODEL_FILE_VERSION &&
+      h.header_bytes == sizeof h && h.params == SUR_PARAMS && h.fin == SUR_FIN && h.hid == SUR_HID &&
+      h.layers == SUR_LAYERS && h.out == SUR_OUT && h.step >= 0) {
+    body = fread(buf.data(), 4, buf.size(), f) == buf.size();
+    char extra;
+    body = body && fread(&extra, 1, 1, f) == 0;  // nothing after the moments
+  }
+  fclose(f);
+  if (!head) return fail(DAGBOUND_E_IO, "%s: short header", path);
+  if (memcmp(h.magic, MODEL_MAGIC, 8)) return fail(DAGBOUND_E_IO, "%s is not a libdagbound model file", path);
+  if (h.version != MODEL_FILE_VERSION)
+    return fail(DAGBOUND_E_IO, "%s: file version %u, this library reads version %u", path, h.version, MODEL_FILE_VERSION);
+  if (!body) return fail(DAGBOUND_E_IO, "%s: wrong architecture or size", path);
+  if (fnv1a(buf.data(), buf.size() * 4, 0xCBF29CE484222325ull) != h.checksum)
+    return fail(DAGBOUND_E_IO, "%s: checksum mismatch", path);
+  DeviceGuard g(m->device);
+  hipError_t e = hipDeviceSynchronize();
+  if (e == hipSuccess) e = hipMemcpy(m->p, buf.data(), (size_t)SUR_PARAMS * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(m->m1, buf.data() + SUR_PARAMS, (size_t)SUR_PARAMS * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(m->m2, buf.data() + 2 * SUR_PARAMS, (size_t)SUR_PARAMS * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemset(m->g, 0, (size_t)SUR_PARAMS * 4);
+  SurArgs s{};
+  s.p = m->p;
+  s.wfwd = m->wfwd;
+  s.wbwd = m->wbwd;
+  if (e == hipSuccess) e = sur_refresh_weights(s, nullptr);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) return hip_fail(e, "loading the model");
+  m->step = h.step;
   return DAGBOUND_OK;
 }
 

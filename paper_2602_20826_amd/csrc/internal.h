@@ -117,7 +117,8 @@ constexpr int LARGE_SLOTS = 8192;
 
 struct SweepArgs {
   Tables t;
-  int32_t D, M, K;
+  int32_t D, M, K;              // K: evaluations per DAG (candidates, or list entries with cand_list)
+  int32_t kalloc;               // candidate rows per DAG in the explicit bytes (the allocation set's K)
   const int32_t* order;         // [D] DAG ids grouped by size class, or nullptr (one class: all DAGs)
   int32_t class_off[NUM_CLASSES + 1];  // host: class c holds order[class_off[c] .. class_off[c + 1])
   int32_t class_max_n[NUM_CLASSES];    // host: largest DAG of each class
@@ -189,6 +190,8 @@ hipError_t launch_sweep(const SweepArgs& a, hipStream_t stream, const SweepStrea
 // is translated to the candidate id.
 hipError_t launch_best_final(const unsigned long long* best, int32_t D, int32_t* idx, int64_t* bound,
                              const int32_t* list, int32_t K, hipStream_t stream);
+// Counts the entries of list [n] outside [0, K) into *bad (zeroed first).
+hipError_t launch_check_list(const int32_t* list, int64_t n, int32_t K, uint32_t* bad, hipStream_t stream);
 
 // Schedule dump of DAG d under candidate c (schedule.hip): records of 8
 // int64 into rec[cap][8]; out = {records the schedule has, bound, critical-

@@ -775,7 +775,7 @@ __device__ void eval_one(const SweepArgs& a, uint64_t item, unsigned char* smem,
     if (c == 0 || !a.alloc) {
       for (int s = lane; s < N; s += WAVE) rb[s] = 0;
     } else {
-      const uint8_t* row = a.alloc + (int64_t)a.K * n0 + (int64_t)c * N;
+      const uint8_t* row = a.alloc + (int64_t)a.kalloc * n0 + (int64_t)c * N;
       for (int v = lane; v < N; v += WAVE) rb[inv[v]] = row[v];
     }
   }

@@ -402,7 +402,7 @@ __device__ bool eval_tile(const SweepArgs& a, int item, unsigned char* smem, uin
     if (c > 0 && active) {
       // 16-byte aligned loads over the lane's row; an aligned chunk holding a
       // byte of the row never leaves that byte's page.
-      const uint8_t* row = a.alloc + (int64_t)a.K * n0 + (int64_t)c * N;
+      const uint8_t* row = a.alloc + (int64_t)a.kalloc * n0 + (int64_t)c * N;
       const uintptr_t rb = (uintptr_t)row;
       const uintptr_t p0 = rb & ~(uintptr_t)15;
       const uintptr_t pe = rb + (uintptr_t)N;
@@ -1004,6 +1004,25 @@ hipError_t launch_sweep(const SweepArgs& a, hipStream_t stream, const SweepStrea
     }
   }
   return e;
+}
+
+namespace {
+__global__ void k_check_list(const int32_t* list, int64_t n, int32_t K, uint32_t* bad) {
+  uint32_t cnt = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    cnt += (list[i] < 0 || list[i] >= K) ? 1u : 0u;
+  if (cnt) atomicAdd(bad, cnt);
+}
+__global__ void k_zero_word(uint32_t* w) { *w = 0u; }
+}  // namespace
+
+hipError_t launch_check_list(const int32_t* list, int64_t n, int32_t K, uint32_t* bad, hipStream_t stream) {
+  hipLaunchKernelGGL(k_zero_word, dim3(1), dim3(1), 0, stream, bad);
+  if (n > 0) {
+    const int64_t blocks = (n + 255) / 256 < 4096 ? (n + 255) / 256 : 4096;
+    hipLaunchKernelGGL(k_check_list, dim3((unsigned)blocks), dim3(256), 0, stream, list, n, K, bad);
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_best_final(const unsigned long long* best, int32_t D, int32_t* idx, int64_t* bound,

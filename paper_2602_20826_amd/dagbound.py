@@ -7,8 +7,11 @@ It fails loudly when the library is not built: there is no fallback.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
+import sys
+import weakref
 from typing import Any, Optional, Sequence, Tuple
 
 import numpy as np
@@ -16,8 +19,8 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libdagbound.so")
 
-OK, E_ARG, E_CYCLE, E_RANGE, E_DUP_EDGE, E_OOM, E_DEVICE, E_STATE, E_OVERFLOW, E_UNSUPPORTED = (
-    0, -1, -2, -3, -4, -5, -6, -7, -8, -9)
+OK, E_ARG, E_CYCLE, E_RANGE, E_DUP_EDGE, E_OOM, E_DEVICE, E_STATE, E_OVERFLOW, E_UNSUPPORTED, E_IO = (
+    0, -1, -2, -3, -4, -5, -6, -7, -8, -9, -10)
 PTR_HOST, PTR_DEVICE = 0, 1
 ALLOC_EXPLICIT, ALLOC_SEEDED = 0, 1
 SEARCH_EXHAUSTIVE, SEARCH_SURROGATE = 0, 1
@@ -29,16 +32,33 @@ MODEL_PARAMS = 100356
 # Every symbol include/dagbound.h declares.
 EXPORTS = (
     "dagbound_create_batch", "dagbound_set_allocations", "dagbound_eval_bounds",
-    "dagbound_best_allocation", "dagbound_get_division", "dagbound_get_schedule", "dagbound_baselines", "dagbound_run_schedule",
+    "dagbound_best_allocation", "dagbound_eval_listed", "dagbound_get_division", "dagbound_get_schedule", "dagbound_baselines", "dagbound_run_schedule",
     "dagbound_set_para_launch",
     "dagbound_set_tuning",
     "dagbound_destroy_batch", "dagbound_model_create", "dagbound_model_destroy",
     "dagbound_model_params", "dagbound_model_forward", "dagbound_model_train_step",
-    "dagbound_model_select",
-    "dagbound_last_error", "dagbound_version",
+    "dagbound_model_select", "dagbound_model_save", "dagbound_model_load",
+    "dagbound_shutdown", "dagbound_last_error", "dagbound_version",
 )
 
 _lib: Optional[ctypes.CDLL] = None
+# Live handles, closed in order at interpreter exit (while the HIP runtime is
+# still up), before the library releases its process-wide resources.
+_live: "weakref.WeakSet" = weakref.WeakSet()
+
+
+def _close_all() -> None:
+    if _lib is None:
+        return
+    for h in list(_live):
+        try:
+            h.close()
+        except Exception:
+            pass
+    _lib.dagbound_shutdown()
+
+
+atexit.register(_close_all)
 
 
 class DagboundError(RuntimeError):
@@ -63,6 +83,14 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.dagbound_set_allocations.argtypes = [P, I32, U32, P, U64, U32]
     lib.dagbound_eval_bounds.restype = I32
     lib.dagbound_eval_bounds.argtypes = [P, P, P, P, U32, P]
+    lib.dagbound_eval_listed.restype = I32
+    lib.dagbound_eval_listed.argtypes = [P, I32, P, P, P, P, U32, P]
+    lib.dagbound_model_save.restype = I32
+    lib.dagbound_model_save.argtypes = [P, ctypes.c_char_p]
+    lib.dagbound_model_load.restype = I32
+    lib.dagbound_model_load.argtypes = [P, ctypes.c_char_p]
+    lib.dagbound_shutdown.restype = None
+    lib.dagbound_shutdown.argtypes = []
     lib.dagbound_best_allocation.restype = I32
     lib.dagbound_best_allocation.argtypes = [P, U32, I32, P, P, P, U32, P]
     lib.dagbound_get_division.restype = I32
@@ -154,12 +182,24 @@ def _marshal(arrays: Sequence[Tuple[Any, str]]):
     return ptrs, (kinds.pop() if kinds else PTR_HOST), keep
 
 
-def _stream_ptr(stream) -> Optional[int]:
+def _stream_ptr(stream, arrays: Sequence[Any] = ()) -> Optional[int]:
+    """The hipStream_t of `stream` (a torch stream or a raw handle).  With
+    None and a device tensor among `arrays`, torch's current stream of that
+    tensor's device, so the call is ordered after the work that produced it
+    (for torch's default stream that is the NULL stream: the call then
+    waits for its work)."""
     if stream is None:
-        return None
+        for a in arrays:
+            if a is not None and _is_torch(a) and a.is_cuda:
+                import torch
+
+                stream = torch.cuda.current_stream(a.device)
+                break
+        else:
+            return None
     if isinstance(stream, int):
         return stream
-    return int(stream.cuda_stream)
+    return int(stream.cuda_stream) or None
 
 
 class Batch:
@@ -170,6 +210,7 @@ class Batch:
         self.num_dags = num_dags
         self.node_off = node_off_host
         self.K = 0
+        _live.add(self)
 
     def close(self) -> None:
         if self.handle:
@@ -183,6 +224,9 @@ class Batch:
         self.close()
 
     def __del__(self):
+        # at interpreter exit the atexit hook has closed every live handle
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:
@@ -199,7 +243,7 @@ def create_batch(node_off, edge_off, edge_src, edge_dst, wcet, max_par, num_cus:
     num_dags = int(len(node_off)) - 1
     out = ctypes.c_void_p()
     _check(lib.dagbound_create_batch(num_dags, p_no, p_eo, p_s, p_t, p_w, p_p, int(num_cus), kind,
-                                     _stream_ptr(stream), ctypes.byref(out)))
+                                     _stream_ptr(stream, keep), ctypes.byref(out)))
     if _is_torch(node_off):
         no = node_off.detach().cpu().numpy()
     else:
@@ -222,7 +266,20 @@ def eval_bounds(batch: Batch, bounds, cp_term=None, intf_term=None, stream=None)
     lib = load_library()
     (p_b, p_c, p_i), kind, keep = _marshal([(bounds, "int64"), (cp_term, "int64"), (intf_term, "int64")])
     _check(lib.dagbound_eval_bounds(ctypes.c_void_p(batch.handle), p_b, p_c, p_i, kind,
-                                    _stream_ptr(stream)))
+                                    _stream_ptr(stream, keep)))
+
+
+def eval_listed(batch: Batch, cand, bounds, cp_term=None, intf_term=None, stream=None) -> None:
+    """dagbound_eval_listed: bounds[d*L + i] of candidate cand[d*L + i] of DAG
+    d (int32 ids, L per DAG), written in place; waits for its work."""
+    lib = load_library()
+    (p_l, p_b, p_c, p_i), kind, keep = _marshal([(cand, "int32"), (bounds, "int64"), (cp_term, "int64"),
+                                                 (intf_term, "int64")])
+    n = int(np.prod(np.shape(cand))) if not _is_torch(cand) else cand.numel()
+    if batch.num_dags == 0 or n % batch.num_dags:
+        raise ValueError("cand must hold L entries per DAG")
+    _check(lib.dagbound_eval_listed(ctypes.c_void_p(batch.handle), n // batch.num_dags, p_l, p_b, p_c, p_i,
+                                    kind, _stream_ptr(stream, keep)))
 
 
 def baselines(batch: Batch, greedy=None, greedy_unaware=None, graham_para=None, stream=None):
@@ -234,7 +291,7 @@ def baselines(batch: Batch, greedy=None, greedy_unaware=None, graham_para=None, 
         greedy, greedy_unaware, graham_para = (np.zeros(batch.num_dags, np.int64) for _ in range(3))
     (p_g, p_u, p_h), kind, keep = _marshal([(greedy, "int64"), (greedy_unaware, "int64"),
                                             (graham_para, "int64")])
-    _check(lib.dagbound_baselines(ctypes.c_void_p(batch.handle), p_g, p_u, p_h, kind, _stream_ptr(stream)))
+    _check(lib.dagbound_baselines(ctypes.c_void_p(batch.handle), p_g, p_u, p_h, kind, _stream_ptr(stream, keep)))
     return greedy, greedy_unaware, graham_para
 
 
@@ -261,7 +318,7 @@ def best_allocation(batch: Batch, best_idx, best_bound, search: int = SEARCH_EXH
     (p_i, p_b), kind, keep = _marshal([(best_idx, "int32"), (best_bound, "int64")])
     mh = ctypes.c_void_p(model.handle) if model is not None else None
     _check(lib.dagbound_best_allocation(ctypes.c_void_p(batch.handle), int(search), int(top_k),
-                                        mh, p_i, p_b, kind, _stream_ptr(stream)))
+                                        mh, p_i, p_b, kind, _stream_ptr(stream, keep)))
 
 
 class Model:
@@ -271,6 +328,7 @@ class Model:
         out = ctypes.c_void_p()
         _check(load_library().dagbound_model_create(ctypes.c_uint64(seed & (2**64 - 1)), ctypes.byref(out)))
         self.handle = out.value
+        _live.add(self)
 
     def close(self) -> None:
         if self.handle:
@@ -278,10 +336,20 @@ class Model:
             self.handle = 0
 
     def __del__(self):
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:
             pass
+
+    def save(self, path: str) -> None:
+        """dagbound_model_save: parameters, Adam moments and step to `path`."""
+        _check(load_library().dagbound_model_save(ctypes.c_void_p(self.handle), os.fsencode(path)))
+
+    def load(self, path: str) -> None:
+        """dagbound_model_load: parameters, Adam moments and step from `path`."""
+        _check(load_library().dagbound_model_load(ctypes.c_void_p(self.handle), os.fsencode(path)))
 
     def params(self) -> np.ndarray:
         out = np.empty(MODEL_PARAMS, np.float32)
@@ -312,7 +380,7 @@ def model_forward(model: Model, batch: Batch, node_out, stream=None) -> None:
     """dagbound_model_forward: per-node head coefficients [T_N][3]."""
     (p_o,), kind, keep = _marshal([(node_out, "float32")])
     _check(load_library().dagbound_model_forward(ctypes.c_void_p(model.handle), ctypes.c_void_p(batch.handle),
-                                                 p_o, kind, _stream_ptr(stream)))
+                                                 p_o, kind, _stream_ptr(stream, keep)))
 
 
 def model_train_step(model: Model, batch: Batch, K: int, seed: int, bounds, lr: float, stream=None) -> float:
@@ -322,7 +390,7 @@ def model_train_step(model: Model, batch: Batch, K: int, seed: int, bounds, lr: 
     _check(load_library().dagbound_model_train_step(ctypes.c_void_p(model.handle), ctypes.c_void_p(batch.handle),
                                                     int(K), ctypes.c_uint64(seed & (2**64 - 1)), p_b,
                                                     ctypes.c_float(lr), ctypes.byref(loss), kind,
-                                                    _stream_ptr(stream)))
+                                                    _stream_ptr(stream, keep)))
     return float(loss.value)
 
 
@@ -332,7 +400,7 @@ def model_select(model: Model, batch: Batch, K: int, seed: int, top_k: int, node
     (p_c, p_s), kind, keep = _marshal([(cand, "int32"), (scores, "float32")])
     _check(load_library().dagbound_model_select(ctypes.c_void_p(model.handle), ctypes.c_void_p(batch.handle),
                                                 int(K), ctypes.c_uint64(seed & (2**64 - 1)), int(top_k),
-                                                int(nodes), p_c, p_s, kind, _stream_ptr(stream)))
+                                                int(nodes), p_c, p_s, kind, _stream_ptr(stream, keep)))
 
 
 def get_division(batch: Batch, d: int):
@@ -370,3 +438,9 @@ def set_tuning(batch: Batch, key: str, value: int) -> None:
 
 def destroy_batch(batch: Batch) -> None:
     batch.close()
+
+
+def shutdown() -> None:
+    """dagbound_shutdown after closing every live batch and model (also run
+    at interpreter exit)."""
+    _close_all()

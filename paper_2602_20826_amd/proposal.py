@@ -69,8 +69,31 @@ def train(model: db.Model, shards: Sequence[Shard], epochs: int, lr: float = 2e-
     return hist
 
 
-def compare_search(torch, model: db.Model, dags, M: int, K: int, seed: int, top_k: int) -> Dict:
-    """Best bounds and DAGs/s of the four searches on a held-out set."""
+def surrogate_lists(torch, model: db.Model, b: db.Batch, K: int, seed: int, top_k: int):
+    """The candidate lists a surrogate search of batch `b` evaluates (candidate
+    0, then the model's top_k, as dagbound_best_allocation picks them) and
+    their exact bounds from dagbound_eval_listed: two host arrays [D, top_k+1]."""
+    dev = torch.device("cuda:0")
+    D = b.num_dags
+    cand = torch.empty(D * (top_k + 1), dtype=torch.int32, device=dev)
+    db.model_select(model, b, K, seed, top_k, 32, cand)
+    out = torch.empty(D * (top_k + 1), dtype=torch.int64, device=dev)
+    db.eval_listed(b, cand, out)
+    return cand.view(D, top_k + 1).cpu().numpy(), out.view(D, top_k + 1).cpu().numpy()
+
+
+def gap_stats(x: np.ndarray, ref: np.ndarray) -> Dict:
+    """Relative gap of best bounds x to the reference ref, per DAG."""
+    g = x / ref - 1.0
+    return {"mean": float(g.mean()), "p99": float(np.quantile(g, 0.99)), "max": float(g.max()),
+            "exact_frac": float(np.mean(g == 0)), "within_1pct_frac": float(np.mean(g <= 0.01))}
+
+
+def compare_search(torch, model: db.Model, dags, M: int, K: int, seed: int, top_k: int,
+                   keep_lists: bool = False) -> Dict:
+    """Best bounds and DAGs/s of the four searches on a held-out set.  With
+    keep_lists, the result also holds the surrogate's candidate lists and
+    their exact bounds ("lists", "list_bounds", host arrays [D, top_k+1])."""
     dev = torch.device("cuda:0")
     D = dags.num_dags
     b = _dev_batch(torch, dev, dags, M)
@@ -95,6 +118,7 @@ def compare_search(torch, model: db.Model, dags, M: int, K: int, seed: int, top_
                        stream=stream)  # warm
     t_sur = timed(lambda: db.best_allocation(b, idx, best_sur, search=db.SEARCH_SURROGATE, top_k=top_k,
                                              model=model, stream=stream))
+    lists = surrogate_lists(torch, model, b, K, seed, top_k) if keep_lists else None
     # the encoder's forward pass alone (its layer GEMMs run on MFMA)
     fwd = torch.empty(int(dags.node_off[-1]) * 3, dtype=torch.float32, device=dev)
     t_fwd = timed(lambda: db.model_forward(model, b, fwd, stream=stream))
@@ -112,11 +136,9 @@ def compare_search(torch, model: db.Model, dags, M: int, K: int, seed: int, top_
     b.close()
 
     def gap(x):
-        g = x / exh - 1.0
-        return {"mean": float(g.mean()), "p99": float(np.quantile(g, 0.99)), "max": float(g.max()),
-                "exact_frac": float(np.mean(g == 0))}
+        return gap_stats(x, exh)
 
-    return {
+    res = {
         "dags": D, "K": K, "top_k": top_k,
         "exhaustive_dags_per_s": D / t_exh, "surrogate_dags_per_s": D / t_sur,
         "speedup": t_exh / t_sur,
@@ -126,11 +148,16 @@ def compare_search(torch, model: db.Model, dags, M: int, K: int, seed: int, top_
         "gain_over_paper_rule_mean": float(np.mean(1.0 - sur / c0)),
         "gain_over_random_mean": float(np.mean(1.0 - sur / rnd)),
         "dags_improved_over_paper_rule": int(np.sum(sur < c0)),
+        "dags_improved_over_random": int(np.sum(sur < rnd)),
     }
+    if lists is not None:
+        res["lists"], res["list_bounds"] = lists
+        res["surrogate_best"] = sur
+    return res
 
 
 def compare_budget(torch, model: db.Model, dags, M: int, K: int, seed: int, top_k: int, per_shard: int,
-                   exh_dags: int) -> Dict:
+                   exh_dags: int, keep_lists: int = 0) -> Dict:
     """Surrogate-guided search against plain search at the same time budget,
     on DAGs taken per_shard at a time:
       - surrogate: candidate 0 plus the top_k of K seeded candidates ranked by
@@ -141,7 +168,9 @@ def compare_budget(torch, model: db.Model, dags, M: int, K: int, seed: int, top_
         evaluation of the same shard), timed;
       - exhaustive over all K candidates on the first exh_dags DAGs of each
         shard, as the reference of the gaps (and timed, for its DAGs/s).
-    Returns mean gaps and times."""
+    Returns mean gaps and times.  With keep_lists = n, the result also holds
+    the surrogate's candidate lists and their exact bounds for the first n
+    DAGs of the first shard ("lists", "list_bounds", "list_best")."""
     dev = torch.device("cuda:0")
     st = torch.cuda.current_stream(dev)
 
@@ -153,6 +182,7 @@ def compare_budget(torch, model: db.Model, dags, M: int, K: int, seed: int, top_
         return time.perf_counter() - t0
 
     sur_all, plain_all, c0_all, exh_all, sur_s, plain_s, exh_s = [], [], [], [], [], [], []
+    kept = None
     kps = []
     for s0 in range(0, dags.num_dags, per_shard):
         sub = dags.subset(range(s0, min(dags.num_dags, s0 + per_shard)))
@@ -165,6 +195,9 @@ def compare_budget(torch, model: db.Model, dags, M: int, K: int, seed: int, top_
         t_sur = timed(lambda: db.best_allocation(b, idx, best, search=db.SEARCH_SURROGATE, top_k=top_k,
                                                  model=model, stream=st))
         sur = best.cpu().numpy().astype(np.float64)
+        if keep_lists and s0 == 0:
+            cl, bl = surrogate_lists(torch, model, b, K, seed, top_k)
+            kept = (cl[:keep_lists], bl[:keep_lists], best.cpu().numpy()[:keep_lists])
         # rate of exact search on this shard, then the plain budget
         db.set_allocations(b, 64, db.ALLOC_SEEDED, None, seed)
         out64 = torch.empty(D * 64, dtype=torch.int64, device=dev)
@@ -199,12 +232,10 @@ def compare_budget(torch, model: db.Model, dags, M: int, K: int, seed: int, top_
     first = np.concatenate([np.arange(len(x)) < len(e) for x, e in zip(sur_all, exh_all)])
 
     def gap(x, ref):
-        g = x / ref - 1.0
-        return {"mean": float(g.mean()), "p99": float(np.quantile(g, 0.99)), "max": float(g.max()),
-                "exact_frac": float(np.mean(g == 0))}
+        return gap_stats(x, ref)
 
     D = len(sur)
-    return {
+    res = {
         "dags": D, "K": K, "top_k": top_k,
         "surrogate_seconds": float(sum(sur_s)), "plain_seconds": float(sum(plain_s)),
         "surrogate_dags_per_s": D / sum(sur_s), "plain_dags_per_s": D / sum(plain_s),
@@ -220,4 +251,8 @@ def compare_budget(torch, model: db.Model, dags, M: int, K: int, seed: int, top_
         "gap_plain": gap(plain[first], exh),
         "gap_paper_rule": gap(c0[first], exh),
         "gain_over_paper_rule_mean": float(np.mean(1.0 - sur / c0)),
+        "paper_rule_is_best_frac": float(np.mean(c0[first] == exh)),
     }
+    if keep_lists:
+        res["lists"], res["list_bounds"], res["list_best"] = kept
+    return res

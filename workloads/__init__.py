@@ -21,6 +21,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libwl.so")
+GPU_LIB_PATH = os.path.join(_HERE, "libwlgpu.so")
 BASE_SEED = 0x2602208260000000
 
 
@@ -159,8 +160,9 @@ class DagBatch:
 _lib: Optional[ctypes.CDLL] = None
 
 
-def build(force: bool = False) -> str:
-    """Compile gen.c into libwl.so (gcc, OpenMP)."""
+def build(force: bool = False, gpu: bool = True) -> str:
+    """Compile gen.c into libwl.so (gcc, OpenMP) and, with `gpu`, the
+    device-side byte generator gen_gpu.hip into libwlgpu.so (hipcc, gfx950)."""
     import subprocess
 
     src = os.path.join(_HERE, "gen.c")
@@ -169,6 +171,16 @@ def build(force: bool = False) -> str:
         subprocess.check_call(["gcc", "-O2", "-std=c99", "-fopenmp", "-fPIC", "-shared",
                                "-o", tmp, src, "-lm"])
         os.replace(tmp, LIB_PATH)
+    gsrc = os.path.join(_HERE, "gen_gpu.hip")
+    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    if gpu and os.path.exists(hipcc) and (force or not os.path.exists(GPU_LIB_PATH)
+                                          or os.path.getmtime(GPU_LIB_PATH) < os.path.getmtime(gsrc)):
+        tmp = GPU_LIB_PATH + ".tmp"
+        arch = os.environ.get("DAGBOUND_OFFLOAD_ARCH", "gfx950")
+        subprocess.check_call([hipcc, "-O3", "-std=c++17", "-fPIC", "-shared", f"--offload-arch={arch}",
+                               "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+                               "-o", tmp, gsrc])
+        os.replace(tmp, GPU_LIB_PATH)
     return LIB_PATH
 
 
@@ -193,6 +205,10 @@ def _load() -> ctypes.CDLL:
         lib.wl_alloc_bytes.argtypes = [ctypes.c_uint64, ctypes.c_int64, ctypes.c_int64,
                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
                                        ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32]
+        lib.wl_alloc_bytes_list.restype = None
+        lib.wl_alloc_bytes_list.argtypes = [ctypes.c_uint64, ctypes.c_int64, ctypes.c_int64,
+                                            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                            ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32]
         _lib = lib
     return _lib
 
@@ -237,6 +253,53 @@ def alloc_bytes(batch: DagBatch, num_cus: int, K: int, seed: int, first: int = 0
     out = np.empty(int(batch.node_off[-1]) * K, np.uint8)
     lib.wl_alloc_bytes(ctypes.c_uint64(seed & (2**64 - 1)), first, batch.num_dags,
                        _ptr(batch.node_off), _ptr(batch.par), num_cus, K, _ptr(out), _threads())
+    return out
+
+
+_gpu_lib: Optional[ctypes.CDLL] = None
+
+
+def alloc_bytes_device(node_off_dev, par_dev, count: int, max_n: int, num_cus: int, K: int, seed: int,
+                       out_dev, stream=None, first: int = 0) -> None:
+    """The bytes of `alloc_bytes` written by a GPU kernel straight into the
+    device tensor `out_dev` (uint8, K * N), from device tensors `node_off_dev`
+    (int64, count + 1) and `par_dev` (int32, N), on `stream` (a torch stream
+    or None for the current one).  Same values as `alloc_bytes` for DAGs
+    first .. first + count - 1."""
+    global _gpu_lib
+    if _gpu_lib is None:
+        if not os.path.exists(GPU_LIB_PATH):
+            raise ImportError(f"{GPU_LIB_PATH} is not built (workloads.build())")
+        lib = ctypes.CDLL(GPU_LIB_PATH)
+        lib.wl_alloc_bytes_device.restype = ctypes.c_int
+        lib.wl_alloc_bytes_device.argtypes = [ctypes.c_uint64, ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p,
+                                              ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                              ctypes.c_void_p, ctypes.c_void_p]
+        _gpu_lib = lib
+    import torch
+
+    assert out_dev.dtype == torch.uint8 and node_off_dev.dtype == torch.int64 and par_dev.dtype == torch.int32
+    total = int(node_off_dev[-1].item() - node_off_dev[0].item())
+    assert out_dev.numel() >= total * K and par_dev.numel() >= total
+    st = stream if stream is not None else torch.cuda.current_stream(out_dev.device)
+    rc = _gpu_lib.wl_alloc_bytes_device(ctypes.c_uint64(seed & (2**64 - 1)), first, count,
+                                        node_off_dev.data_ptr(), par_dev.data_ptr(), num_cus, K, max_n,
+                                        out_dev.data_ptr(), ctypes.c_void_p(st.cuda_stream))
+    if rc != 0:
+        raise RuntimeError(f"wl_alloc_bytes_device failed: hipError {rc}")
+
+
+def alloc_bytes_list(batch: DagBatch, num_cus: int, cand: np.ndarray, seed: int, first: int = 0) -> np.ndarray:
+    """Bytes of listed candidates: `cand` [D, L] candidate ids per DAG; row i
+    of DAG d holds the bytes `alloc_bytes` gives candidate cand[d, i] (all
+    zero for candidate 0), at L*node_off[d] + i*N_d + v."""
+    lib = _load()
+    cand = np.ascontiguousarray(np.asarray(cand, np.int32))
+    assert cand.ndim == 2 and cand.shape[0] == batch.num_dags
+    L = cand.shape[1]
+    out = np.empty(int(batch.node_off[-1]) * L, np.uint8)
+    lib.wl_alloc_bytes_list(ctypes.c_uint64(seed & (2**64 - 1)), first, batch.num_dags, _ptr(batch.node_off),
+                            _ptr(batch.par), num_cus, L, _ptr(cand), _ptr(out), _threads())
     return out
 
 

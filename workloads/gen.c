@@ -315,3 +315,25 @@ void wl_alloc_bytes(uint64_t seed, int64_t d0, int64_t count, const int64_t* nod
       }
   }
 }
+
+/* The bytes of listed candidates: row i of DAG d holds the bytes of
+ * candidate list[d * L + i] (same draw as wl_alloc_bytes), at
+ * L * node_off[d] + i * N_d + v (node_off relative to DAG d0). */
+void wl_alloc_bytes_list(uint64_t seed, int64_t d0, int64_t count, const int64_t* node_off,
+                         const int32_t* par, int32_t M, int32_t L, const int32_t* list, uint8_t* out,
+                         int32_t nthreads) {
+#pragma omp parallel for schedule(dynamic, 64) num_threads(nthreads > 0 ? nthreads : 1)
+  for (int64_t i = 0; i < count; i++) {
+    int64_t n0 = node_off[i], nd = node_off[i + 1] - n0;
+    uint8_t* o = out + (int64_t)L * n0;
+    for (int32_t j = 0; j < L; j++) {
+      int64_t c = list[i * L + j];
+      for (int64_t v = 0; v < nd; v++) {
+        int64_t p = par[n0 + v];
+        uint32_t range = (uint32_t)(p < M ? p : M);
+        if (range > 255u) range = 255u;
+        o[(int64_t)j * nd + v] = c == 0 ? 0 : (uint8_t)cand_r(seed, (uint64_t)(d0 + i), (uint64_t)c, (uint64_t)v, range);
+      }
+    }
+  }
+}
