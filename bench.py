@@ -565,7 +565,7 @@ def baselines_block(torch, db, batch, inputs, M, stream, reps: int = 5) -> dict:
             "algorithmic_bytes_per_launch": nb, "achieved_gbs": nb / f / 1e6}
 
 
-# Setups of the evaluation's three sweeps (Section 6.2), 1,000 DAGs each,
+# Setups of the evaluation's three sweeps (Section 5.2), 1,000 DAGs each,
 # average load 20: compute units, maximum layer width and layer count.
 PAPER_SWEEPS = {
     "M": [dict(M=m, P=8, depth=(5, 8)) for m in (4, 8, 16, 32, 64, 128, 256)],

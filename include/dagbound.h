@@ -25,11 +25,11 @@
  *
  * All results are exact int64, bit-identical to the plain CPU definition.
  *
- * Beyond the bound: the comparison bounds of the evaluation (Section 6.2:
+ * Beyond the bound: the comparison bounds of the evaluation (Section 5.2:
  * Greedy, Greedy + unaware, Graham_para; dagbound_baselines), the other
  * reading of the launching loop (WS_j as an area, launched nodes chained;
  * dagbound_set_para_launch), and a schedule run on this GPU as a HIP graph
- * (the case study of Section 6.1; dagbound_run_schedule).
+ * (the case study of Section 5.3; dagbound_run_schedule).
  *
  * Conventions shared by every call:
  *   - Status: 0 on success, a negative DAGBOUND_E_* code on failure;
@@ -218,7 +218,7 @@ dagbound_status dagbound_set_para_launch(dagbound_batch* batch, uint32_t mode);
 /*
  * dagbound_run_schedule -- runs the schedule of DAG d under candidate c on
  * this GPU as a HIP graph, the counterpart of the paper's case study
- * (Section 6.1: one busy kernel, m_i set through the launch shape, the DAG
+ * (Sections 5.1 and 5.3: one busy kernel, m_i set through the launch shape, the DAG
  * as a graph) in the execution model of Section 2.2: every launched part
  * (member, parallel node, segment) is m workgroups, each holding one compute
  * unit alone for C ticks of tick_ns nanoseconds on the GPU's constant-rate
@@ -242,7 +242,7 @@ dagbound_status dagbound_run_schedule(dagbound_batch* batch, int32_t d, int32_t 
                                       int32_t barriers, int32_t reps, int64_t* makespan_ns, int64_t* terms);
 
 /*
- * dagbound_baselines -- the comparison bounds of Section 6.2 for every DAG of
+ * dagbound_baselines -- the comparison bounds of Section 5.2 for every DAG of
  * the batch, independent of any allocation set.  With t_min = 1 a node's
  * most useful parallelism is m^max = min(p_v, C_hat_v) (Section 2.2).
  *   greedy          int64 [D] or NULL: Greedy, nodes run one after another

@@ -244,7 +244,7 @@ def bounds_batch(batch, M: int, K: int, alloc: np.ndarray, dags: Optional[Sequen
 
 
 def baselines(n, src, dst, wcet, par, M) -> Tuple[int, int, int]:
-    """The comparison bounds of Section 6.2 for one DAG: (Greedy,
+    """The comparison bounds of Section 5.2 for one DAG: (Greedy,
     Greedy + unaware, Graham_para)."""
     lib = _load()
     s, sp = _arr(src, np.int32)

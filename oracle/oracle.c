@@ -19,7 +19,7 @@
  *   node segmentation, extra dependencies .... Section 4.1, Algorithm 2
  *   group response and makespan bound ........ Section 4.2, Lemma 1, Theorem 1
  *   comparison bounds (Greedy, Greedy +
- *   unaware, Graham_para) .................... Section 6.2
+ *   unaware, Graham_para) .................... Section 5.2
  * with these readings of passages that are informal or inconsistent
  * (each one is listed with its reason in the design notes):
  *   - Theta is sorted by ASCENDING W^anc, ties by smaller id (the worked
@@ -601,7 +601,7 @@ int oracle_bounds_dag(int n, int e, const int32_t* src, const int32_t* dst, cons
 }
 
 /* ------------------------------------------------------------------ */
-/* Comparison bounds of the evaluation (Section 6.2).                  */
+/* Comparison bounds of the evaluation (Section 5.2).                  */
 /*                                                                     */
 /* With t_min = 1 the maximum useful parallelism of v is               */
 /* m^max = min(p_v, C_hat_v) (Section 2.2, with the input cap p_v).     */

@@ -17,6 +17,9 @@ r_v >= 1 and range_v = min(p_v, M, 255):
   s(r) = (1/n) sum_v a_v . phi(t_v)
 Training target for candidate c >= 1: ln(bound_c) - ln(bound_0); loss =
 mean squared error over the (DAG, candidate) pairs of a step.
+Inference head (ranking thousands of candidates per DAG): the same score
+summed over at most T nodes only (`head_select`: range > 1, largest
+|a0| + |a1| + range*|a2| first, ties to the smaller id), still divided by n.
 
 Parameters are one flat float32 vector in this order: W0 [8x128], b0 [128],
 then for l = 1..3: Ws_l [128x128], Wm_l [128x128], b_l [128]; then
@@ -141,6 +144,32 @@ def scores(A: np.ndarray, rbytes: np.ndarray, rng_v: np.ndarray) -> np.ndarray:
     """rbytes [C, n] (>= 1), rng_v [n] -> scores [C]."""
     t = np.asarray(rbytes, np.float64) / np.asarray(rng_v, np.float64)[None, :]
     return (phi(t) * A[None, :, :3]).sum((1, 2)) / A.shape[0]
+
+
+def head_select(A: np.ndarray, rng_v: np.ndarray, T: int) -> List[int]:
+    """Nodes whose candidate bytes the per-candidate head reads: among the
+    nodes of range > 1 (a node of range 1 has t = 1 in every candidate, so it
+    adds the same amount to every score), the T of largest importance
+    |a0| + |a1| + range * |a2|, largest first, ties to the smaller id."""
+    A = np.asarray(A, np.float64)
+    rng_v = np.asarray(rng_v, np.float64)
+    imp = np.abs(A[:, 0]) + np.abs(A[:, 1]) + rng_v * np.abs(A[:, 2])
+    eligible = [v for v in range(A.shape[0]) if rng_v[v] > 1]
+    eligible.sort(key=lambda v: (-imp[v], v))
+    return eligible[:T]
+
+
+def head_scores(A: np.ndarray, rbytes: np.ndarray, rng_v: np.ndarray, sel: List[int]) -> np.ndarray:
+    """Score of each candidate row of rbytes [C, n] over the selected nodes
+    only, still divided by the DAG's node count n:
+      s(r) = (1/n) sum over v in sel of a_v . phi(r_v / range_v)."""
+    A = np.asarray(A, np.float64)
+    n = A.shape[0]
+    sel = list(sel)
+    if not sel:
+        return np.zeros(np.asarray(rbytes).shape[0])
+    t = np.asarray(rbytes, np.float64)[:, sel] / np.asarray(rng_v, np.float64)[None, sel]
+    return (phi(t) * A[None, sel, :3]).sum((1, 2)) / n
 
 
 def loss_and_grad(p, X, nb, rbytes, rng_v, y, scale):

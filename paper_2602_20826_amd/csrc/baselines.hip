@@ -1,4 +1,4 @@
-// Comparison bounds of the evaluation (Section 6.2), per DAG, from the
+// Comparison bounds of the evaluation (Section 5.2), per DAG, from the
 // batch's tables.  With t_min = 1 the most useful parallelism of a node is
 // m^max = min(p, C_hat) (the table mx).
 //   Greedy:          sum of Eq. 1 times at m = min(m^max, M).

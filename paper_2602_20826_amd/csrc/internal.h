@@ -72,7 +72,7 @@ hipError_t launch_prep_large(const Tables& t, const PrepInputs& in, int32_t coun
                              unsigned long long* err, void* scratch, int32_t max_n, int32_t max_e,
                              hipStream_t stream);
 
-// Comparison bounds of Section 6.2 (Greedy, Greedy+unaware, Graham_para)
+// Comparison bounds of Section 5.2 (Greedy, Greedy+unaware, Graham_para)
 // per DAG into the non-null outputs ([D] each); the largest DAG's nodes and
 // edges size the LDS.
 hipError_t launch_baselines(const Tables& t, int32_t D, int32_t M, int32_t max_n, int32_t max_e, int64_t* greedy,

@@ -1,5 +1,5 @@
 // Realization of one schedule on this GPU as a HIP graph, the counterpart
-// of the paper's case study (Section 6.1: one busy kernel with per-node
+// of the paper's case study (Sections 5.1 and 5.3: one busy kernel with per-node
 // iteration counts, m_i set through the launch shape, the DAG run as a CUDA
 // graph).  Each launched part of the schedule becomes one kernel node of m
 // workgroups; a workgroup reserves more than half of a compute unit's LDS,

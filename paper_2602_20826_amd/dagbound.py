@@ -283,7 +283,7 @@ def eval_listed(batch: Batch, cand, bounds, cp_term=None, intf_term=None, stream
 
 
 def baselines(batch: Batch, greedy=None, greedy_unaware=None, graham_para=None, stream=None):
-    """dagbound_baselines: the comparison bounds of Section 6.2 per DAG,
+    """dagbound_baselines: the comparison bounds of Section 5.2 per DAG,
     written in place into the given [D] int64 arrays; with none given, host
     arrays are allocated and returned as (greedy, greedy_unaware, graham_para)."""
     lib = load_library()

@@ -1,6 +1,6 @@
-"""GPU comparison bounds of Section 6.2 (dagbound_baselines: Greedy,
+"""GPU comparison bounds of Section 5.2 (dagbound_baselines: Greedy,
 Greedy + unaware, Graham_para) against the oracle, bit-exact, on the paper's
-worked example, the evaluation-style setups of Section 6.1, every benchmark
+worked example, the evaluation-style setups of Section 5.1, every benchmark
 workload shape (small, batched-layered, persistent-mixed, large DAGs) and
 edge cases.  Expected values come from `oracle` only."""
 import json

@@ -373,7 +373,56 @@ def _check_safe(n, src, dst, w, p, M, r, early_seeds=3, para_mode=oracle.SPATIAL
     for k in range(early_seeds):
         # early completion never exceeds the bound (sustainability)
         assert oracle.random_makespan(m, C, preds, M, seed=k, early=True) <= s.bound
+        if all(sl.sum_m <= M for sl in s.slots):
+            # one random dispatch at full durations of a predictable schedule
+            # ends exactly at the bound
+            assert oracle.random_makespan(m, C, preds, M, seed=k, early=False) == s.bound
     return worst
+
+
+# Pins of the random dispatcher itself (values derived by hand in the block
+# model: part x is m[x] blocks of C[x] ticks, one SM each, started only after
+# every predecessor part has finished all its blocks).
+
+def test_random_dispatch_chain_waits_for_predecessors():
+    # a chain 3 -> 5 -> 2 ticks runs one part after another on any number of
+    # SMs: 10 ticks for every seed (started together they would end at 5)
+    for seed in range(10):
+        assert oracle.random_makespan([1, 1, 1], [3, 5, 2], [[], [0], [1]], 4, seed, early=False) == 10
+
+
+def test_random_dispatch_runs_blocks_in_waves():
+    # five blocks of 3 ticks on 2 SMs: waves of 2, 2 and 1 blocks, 9 ticks
+    for seed in range(10):
+        assert oracle.random_makespan([5], [3], [[]], 2, seed, early=False) == 9
+
+
+def test_random_dispatch_diamond():
+    # a (1 block, 2 ticks) -> b (2 blocks, 3 ticks) and c (1 block, 4 ticks)
+    # -> d (1 block, 1 tick).  On 3 SMs b and c start together at 2, c ends
+    # at 6, d at 7.  On 2 SMs two of the three blocks start at 2: both of b
+    # (c runs 5-9, d ends at 10) or one of b with c (b's second block runs
+    # 5-8, d ends at 9); the worst order gives 10.
+    m, C, preds = [1, 2, 1, 1], [2, 3, 4, 1], [[], [0], [0], [1, 2]]
+    for seed in range(10):
+        assert oracle.random_makespan(m, C, preds, 3, seed, early=False) == 7
+    seen = {oracle.random_makespan(m, C, preds, 2, seed, early=False) for seed in range(60)}
+    assert seen == {9, 10}
+    assert oracle.worst_makespan(m, C, preds, 2) == 10
+    assert oracle.worst_makespan(m, C, preds, 3) == 7
+
+
+def test_random_early_completion_on_a_chain():
+    # with early completion each block runs uniformly 1..C ticks: a chain of
+    # four parts of 4 ticks ends between 4 and 16, after 10 ticks on average
+    # (four parts of mean 2.5); started together it would end by 4.
+    m, C, preds = [1, 1, 1, 1], [4, 4, 4, 4], [[], [0], [1], [2]]
+    runs = [oracle.random_makespan(m, C, preds, 4, seed, early=True) for seed in range(400)]
+    assert min(runs) >= 4 and max(runs) <= 16
+    assert 9.5 <= float(np.mean(runs)) <= 10.5
+    assert len(set(runs)) > 5
+    # a single block of 1 tick cannot end early
+    assert oracle.random_makespan([1], [1], [[]], 1, 0, early=True) == 1
 
 
 def _worst_by_enumeration(m, C, preds, M):
@@ -504,10 +553,10 @@ def test_bound_tight_on_oversubscribed_group():
     assert worst == case["expect"]["bound"]
 
 
-# ---------------------------------------------------------------- comparison bounds (Section 6.2)
+# ---------------------------------------------------------------- comparison bounds (Section 5.2)
 
 def test_baselines_worked_example():
-    # Derived by hand from Section 6.2's definitions (the paper prints no
+    # Derived by hand from Section 5.2's definitions (the paper prints no
     # value for them on this DAG).  Paper mode p = C_hat and M = 6: every
     # m^max = C_hat <= 6, so Greedy and Greedy + unaware run each node at
     # m = C_hat with C = 1, and the sequential sum over 7 nodes is 7.

@@ -109,3 +109,85 @@ def test_messages_do_not_depend_on_edge_direction():
     # and a node's output does depend on its neighbours
     c = S.forward(params, X, S.neighbours(n, src[:-1], dst[:-1])).A
     assert not np.allclose(a[6], c[6])
+
+
+def sparse_params():
+    """All-zero parameters except a few entries, so that the encoder's output
+    on a small graph can be worked out by hand."""
+    p = {name: np.zeros(shp) for name, shp in S.param_shapes()}
+    p["W0"][0, 0] = 1.0    # unit 0 <- feature 0
+    p["W0"][0, 1] = -1.0   # unit 1 <- -feature 0 (cut to zero by the ReLU)
+    p["Ws1"][0, 0] = 1.0   # layer 1: unit 0 keeps itself ...
+    p["Wm1"][0, 0] = 1.0   # ... plus its neighbours' mean
+    p["Ws1"][0, 1] = 2.0   # unit 1 <- 2 x unit 0 (input index first)
+    p["Ws2"][0, 0] = 1.0
+    p["Wm2"][0, 0] = 1.0
+    p["Ws2"][1, 1] = 1.0
+    p["b2"][1] = -3.0
+    p["Ws3"][0, 0] = 1.0
+    p["Wm3"][0, 0] = 1.0
+    p["Wm3"][1, 1] = 1.0   # unit 1 <- its neighbours' mean of unit 1 only
+    p["Wa"][0, 0] = 1.0
+    p["Wa"][1, 2] = 1.0
+    p["ba"][1] = 0.25
+    p["ba"][3] = 7.0
+    return p
+
+
+def test_forward_by_hand_on_a_path():
+    # Path 0 - 1 - 2 (edges 0->1, 1->2; N(1) = {0, 2}), feature 0 = (1, 2, 4).
+    #   H0: unit 0 = (1, 2, 4), unit 1 = relu(-x) = 0
+    #   layer 1: unit 0 = x + mean of neighbours = (1+2, 2+(1+4)/2, 4+2)
+    #            = (3, 4.5, 6); unit 1 = 2 x H0 unit 0 = (2, 4, 8)
+    #   layer 2: unit 0 = (3+4.5, 4.5+(3+6)/2, 6+4.5) = (7.5, 9, 10.5);
+    #            unit 1 = relu((2, 4, 8) - 3) = (0, 1, 5)
+    #   layer 3: unit 0 = (7.5+9, 9+(7.5+10.5)/2, 10.5+9) = (16.5, 18, 19.5);
+    #            unit 1 = neighbours' mean of (0, 1, 5) = (1, (0+5)/2, 1)
+    #   A = (unit 0, 0.25, unit 1, 7)
+    # A sum over the neighbours instead of the mean gives 7 for node 1 in
+    # layer 1 already.
+    X = np.zeros((3, S.F_IN))
+    X[:, 0] = (1.0, 2.0, 4.0)
+    X[:, 3] = (5.0, -2.0, 0.5)  # features without a weight change nothing
+    nb = S.neighbours(3, np.array([0, 1]), np.array([1, 2]))
+    A = S.forward(sparse_params(), X, nb).A
+    want = np.array([[16.5, 0.25, 1.0, 7.0], [18.0, 0.25, 2.5, 7.0], [19.5, 0.25, 1.0, 7.0]])
+    assert np.array_equal(A, want), A
+
+
+def test_score_by_hand():
+    # With the A above, ranges 4 and bytes (2, 4, 1): t = (1/2, 1, 1/4),
+    #   node 0: 16.5/2 + 0.25/4 + 1*2   = 10.3125
+    #   node 1: 18     + 0.25   + 2.5   = 20.75
+    #   node 2: 19.5/4 + 0.25/16 + 1*4  = 8.890625
+    # sum 39.953125 over n = 3 nodes.
+    A = np.array([[16.5, 0.25, 1.0, 7.0], [18.0, 0.25, 2.5, 7.0], [19.5, 0.25, 1.0, 7.0]])
+    s = S.scores(A, np.array([[2.0, 4.0, 1.0]]), np.array([4, 4, 4]))
+    assert s[0] == 39.953125 / 3
+
+
+def test_head_selection_and_score_by_hand():
+    # importance |a0| + |a1| + range * |a2|, nodes of range 1 never chosen:
+    #   v0: 1 + 0 + 4 * 0.5 = 3;  v1: 2 + 1 + 2 * 0 = 3 (ties v0: v0 first)
+    #   v2: range 1 (excluded);   v3: 0.5 + 0.5 + 8 * 0.5 = 5;  v4: 0 + 1 + 0 = 1
+    A = np.array([[1.0, 0.0, 0.5, 0.0],
+                  [-2.0, 1.0, 0.0, 0.0],
+                  [0.0, 0.0, 1.0, 0.0],
+                  [0.5, 0.5, 0.5, 0.0],
+                  [0.0, -1.0, 0.0, 0.0]])
+    rng_v = np.array([4, 2, 1, 8, 3])
+    assert S.head_select(A, rng_v, 1) == [3]
+    assert S.head_select(A, rng_v, 3) == [3, 0, 1]
+    assert S.head_select(A, rng_v, 10) == [3, 0, 1, 4]
+    r = np.array([[2.0, 1.0, 1.0, 4.0, 3.0],    # t = (1/2, 1/2, 1, 1/2, 1)
+                  [4.0, 2.0, 1.0, 8.0, 1.0]])   # t = (1, 1, 1, 1, 1/3)
+    # candidate 0 over {3, 0, 1}: v3 0.25 + 0.125 + 1 = 1.375, v0 0.5 + 1 = 1.5,
+    # v1 -1 + 0.25 = -0.75: 2.125 / 5.  Candidate 1: v3 1.5, v0 1.5, v1 -1: 2 / 5.
+    assert np.allclose(S.head_scores(A, r, rng_v, [3, 0, 1]), [2.125 / 5, 2.0 / 5], rtol=0, atol=1e-15)
+    # one node: v3 only; all four: v4 adds -t^2 (-1 and -1/9)
+    assert np.allclose(S.head_scores(A, r, rng_v, [3]), [1.375 / 5, 1.5 / 5], rtol=0, atol=1e-15)
+    assert np.allclose(S.head_scores(A, r, rng_v, [3, 0, 1, 4]), [1.125 / 5, (2.0 - 1.0 / 9) / 5],
+                       rtol=0, atol=1e-15)
+    # with every node chosen the head score is the full score
+    full = S.head_scores(A, r, rng_v, [0, 1, 2, 3, 4])
+    assert np.allclose(full, S.scores(A, r, rng_v), rtol=1e-15, atol=0)

@@ -1,4 +1,4 @@
-"""The evaluation-style input generator (Section 6.1's setups) produces the
+"""The evaluation-style input generator (Section 5.1's setups) produces the
 shapes its docstring states: one source as the first layer, later layers of
 2..P nodes, the layer count in range, a single sink, loads of the stated mean
 with p = C_hat, acyclic and seeded (the same DAGs on every call)."""

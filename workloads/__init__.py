@@ -316,13 +316,13 @@ def from_dags(dags) -> DagBatch:
                     cat([d[3] for d in dags], np.int64), cat([d[4] for d in dags], np.int32))
 
 
-# Seed of the evaluation-style workloads (Section 6.1's setups).
+# Seed of the evaluation-style workloads (Section 5.1's setups).
 PAPER_STYLE_SEED = BASE_SEED + 6
 
 
 def paper_style(count: int, P: int, c_avg: int, depth=(5, 8), p_adj: float = 0.3,
                 seed: int = PAPER_STYLE_SEED) -> DagBatch:
-    """DAGs shaped like the evaluation's synthetic setups (Section 6.1): the
+    """DAGs shaped like the evaluation's synthetic setups (Section 5.1): the
     number of layers is drawn in depth[0]..depth[1], the first layer is one
     source node and every later layer has U{2..P} nodes; each node of a layer
     takes one predecessor drawn from the layer before and every other pair of
