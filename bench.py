@@ -574,10 +574,13 @@ PAPER_SWEEPS = {
 }
 
 
-def paper_sweep(count: int = 1000, c_avg: int = 20) -> int:
+def paper_sweep(count: int = 1000, c_avg: int = 20, tick_scale: int = 1) -> int:
     """The evaluation's sweeps on evaluation-style DAGs: per setup, the
     paper's bound (candidate 0), Greedy and Graham_para, each normalised by
-    Greedy + unaware per DAG and averaged, all computed by the library."""
+    Greedy + unaware per DAG and averaged, all computed by the library.
+    tick_scale F > 1 multiplies every load by F and keeps the parallelism
+    cap at the original load: time is counted in 1/F of the load unit, which
+    approaches Eq. 1 with real-valued times (t_min = 1/F)."""
     import torch
 
     import paper_2602_20826_amd as db
@@ -591,6 +594,9 @@ def paper_sweep(count: int = 1000, c_avg: int = 20) -> int:
     for sweep, setups in PAPER_SWEEPS.items():
         for cfg in setups:
             batch = W.paper_style(count, cfg["P"], c_avg, depth=cfg["depth"])
+            if tick_scale > 1:
+                batch = W.DagBatch(batch.node_off, batch.edge_off, batch.src, batch.dst,
+                                   batch.wcet * tick_scale, batch.par)
             D = batch.num_dags
             b = db.create_batch(t(batch.node_off), t(batch.edge_off), t(batch.src), t(batch.dst),
                                 t(batch.wcet), t(batch.par), cfg["M"], stream=st)
@@ -605,7 +611,7 @@ def paper_sweep(count: int = 1000, c_avg: int = 20) -> int:
             torch.cuda.synchronize()
             b.close()
             prop, g, u, h, tprop = (x.cpu().numpy().astype(np.float64) for x in (prop, g, u, h, tprop))
-            row = {"sweep": sweep, "M": cfg["M"], "P": cfg["P"], "layers": list(cfg["depth"]),
+            row = {"sweep": sweep, "M": cfg["M"], "P": cfg["P"], "layers": list(cfg["depth"]), "tick_scale": tick_scale,
                    "mean_nodes": float(np.diff(batch.node_off).mean()),
                    "proposed": float(np.mean(prop / u)), "greedy": float(np.mean(g / u)),
                    "graham_para": float(np.mean(h / u)),
@@ -701,6 +707,9 @@ def main() -> int:
                     help="time the surrogate encoder's forward pass over DAGS learned-proposal DAGs")
     ap.add_argument("--paper-sweep", action="store_true",
                     help="the evaluation's sweeps over M, P and |V| (bound and comparison bounds), one JSON line each")
+    ap.add_argument("--tick-scale", type=int, default=1, metavar="F",
+                    help="--paper-sweep with every load multiplied by F and the parallelism cap kept at the "
+                         "original load (time in 1/F load units)")
     ap.add_argument("--realize", action="store_true",
                     help="schedules run as HIP graphs of busy kernels: measured makespan against the bound")
     ap.add_argument("--traffic-probe", action="store_true",
@@ -716,7 +725,7 @@ def main() -> int:
     if args.surrogate_probe:
         return surrogate_probe(args.surrogate_probe)
     if args.paper_sweep:
-        return paper_sweep()
+        return paper_sweep(tick_scale=args.tick_scale)
     if args.realize:
         return realize()
     if args.gpus != 1:

@@ -389,14 +389,21 @@ __device__ bool eval_tile(const SweepArgs& a, int item, unsigned char* smem, uin
   uint32_t freem = (1u << a.res_slots) - 1u;  // free residual slots
   // ---- candidate bytes of this lane, by sigma rank.  Candidate 0 is the
   // paper's own rule (all zero); lanes past K run zeros and store nothing.
-  // With RS the seeded bytes are drawn where they are used (r_of).
+  // With RS the bytes stay out of LDS: seeded bytes are drawn where they are
+  // used (r_of), explicit ones (XB) are read from the lane's row in device
+  // memory one use ahead (the row's bytes stay in the caches: each lane's
+  // row is N bytes).
   const bool rlive = c > 0 && active;
+  const bool XB = RS && a.alloc != nullptr;
   const uint64_t rkey = a.alloc ? 0ull : mix64(a.seed ^ mix64((uint64_t)d * 0x9E3779B97F4A7C15ull));
   auto r_of = [&](uint32_t v, uint32_t pp) -> uint32_t {
     const uint64_t word = mix64(rkey ^ (((uint64_t)c << 32) | (uint64_t)(v >> 2)));
     const uint32_t h16 = (uint32_t)(word >> (16 * (v & 3))) & 0xFFFFu;
     return rlive ? 1u + ((h16 * min(pp, 255u)) >> 16) : 0u;
   };
+  // the lane's explicit row (lanes of candidate 0 or past K read row 0 and
+  // use zero)
+  const uint8_t* xrow = XB ? a.alloc + (int64_t)a.kalloc * n0 + (int64_t)(rlive ? c : 0) * N : nullptr;
   if (RS) {
   } else if (a.alloc) {
     if (c > 0 && active) {
@@ -507,13 +514,17 @@ __device__ bool eval_tile(const SweepArgs& a, int item, unsigned char* smem, uin
       uint32_t rnext = 0, recv = 0;
       if (RS) {  // local ids of the chunk's members
         if (base + lane < kend) recv = s_node[(rec.y >> 16) & 0x7FFF].y >> 16;
+        if (XB) rnext = xrow[(uint32_t)__builtin_amdgcn_readlane((int)recv, 0)];
       } else {
         rnext = s_r[(((uint32_t)__builtin_amdgcn_readlane((int)rec.y, 0) >> 16) & 0x7FFF) * WAVE + lane];
       }
       for (int i = 0; i < cnt; i++) {
         const int s = ((uint32_t)__builtin_amdgcn_readlane((int)rec.y, i) >> 16) & 0x7FFF;
         uint32_t rv = rnext;
-        if (RS) {
+        if (XB) {
+          rv = rlive ? rnext : 0u;
+          if (i + 1 < cnt) rnext = xrow[(uint32_t)__builtin_amdgcn_readlane((int)recv, i + 1)];
+        } else if (RS) {
           rv = r_of((uint32_t)__builtin_amdgcn_readlane((int)recv, i),
                     (uint32_t)__builtin_amdgcn_readlane((int)rec.y, i) & 0xFFFFu);
         } else if (i + 1 < cnt) {
@@ -551,7 +562,7 @@ __device__ bool eval_tile(const SweepArgs& a, int item, unsigned char* smem, uin
     int cn = S ? (CURSOR ? pq.pop(Q) : pop_first<NW>(Q)) : -1;
     int ci = max(cn, 0);
     uint2 nd = s_node[ci];
-    uint32_t rc = RS ? 0u : s_r[ci * WAVE + lane];
+    uint32_t rc = RS ? (XB ? (uint32_t)xrow[nd.y >> 16] : 0u) : s_r[ci * WAVE + lane];
     uint32_t mw = BIG ? 0u : s_map[(ci >> 3) * WAVE + lane];
     bool go = cn >= 0;
     // temporal reading: S stays for every node, the launched nodes run one
@@ -560,7 +571,7 @@ __device__ bool eval_tile(const SweepArgs& a, int item, unsigned char* smem, uin
     while (go) {
       const int cur = cn;
       const uint2 ndc = nd;
-      const uint32_t rcc = RS ? r_of(ndc.y >> 16, ndc.y & 0xFFFFu) : rc, mwc = mw;
+      const uint32_t rcc = XB ? (rlive ? rc : 0u) : RS ? r_of(ndc.y >> 16, ndc.y & 0xFFFFu) : rc, mwc = mw;
       // remaining load of cur: read before the next node's data, so that
       // waiting for it leaves those reads in flight
       bool sg;
@@ -578,6 +589,7 @@ __device__ bool eval_tile(const SweepArgs& a, int item, unsigned char* smem, uin
       ci = max(cn, 0);
       nd = s_node[ci];
       if (!RS) rc = s_r[ci * WAVE + lane];
+      else if (XB) rc = xrow[nd.y >> 16];
       if (!BIG) mw = s_map[(ci >> 3) * WAVE + lane];
       const uint32_t mx = min(ndc.y & 0xFFFFu, cc);
       const uint32_t mc = min(rcc ? min(rcc, mx) : mx, S);
@@ -892,18 +904,16 @@ hipError_t launch_nw(const SweepArgs& a, uint32_t* counters, uint32_t* list, hip
   return hipGetLastError();
 }
 
-// Seeded candidates of DAGs above 128 nodes are drawn where they are used
-// (no LDS for the bytes); smaller DAGs keep them in LDS.
+// The candidate bytes of DAGs above 128 nodes stay out of LDS (seeded ones
+// drawn where they are used, explicit ones read from device memory), which
+// keeps several wavefronts per compute unit; smaller DAGs keep them in LDS.
 template <bool SMALL, bool TP>
 hipError_t launch_class_tp(int cls, const SweepArgs& a, uint32_t* counters, uint32_t* list, hipStream_t stream) {
-  const bool rs = a.alloc == nullptr;
   switch (cls) {
     case 0: return launch_nw<1, SMALL, false, TP>(a, counters, list, stream);
     case 1: return launch_nw<2, SMALL, false, TP>(a, counters, list, stream);
-    case 2: return rs ? launch_nw<4, SMALL, true, TP>(a, counters, list, stream)
-                      : launch_nw<4, SMALL, false, TP>(a, counters, list, stream);
-    default: return rs ? launch_nw<8, SMALL, true, TP>(a, counters, list, stream)
-                       : launch_nw<8, SMALL, false, TP>(a, counters, list, stream);
+    case 2: return launch_nw<4, SMALL, true, TP>(a, counters, list, stream);
+    default: return launch_nw<8, SMALL, true, TP>(a, counters, list, stream);
   }
 }
 
@@ -921,7 +931,7 @@ size_t sweep_lds_need(int max_n, int max_e) {
   (void)max_e;
   if (class_of(max_n) == LARGE_CLASS) return eval_large_lds_bytes(max_n);
   const int nw = 1 << class_of(max_n);
-  return lds_layout(max_n, nw, false, false).total;
+  return lds_layout(max_n, nw, false, nw >= 4).total;
 }
 
 size_t sweep_rows_words(const int32_t class_max_n[NUM_CLASSES], const int32_t class_off[NUM_CLASSES + 1],

@@ -159,7 +159,7 @@ def test_head_scores_match_reference(env):
         A_ref = S.forward(p32, X, nb).A
         rng_v = np.minimum(np.minimum(p, M), 255)
         sel = S.head_select(A_ref, rng_v, 32)
-        assert sel == [v for v in range(n) if rng_v[v] > 1]
+        assert sorted(sel) == [v for v in range(n) if rng_v[v] > 1]
         n0 = int(small.node_off[d])
         rb = alloc[K * n0: K * n0 + K * n].reshape(K, n)[1:].astype(np.float64)
         ref = S.head_scores(A_ref, rb, rng_v, sel)
@@ -241,7 +241,7 @@ def test_gradient_matches_reference(env):
     cos = gr @ gg / (np.linalg.norm(gr) * np.linalg.norm(gg))
     rel = np.linalg.norm(gg - gr) / np.linalg.norm(gr)
     say(f"gradient cosine {cos:.6f} relative error {rel:.4f}")
-    assert cos >= 0.999 and rel <= 0.05
+    assert cos >= 0.999 and rel <= 1e-2
     o = 0
     for name, shp in S.param_shapes():
         k = int(np.prod(shp))
@@ -358,3 +358,33 @@ def test_surrogate_search_full_size_sampled(env):
         assert cand[d, 0] == 0 and len(set(cand[d, 1:].tolist())) == top_k
         pos = int(np.argmin(want[i]))
         assert bb[d] == want[i, pos] and bi[d] == cand[d, pos], d
+
+
+def test_trained_model_beats_random_candidates(env):
+    # The gain test: a model trained on labelled learned-proposal DAGs
+    # (training is bitwise deterministic, seeds fixed), searched on other
+    # held-out DAGs (4,096 seeded candidates each, candidate 0 plus the top 16
+    # evaluated exactly), must come closer to exhaustive search than the
+    # paper's rule alone and than 16 plain random candidates.
+    torch, db = env
+    from paper_2602_20826_amd import proposal as P
+
+    wl = W.WORKLOADS[4]
+    M = wl.num_cus
+    train = W.generate_workload(4, count=4000, first=2_000_000)
+    test = W.generate_workload(4, count=4000, first=3_000_000)
+    say("gain test: labelling", train.num_dags, "x 256, training")
+    shards = P.label_shards(torch, train, M, 256, seed=11, per_shard=2000)
+    model = db.Model(3)
+    hist = P.train(model, shards, 30, lr=2e-3, lr_end=2e-4)
+    for sh in shards:
+        sh.batch.close()
+    assert hist[-1] < hist[0]
+    res = P.compare_search(torch, model, test, M, 4096, seed=5, top_k=16)
+    model.close()
+    gs, gp, gr = res["gap_surrogate"]["mean"], res["gap_paper_rule"]["mean"], res["gap_random"]["mean"]
+    say(f"gain test: mean gap surrogate {gs:.5f}, paper rule {gp:.5f}, random 16 {gr:.5f}, "
+        f"improved over the paper's rule on {res['dags_improved_over_paper_rule']} DAGs")
+    assert gs <= 0.8 * gr and gs <= 0.8 * gp, (gs, gr, gp)
+    assert res["dags_improved_over_paper_rule"] > 0.01 * test.num_dags
+    assert res["gap_surrogate"]["within_1pct_frac"] >= res["gap_random"]["within_1pct_frac"]
