@@ -406,6 +406,28 @@ dagbound_status dagbound_model_select(dagbound_model* model, dagbound_batch* bat
                                       int32_t top_k, int32_t nodes, int32_t* cand, float* scores,
                                       uint32_t ptr_kind, void* hip_stream);
 
+/*
+ * dagbound_best_allocation_static -- the surrogate search of
+ * dagbound_best_allocation (SURROGATE) without any device allocation, for
+ * callers that cannot allocate (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc).  Same results as that call.
+ *   The candidate lists (D x (top_k + 1) int32 entries) live in a static
+ *   device array of DAGBOUND_STATIC_LIST_ENTRIES entries (16 MiB) that each
+ *   GPU holds until the process ends; every call on a GPU shares it, so
+ *   calls that overlap on one GPU race.  The model's activation workspace
+ *   must already be sized for the batch by an earlier allocating call
+ *   (dagbound_best_allocation with SURROGATE, dagbound_model_select or
+ *   dagbound_model_forward on this batch or a larger one).
+ *   best_idx int32 [D], best_bound int64 [D]: device pointers.  The size
+ *   classes run one after another on hip_stream (NULL: the call waits).
+ * Errors: E_ARG (NULL, top_k outside [1, min(255, K-1)], explicit candidates,
+ * D x (top_k + 1) above DAGBOUND_STATIC_LIST_ENTRIES), E_STATE (no
+ * allocations set, workspace too small, autotune pending), E_DEVICE.
+ */
+#define DAGBOUND_STATIC_LIST_ENTRIES (4 << 20)
+dagbound_status dagbound_best_allocation_static(dagbound_batch* batch, const dagbound_model* model, int32_t top_k,
+                                                int32_t* best_idx, int64_t* best_bound, void* hip_stream);
+
 /* Release the batch and its device memory (waits for its work).  NULL is a
  * no-op. */
 void dagbound_destroy_batch(dagbound_batch* batch);

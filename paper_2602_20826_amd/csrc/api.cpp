@@ -1164,12 +1164,20 @@ void model_init_params(uint64_t seed, std::vector<float>& h) {
 
 // Activation workspace of a batch; returns the argument block.  Inference
 // (train = false) leaves out the gradient buffers (about half the bytes).
-dagbound_status model_workspace(dagbound_model* m, const dagbound_batch* b, SurArgs* s, bool train) {
+// With may_alloc = false a workspace too small for the batch is E_STATE
+// instead of being replaced.
+dagbound_status model_workspace(dagbound_model* m, const dagbound_batch* b, SurArgs* s, bool train,
+                                bool may_alloc = true) {
   const int64_t R = b->tn, D = b->D;
   const int64_t nchunk = train ? (R + SUR_CHUNK - 1) / SUR_CHUNK : 0;
   const size_t node = train ? sur_node_bytes() : sur_node_bytes() - sur_node_grad_bytes();
   const size_t need = 32 * 256 + (size_t)R * node + (size_t)(R + D) * 4 + (size_t)b->te * 4 +
                       (size_t)nchunk * (256 * 128 + 128) * 4 + (size_t)D * 4;
+  if (m->ws_size < need && !may_alloc)
+    return fail(DAGBOUND_E_STATE,
+                "the model's workspace (%zu bytes) is too small for this batch (%zu bytes); a call that may "
+                "allocate (dagbound_best_allocation, dagbound_model_select or dagbound_model_forward) sizes it",
+                m->ws_size, need);
   if (m->ws_size < need) {
     dev_release(m->ws, m->ws_size, m->device);
     m->ws = nullptr;
@@ -1506,6 +1514,84 @@ dagbound_status dagbound_model_select(dagbound_model* m, dagbound_batch* b, int3
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Allocation-free surrogate search (dagbound_best_allocation_static).  The
+// candidate lists live in one file-scope device array; every device the
+// library runs on holds its own copy, at its own address, until the process
+// ends.  In host code `scratch` names a host-side stand-in, never the device
+// memory: its device address is taken once per device with
+// hipGetSymbolAddress (that device current) and kept in g_scratch_dev.
+namespace {
+
+static __device__ __align__(256) int32_t scratch[DAGBOUND_STATIC_LIST_ENTRIES];
+
+std::mutex g_scratch_mu;
+std::vector<int32_t*> g_scratch_dev;  // per device, nullptr until looked up
+
+// Device address of `scratch` on `device` (which must be current).
+hipError_t scratch_on(int device, int32_t** out) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if ((int)g_scratch_dev.size() <= device) g_scratch_dev.resize((size_t)device + 1, nullptr);
+  if (!g_scratch_dev[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch_dev[device] = (int32_t*)p;
+  }
+  *out = g_scratch_dev[device];
+  return hipSuccess;
+}
+
+}  // namespace
+
+extern "C" dagbound_status dagbound_best_allocation_static(dagbound_batch* b, const dagbound_model* model,
+                                                           int32_t top_k, int32_t* best_idx, int64_t* best_bound,
+                                                           void* hip_stream) {
+  g_err.clear();
+  if (!b || !model) return fail(DAGBOUND_E_ARG, "batch or model is NULL");
+  dagbound_model* m = const_cast<dagbound_model*>(model);
+  if (!b->has_alloc) return fail(DAGBOUND_E_STATE, "set_allocations has not been called");
+  if (b->mode != DAGBOUND_ALLOC_SEEDED) return fail(DAGBOUND_E_ARG, "surrogate search needs seeded candidates");
+  if (top_k < 1 || top_k > 255 || top_k >= b->K)
+    return fail(DAGBOUND_E_ARG, "top_k = %d outside [1, min(255, K-1)]", top_k);
+  if (m->device != b->device) return fail(DAGBOUND_E_ARG, "model and batch live on different devices");
+  const int32_t kk = top_k + 1;
+  const size_t entries = (size_t)b->D * (size_t)kk;
+  if (entries > (size_t)DAGBOUND_STATIC_LIST_ENTRIES)
+    return fail(DAGBOUND_E_ARG, "D x (top_k + 1) = %zu list entries exceed the static scratch (%d entries)", entries,
+                DAGBOUND_STATIC_LIST_ENTRIES);
+  if (b->D == 0) return DAGBOUND_OK;
+  if (!best_idx || !best_bound) return fail(DAGBOUND_E_ARG, "best_idx/best_bound is NULL");
+  if (b->autotune_pending)
+    return fail(DAGBOUND_E_STATE, "an autotune is pending; it runs in a call that may allocate");
+  DeviceGuard g(b->device);
+  hipStream_t st = (hipStream_t)hip_stream;
+  SurArgs s;
+  dagbound_status rc = model_workspace(m, b, &s, false, false);
+  if (rc != DAGBOUND_OK) return rc;
+  int32_t* cand = nullptr;
+  hipError_t e = scratch_on(b->device, &cand);
+  if (e != hipSuccess) return hip_fail(e, "device address of the static scratch");
+  e = sur_features(s, st);
+  if (e == hipSuccess) e = sur_forward(s, st);
+  if (e == hipSuccess) e = sur_select(s, b->K, b->seed, SUR_HEAD_NODES, top_k, nullptr, cand, st);
+  if (e == hipSuccess) {
+    SweepArgs a = sweep_args(b);
+    a.K = kk;
+    a.cand_list = cand;
+    a.best = b->best;
+    // the size classes one after another on the caller's stream (no side
+    // streams or events to create)
+    e = launch_sweep(a, st, nullptr);
+    b->best_gen = ~0ull;  // the per-DAG minimum now holds list positions
+  }
+  if (e == hipSuccess) e = launch_best_final(b->best, b->D, best_idx, best_bound, cand, kk, st);
+  if (e == hipSuccess && !st) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(e, "allocation-free surrogate search");
+  return DAGBOUND_OK;
+}
 
 // Surrogate-guided search: score every seeded candidate from the encoder's
 // per-node coefficients over a bounded node set, evaluate the paper's rule

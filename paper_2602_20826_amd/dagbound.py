@@ -32,7 +32,7 @@ MODEL_PARAMS = 100356
 # Every symbol include/dagbound.h declares.
 EXPORTS = (
     "dagbound_create_batch", "dagbound_set_allocations", "dagbound_eval_bounds",
-    "dagbound_best_allocation", "dagbound_eval_listed", "dagbound_get_division", "dagbound_get_schedule", "dagbound_baselines", "dagbound_run_schedule",
+    "dagbound_best_allocation", "dagbound_best_allocation_static", "dagbound_eval_listed", "dagbound_get_division", "dagbound_get_schedule", "dagbound_baselines", "dagbound_run_schedule",
     "dagbound_set_para_launch",
     "dagbound_set_tuning",
     "dagbound_destroy_batch", "dagbound_model_create", "dagbound_model_destroy",
@@ -93,6 +93,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.dagbound_shutdown.argtypes = []
     lib.dagbound_best_allocation.restype = I32
     lib.dagbound_best_allocation.argtypes = [P, U32, I32, P, P, P, U32, P]
+    lib.dagbound_best_allocation_static.restype = I32
+    lib.dagbound_best_allocation_static.argtypes = [P, P, I32, P, P, P]
     lib.dagbound_get_division.restype = I32
     lib.dagbound_get_division.argtypes = [P, I32, P, P, P, P]
     lib.dagbound_get_schedule.restype = I32
@@ -225,7 +227,8 @@ class Batch:
 
     def __del__(self):
         # at interpreter exit the atexit hook has closed every live handle
-        if sys.is_finalizing():
+        # (and module globals such as sys may already be gone)
+        if not self.handle or sys is None or sys.is_finalizing():
             return
         try:
             self.close()
@@ -321,6 +324,18 @@ def best_allocation(batch: Batch, best_idx, best_bound, search: int = SEARCH_EXH
                                         mh, p_i, p_b, kind, _stream_ptr(stream, keep)))
 
 
+def best_allocation_static(batch: Batch, model, top_k: int, best_idx, best_bound, stream=None) -> None:
+    """dagbound_best_allocation_static: the surrogate search without device
+    allocation (device tensors only; the model's workspace must already be
+    sized for the batch by an allocating call)."""
+    lib = load_library()
+    (p_i, p_b), kind, keep = _marshal([(best_idx, "int32"), (best_bound, "int64")])
+    if kind != PTR_DEVICE:
+        raise DagboundError(E_ARG, "best_allocation_static takes device tensors")
+    _check(lib.dagbound_best_allocation_static(ctypes.c_void_p(batch.handle), ctypes.c_void_p(model.handle),
+                                               int(top_k), p_i, p_b, _stream_ptr(stream, keep)))
+
+
 class Model:
     """Owning handle of a dagbound_model (learned candidate proposal)."""
 
@@ -336,7 +351,7 @@ class Model:
             self.handle = 0
 
     def __del__(self):
-        if sys.is_finalizing():
+        if not self.handle or sys is None or sys.is_finalizing():
             return
         try:
             self.close()
