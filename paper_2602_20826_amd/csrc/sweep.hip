@@ -685,8 +685,10 @@ __device__ bool eval_tile(const SweepArgs& a, int item, unsigned char* smem, uin
 #pragma unroll
         for (int k2 = 0; k2 < NW; k2++) cand[k2] = (__ballot(acc[k2] != 0) ? wave_or64(acc[k2]) : 0ull) & ~blocked[k2];
       } else {
-        // rows from LDS: successor rows of the finished nodes, then
-        // predecessor rows of the candidates only
+        // rows from LDS or the row region: successor rows of the finished
+        // nodes (lane-parallel), then, one word of candidates at a time, the
+        // predecessor rows of those candidates (lane-parallel, one load
+        // round trip per word), broadcast from the lane holding each row
 #pragma unroll
         for (int w = 0; w < NW; w++) {
           if ((Fu[w] >> lane) & 1) {
@@ -700,17 +702,24 @@ __device__ bool eval_tile(const SweepArgs& a, int item, unsigned char* smem, uin
         for (int k2 = 0; k2 < NW; k2++) cand[k2] = __ballot(acc[k2] != 0) ? wave_or64(acc[k2]) : 0ull;
 #pragma unroll
         for (int w = 0; w < NW; w++) {
+          if (cand[w] == 0) continue;
+          uint64_t pr[NW];
+#pragma unroll
+          for (int k2 = 0; k2 < NW; k2++) pr[k2] = 0;
+          if ((cand[w] >> lane) & 1) load_row<NW>(pr, s_pb + (w * WAVE + lane) * NW);
           uint64_t open = 0;
-          if ((cand[w] >> lane) & 1) {
-            uint64_t pr[NW];
-            load_row<NW>(pr, s_pb + (w * WAVE + lane) * NW);
 #pragma unroll
-            for (int k2 = 0; k2 < NW; k2++) open |= pr[k2] & ~FO[k2];
+          for (int k2 = 0; k2 < NW; k2++) open |= pr[k2] & ~FO[k2];
+          uint64_t cw = cand[w] & ~__ballot(open != 0);
+          while (cw) {
+            const int ul = __builtin_ctzll(cw);
+            cw &= cw - 1;
+            uint64_t o = 0;
+#pragma unroll
+            for (int k2 = 0; k2 < NW; k2++) o |= readlane64(pr[k2], ul) & ~fin[k2];
+            if (o == 0) rel[w] |= 1ull << ul;
           }
-          blocked[w] = __ballot(open != 0);
         }
-#pragma unroll
-        for (int k2 = 0; k2 < NW; k2++) cand[k2] &= ~blocked[k2];
       }
     }
     // A node found ready is added to rel even where it has finished already;
@@ -726,29 +735,6 @@ __device__ bool eval_tile(const SweepArgs& a, int item, unsigned char* smem, uin
 #pragma unroll
           for (int k2 = 0; k2 < NW; k2++) open |= readlane64(PB[w][k2], ul) & ~fin[k2];
           if (open == 0) rel[w] |= 1ull << ul;
-        }
-      }
-    } else {
-      // rows in flight: two for four-word rows, one for eight-word rows (whose
-      // registers decide between one and two waves per SIMD)
-      constexpr int RIF = NW >= 8 ? 1 : 2;
-      while (bits_any<NW>(cand)) {
-        int u[RIF];
-        uint64_t pr[RIF][NW];
-#pragma unroll
-        for (int t = 0; t < RIF; t++) u[t] = pop_first<NW>(cand);
-#pragma unroll
-        for (int t = 0; t < RIF; t++) {
-          if (u[t] >= 0) load_row<NW>(pr[t], s_pb + u[t] * NW);
-        }
-#pragma unroll
-        for (int t = 0; t < RIF; t++) {
-          if (u[t] >= 0) {
-            uint64_t open = 0;
-#pragma unroll
-            for (int k2 = 0; k2 < NW; k2++) open |= pr[t][k2] & ~fin[k2];
-            if (open == 0) bit_set_u<NW>(rel, u[t]);
-          }
         }
       }
     }
