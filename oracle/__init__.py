@@ -58,6 +58,8 @@ def _load() -> ctypes.CDLL:
         lib.oracle_baselines.argtypes = [ctypes.c_int, ctypes.c_int, P, P, P, P, ctypes.c_int, P]
         lib.oracle_worst_makespan.restype = ctypes.c_int64
         lib.oracle_worst_makespan.argtypes = [ctypes.c_int, ctypes.c_int, P, P, P, P, ctypes.c_int64]
+        lib.oracle_cond_bound.restype = ctypes.c_int
+        lib.oracle_cond_bound.argtypes = [ctypes.c_int, ctypes.c_int, P, P, P, P, ctypes.c_int, P, P, P]
         lib.oracle_random_makespan.restype = ctypes.c_int64
         lib.oracle_random_makespan.argtypes = [ctypes.c_int, ctypes.c_int, P, P, P, P,
                                                ctypes.c_uint64, ctypes.c_int]
@@ -195,6 +197,61 @@ def bound(n, src, dst, wcet, par, M, r=None, trace: bool = False, para_mode: int
         elif tag == 3:
             edges.append((int(rec[1]), int(rec[2]), int(rec[3]), int(rec[4]), int(rec[5])))
     return Schedule(int(out[0]), int(out[1]), int(out[2]), slots, edges)
+
+
+def cond_bound(n, src, dst, wcet, par, M, r, xmask) -> Tuple[int, int, int]:
+    """Bound of one realization of a conditional DAG (spatial reading): the
+    schedule of the DAG with every branch present, each slot's response
+    from the parts of the nodes with xmask[v] != 0 (oracle_cond_bound).
+    Returns (bound, cp, intf)."""
+    lib = _load()
+    s, sp = _arr(src, np.int32)
+    t, tp = _arr(dst, np.int32)
+    w, wp = _arr(wcet, np.int64)
+    p, pp = _arr(par, np.int32)
+    rp = _arr(r, np.uint8)[1] if r is not None else None
+    x, xp = _arr(xmask, np.uint8)
+    out = np.zeros(3, np.int64)
+    rc = lib.oracle_cond_bound(n, len(s), sp, tp, wp, pp, M, rp, xp, out.ctypes.data)
+    if rc != OK:
+        raise OracleError(rc)
+    return int(out[0]), int(out[1]), int(out[2])
+
+
+def realizations(cond_of, branch_of) -> List[np.ndarray]:
+    """Every realization of a conditional DAG as an execution mask, in
+    mixed-radix order: node v with cond_of[v] = q >= 0 runs only in the
+    realizations whose digit q equals branch_of[v] (conditional 0 is the
+    least significant digit, each conditional has max branch + 1
+    branches); nodes with cond_of[v] < 0 always run."""
+    cond_of = np.asarray(cond_of, np.int64)
+    branch_of = np.asarray(branch_of, np.int64)
+    nc = int(cond_of.max()) + 1 if len(cond_of) and cond_of.max() >= 0 else 0
+    nb = [int(branch_of[cond_of == q].max()) + 1 if np.any(cond_of == q) else 1 for q in range(nc)]
+    total = int(np.prod(nb)) if nc else 1
+    out = []
+    for rho in range(total):
+        digit, rest = [], rho
+        for q in range(nc):
+            digit.append(rest % nb[q])
+            rest //= nb[q]
+        m = np.ones(len(cond_of), np.uint8)
+        for v in range(len(cond_of)):
+            if cond_of[v] >= 0 and branch_of[v] != digit[cond_of[v]]:
+                m[v] = 0
+        out.append(m)
+    return out
+
+
+def cond_bound_max(n, src, dst, wcet, par, M, r, cond_of, branch_of) -> Tuple[int, int]:
+    """The conditional DAG's bound: the largest realization bound, and the
+    first realization (mixed-radix index) that reaches it."""
+    best, arg = -1, -1
+    for rho, m in enumerate(realizations(cond_of, branch_of)):
+        b = cond_bound(n, src, dst, wcet, par, M, r, m)[0]
+        if b > best:
+            best, arg = b, rho
+    return best, arg
 
 
 def bounds_dag(n, src, dst, wcet, par, M, K, alloc_dag,

@@ -395,7 +395,8 @@ static void trace_put(trace_t* t, int64_t a0, int64_t a1, int64_t a2, int64_t a3
  * launched nodes run one after another on them (chain edges), and the
  * budget is the slot's time maxC; a node that does not fit in the time left
  * is segmented at (time left) * m_c and the launching stops. */
-static int oracle_schedule(const odag* g, const uint8_t* r, int64_t* out3, trace_t* tr, int temporal) {
+static int oracle_schedule(const odag* g, const uint8_t* r, int64_t* out3, trace_t* tr, int temporal,
+                           const uint8_t* xm) {
   int n = g->n;
   int64_t M = g->M;
   int64_t* cur = malloc(sizeof(int64_t) * (size_t)(n + 1));       /* remaining load, \hat C */
@@ -423,6 +424,9 @@ static int oracle_schedule(const odag* g, const uint8_t* r, int64_t* out3, trace
     released[v] = (npred[v] == 0);      /* Released_nodes <- src(G) */
   }
   int64_t bound = 0, cp = 0, intf = 0;
+  /* conditional reading (xm != NULL): the same schedule, and each slot's
+   * response from the parts of the nodes that execute (xm[v] != 0) */
+  int64_t xbound = 0, xcp = 0;
   for (int j = 0; j < g->ngroups; j++) {
     /* members of pi_j that are not complete yet */
     int nP = 0;
@@ -435,6 +439,7 @@ static int oracle_schedule(const odag* g, const uint8_t* r, int64_t* out3, trace
     int64_t W = 0;
     for (int i = 0; i < nP; i++) W += cur[P[i]];
     int64_t maxC = 0, sum_m = 0, A = 0;
+    int64_t xmaxC = 0, xsum_m = 0, xA = 0;
     int vR = -1;
     for (int i = 0; i < nP; i++) {
       int v = P[i];
@@ -451,6 +456,7 @@ static int oracle_schedule(const odag* g, const uint8_t* r, int64_t* out3, trace
       sum_m += mv;
       A += mv * C[v];
       if (C[v] > maxC || (C[v] == maxC && v < vR)) { maxC = C[v]; vR = v; }
+      if (!xm || xm[v]) { xsum_m += mv; xA += mv * C[v]; xmaxC = max64(xmaxC, C[v]); }
     }
     for (int i = 0; i < nP; i++)
       trace_put(tr, 2, j, P[i], nparts[P[i]], 0, m[P[i]], C[P[i]], cur[P[i]]);
@@ -505,6 +511,7 @@ static int oracle_schedule(const odag* g, const uint8_t* r, int64_t* out3, trace
         cur[c] -= cap;
         A += mc * ceil_div(cap, mc);
         sum_m += mc;
+        if (!xm || xm[c]) { xsum_m += mc; xA += mc * ceil_div(cap, mc); xmaxC = max64(xmaxC, ceil_div(cap, mc)); }
         seg_node = c;
         break;
       }
@@ -514,12 +521,18 @@ static int oracle_schedule(const odag* g, const uint8_t* r, int64_t* out3, trace
       launched_part[nl++] = c;
       A += mc * Cc;
       sum_m += mc;
+      if (!xm || xm[c]) { xsum_m += mc; xA += mc * Cc; xmaxC = max64(xmaxC, Cc); }
       S -= mc;
     }
     /* Lemma 1, with the list-scheduling term when the slot oversubscribes */
     int64_t Rj = maxC;
     if (sum_m > M) Rj = maxC + (A - maxC) / M;
     bound += Rj; cp += maxC; intf += Rj - maxC;
+    /* Lemma 1 over the executed parts only: they start together when they
+     * fit, else list scheduling bounds them; no executed part: 0 */
+    int64_t xRj = xmaxC;
+    if (xsum_m > M) xRj = xmaxC + (xA - xmaxC) / M;
+    xbound += xRj; xcp += xmaxC;
     trace_put(tr, 1, j, nP, maxC, sum_m, A, Rj, vR);
     /* extra dependencies (Section 4.1), recorded for inspection */
     int vR_part = nparts[vR];
@@ -557,7 +570,8 @@ static int oracle_schedule(const odag* g, const uint8_t* r, int64_t* out3, trace
     for (int i = 0; i < nP; i++) inP[P[i]] = 0;
     for (int i = 0; i < nl; i++) launched_whole[launched_part[i]] = 0;
   }
-  out3[0] = bound; out3[1] = cp; out3[2] = intf;
+  if (xm) { out3[0] = xbound; out3[1] = xcp; out3[2] = xbound - xcp; }
+  else { out3[0] = bound; out3[1] = cp; out3[2] = intf; }
   free(cur); free(complete); free(released); free(inP); free(npred); free(nparts); free(P);
   free(m); free(C); free(para); free(done); free(launched_whole); free(launched_part);
   return O_OK;
@@ -574,9 +588,27 @@ int oracle_bound(int n, int e, const int32_t* src, const int32_t* dst, const int
   int rc = oracle_prepare(&g, n, e, src, dst, wcet, par, M);
   if (rc == O_OK) {
     trace_t t = { trace, trace_cap, 0 };
-    rc = oracle_schedule(&g, r, out3, &t, para_mode);
+    rc = oracle_schedule(&g, r, out3, &t, para_mode, NULL);
     if (trace_n) *trace_n = t.n;
   }
+  odag_free(&g);
+  return rc;
+}
+
+/* Conditional DAGs (the paper's future work, Section 6), spatial reading:
+ * the schedule of the DAG with every branch present, and the makespan bound
+ * of one realization, in which only the nodes with xm[v] != 0 execute (the
+ * others take no SM and no time).  Each slot's response is Lemma 1 over
+ * the slot's executed parts (members, parallel nodes launched whole and
+ * parallel segments): their largest C when their SMs fit in M, else the
+ * list-scheduling form; a slot with no executed part takes 0.  out3 =
+ * {bound, critical-path term, interference term} of the realization. */
+int oracle_cond_bound(int n, int e, const int32_t* src, const int32_t* dst, const int64_t* wcet,
+                      const int32_t* par, int M, const uint8_t* r, const uint8_t* xm, int64_t* out3) {
+  odag g;
+  if (!xm) return O_E_ARG;
+  int rc = oracle_prepare(&g, n, e, src, dst, wcet, par, M);
+  if (rc == O_OK) rc = oracle_schedule(&g, r, out3, NULL, 0, xm);
   odag_free(&g);
   return rc;
 }
@@ -591,7 +623,7 @@ int oracle_bounds_dag(int n, int e, const int32_t* src, const int32_t* dst, cons
   int rc = oracle_prepare(&g, n, e, src, dst, wcet, par, M);
   for (int c = 0; c < K && rc == O_OK; c++) {
     int64_t o[3];
-    rc = oracle_schedule(&g, c == 0 ? NULL : r + (int64_t)c * n, o, NULL, para_mode);
+    rc = oracle_schedule(&g, c == 0 ? NULL : r + (int64_t)c * n, o, NULL, para_mode, NULL);
     bounds[c] = o[0];
     if (cp) cp[c] = o[1];
     if (intf) intf[c] = o[2];

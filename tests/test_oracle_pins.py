@@ -655,3 +655,129 @@ def test_rejects_bad_inputs():
         oracle.bound(3, [0], [1], w, [1, 1, 0], 4)
     assert e.value.code == oracle.E_RANGE
     assert oracle.bound(0, [], [], [], [], 4) == (0, 0, 0)
+
+
+# ---------------------------------------------------------------- conditional DAGs
+# (the paper's future work): the schedule of the DAG with every branch
+# present; in one realization only the chosen branches' nodes execute, and
+# each slot's response is Lemma 1 over its executed parts.
+
+def test_conditional_hand_cases():
+    # s -> a | b -> t with a and b the two branches of one conditional.
+    #   M = 4, loads (1, 8, 3, 1), p = (1, 4, 1, 1), candidate byte 2 for a.
+    #   Groups {s}, {a} (Rule 2: m^max(a) = 4 >= M), {b}, {t}.  Slot 2: a runs
+    #   on 2 SMs (C = 4), S = 2, and b is launched beside it whole (m = 1,
+    #   C = 3 <= maxC); slot 3 is then empty.  Full bound 1 + 4 + 0 + 1 = 6.
+    #   Realization "a": slot 2 holds a (4): 6.  Realization "b": slot 2
+    #   holds only b's parallel part (3): 1 + 3 + 0 + 1 = 5.
+    src, dst = np.array([0, 0, 1, 2]), np.array([1, 2, 3, 3])
+    w, p = np.array([1, 8, 3, 1]), np.array([1, 4, 1, 1])
+    r = np.array([0, 2, 0, 0], np.uint8)
+    cond, br = [-1, 0, 0, -1], [0, 0, 1, 0]
+    assert oracle.bound(4, src, dst, w, p, 4, r)[0] == 6
+    masks = oracle.realizations(cond, br)
+    assert [m.tolist() for m in masks] == [[1, 1, 0, 1], [1, 0, 1, 1]]
+    assert oracle.cond_bound(4, src, dst, w, p, 4, r, masks[0]) == (6, 6, 0)
+    assert oracle.cond_bound(4, src, dst, w, p, 4, r, masks[1]) == (5, 5, 0)
+    assert oracle.cond_bound_max(4, src, dst, w, p, 4, r, cond, br) == (6, 0)
+    # with the paper's rule a runs on all 4 SMs (C = 2), b has its own slot
+    # (m = 1, C = 3): full 1 + 2 + 3 + 1 = 7; each realization skips one of
+    # the two middle slots: 1 + 2 + 0 + 1 = 4 and 1 + 0 + 3 + 1 = 5.
+    assert oracle.bound(4, src, dst, w, p, 4)[0] == 7
+    assert oracle.cond_bound(4, src, dst, w, p, 4, None, masks[0])[0] == 4
+    assert oracle.cond_bound(4, src, dst, w, p, 4, None, masks[1])[0] == 5
+    assert oracle.cond_bound_max(4, src, dst, w, p, 4, None, cond, br) == (5, 1)
+
+
+def test_conditional_oversubscribed_slot_that_fits_once_branches_are_skipped():
+    # M = 3; s -> x, y -> t, x and y the two branches; loads (1, 6, 6, 1),
+    # p = (1, 2, 2, 1), candidate bytes 2 for x and y.  One group {x, y}
+    # (m^max = 2 < M, no Rule 2): m = 2 + 2 = 4 > 3, C = 3 each, A = 12, so
+    # the slot takes 3 + floor((12 - 3) / 3) = 6; full bound 1 + 6 + 1 = 8.
+    # With one branch the slot holds 2 SMs for 3 ticks: 1 + 3 + 1 = 5.
+    src, dst = np.array([0, 0, 1, 2]), np.array([1, 2, 3, 3])
+    w, p = np.array([1, 6, 6, 1]), np.array([1, 2, 2, 1])
+    r = np.array([0, 2, 2, 0], np.uint8)
+    assert oracle.bound(4, src, dst, w, p, 3, r) == (8, 5, 3)
+    for m in oracle.realizations([-1, 0, 0, -1], [0, 0, 1, 0]):
+        assert oracle.cond_bound(4, src, dst, w, p, 3, r, m) == (5, 5, 0)
+
+
+def test_conditional_realization_order():
+    # two conditionals of 2 and 3 branches: 6 realizations, conditional 0
+    # the least significant digit
+    cond, br = [0, 0, 1, 1, 1, -1], [0, 1, 0, 1, 2, 0]
+    masks = [m.tolist() for m in oracle.realizations(cond, br)]
+    assert masks == [[1, 0, 1, 0, 0, 1], [0, 1, 1, 0, 0, 1], [1, 0, 0, 1, 0, 1],
+                     [0, 1, 0, 1, 0, 1], [1, 0, 0, 0, 1, 1], [0, 1, 0, 0, 1, 1]]
+    assert [m.tolist() for m in oracle.realizations([-1, -1], [0, 0])] == [[1, 1]]
+
+
+@pytest.mark.parametrize("seed", range(20))
+def test_conditional_every_node_executed_is_the_bound(seed):
+    rng = np.random.default_rng(5100 + seed)
+    n, src, dst, w, p = W.random_small_dag(rng, int(rng.integers(2, 40)), 0.15, 500, 40)
+    M = int(rng.integers(1, 64))
+    r = W.random_alloc(rng, p, M, 0.3)
+    for rr in (None, r):
+        assert oracle.cond_bound(n, src, dst, w, p, M, rr, np.ones(n, np.uint8)) == \
+            oracle.bound(n, src, dst, w, p, M, rr)
+
+
+@pytest.mark.parametrize("seed", range(20))
+def test_conditional_bound_is_monotone_in_the_executed_set(seed):
+    rng = np.random.default_rng(5200 + seed)
+    n, src, dst, w, p = W.random_small_dag(rng, int(rng.integers(2, 30)), 0.2, 300, 30)
+    M = int(rng.integers(1, 32))
+    r = W.random_alloc(rng, p, M, 0.3)
+    full = oracle.bound(n, src, dst, w, p, M, r)[0]
+    for _ in range(5):
+        big = (rng.random(n) < 0.7).astype(np.uint8)
+        small = big & (rng.random(n) < 0.6).astype(np.uint8)
+        bs = oracle.cond_bound(n, src, dst, w, p, M, r, small)[0]
+        bb = oracle.cond_bound(n, src, dst, w, p, M, r, big)[0]
+        assert 0 <= bs <= bb <= full
+    assert oracle.cond_bound(n, src, dst, w, p, M, r, np.zeros(n, np.uint8))[0] == 0
+
+
+def _executed_parts(sched, xm):
+    """Part DAG of the executed parts of a traced schedule: one barrier
+    between consecutive slots that keep a part (empty slots pass at once)."""
+    parts = [q for s in sched.slots for q in s.parts if xm[q.node]]
+    m = [q.m for q in parts]
+    C = [q.C for q in parts]
+    by_slot = {}
+    for i, q in enumerate(parts):
+        by_slot.setdefault(q.slot, []).append(i)
+    preds = [[] for _ in parts]
+    slots = sorted(by_slot)
+    for a, b in zip(slots, slots[1:]):
+        for x in by_slot[b]:
+            preds[x] = list(by_slot[a])
+    return m, C, preds, by_slot
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_conditional_bound_safe_against_every_dispatch(seed):
+    # every work-conserving dispatch of the executed blocks (one barrier per
+    # slot boundary) ends by the realization's bound, and exactly at it when
+    # no slot's executed parts oversubscribe M
+    rng = np.random.default_rng(5300 + seed)
+    n, src, dst, w, p = W.random_small_dag(rng, int(rng.integers(3, 8)), 0.3, 6, 4)
+    M = int(rng.integers(1, 6))
+    r = W.random_alloc(rng, p, M, 0.4)
+    cond = np.where(rng.random(n) < 0.6, rng.integers(0, 2, n), -1)
+    br = rng.integers(0, 2, n)
+    s = oracle.bound(n, src, dst, w, p, M, r, trace=True)
+    checked = 0
+    for xm in oracle.realizations(cond, br):
+        b = oracle.cond_bound(n, src, dst, w, p, M, r, xm)[0]
+        m, C, preds, by_slot = _executed_parts(s, xm)
+        worst = oracle.worst_makespan(m, C, preds, M, node_limit=2_000_000) if m else 0
+        if worst < 0:
+            continue
+        assert worst <= b
+        if all(sum(m[i] for i in idx) <= M for idx in by_slot.values()):
+            assert worst == b
+        checked += 1
+    assert checked > 0
