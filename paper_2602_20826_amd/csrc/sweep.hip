@@ -220,6 +220,14 @@ template <int NW, bool RS> struct RowsInGlobal { static constexpr bool value = N
 template <int NW, bool RS> struct RowsInRegs {
   static constexpr bool value = NW <= 4 && !RowsInGlobal<NW, RS>::value;
 };
+// Eight-word rows keep the residual-slot map in the row region too (after
+// the two row blocks): 16 KB of LDS less per wavefront at 512 nodes.
+template <int NW, bool RS> struct MapInGlobal { static constexpr bool value = NW == 8 && RS; };
+// 64-bit words of one workgroup's row region (two row blocks, and the map
+// where it lives there) for DAGs of up to max_n nodes.
+__host__ __device__ inline size_t row_region_words(int max_n, int nw, bool rs) {
+  return 2 * (size_t)max_n * nw + (nw == 8 && rs ? 4 * ((size_t)max_n + 7) : 0);
+}
 
 // LDS layout of one wavefront (bytes), for the batch's largest DAG.
 struct Lds {
@@ -246,7 +254,7 @@ __host__ __device__ inline Lds lds_layout(int maxn, int nw, bool big, bool rs) {
     static_assert(RES_SLOTS * WAVE * 4 >= 2 * 512 * 2, "id tables fit in the residual table");
   }
   l.r = o;    o += rs ? 0 : (size_t)maxn * WAVE;  // candidate bytes [sigma][lane] (none when drawn on the fly)
-  l.map = o;  o += big ? 0 : (size_t)((maxn + 7) / 8) * WAVE * 4;  // residual slot of a node, 4 bits
+  l.map = o;  o += (big || (nw == 8 && rs)) ? 0 : (size_t)((maxn + 7) / 8) * WAVE * 4;  // residual slot of a node, 4 bits
   if (regs) {
     // built in the candidate-byte region before the bytes are loaded
     l.pb = l.r;
@@ -321,7 +329,8 @@ __device__ bool eval_tile(const SweepArgs& a, int item, unsigned char* smem, uin
   uint64_t* s_sb = GROWS ? grows + (size_t)a.max_n * NW : (uint64_t*)(smem + L.sb);  // [sigma][NW]
   uint32_t* res = BIG ? gres : (uint32_t*)(smem + L.res);  // [slot][lane], or [sigma][lane] when BIG
   uint8_t* s_r = smem + L.r;                   // [sigma][lane]
-  uint32_t* s_map = (uint32_t*)(smem + L.map); // [sigma / 8][lane], 4 bits per node: slot + 1
+  uint32_t* s_map = MapInGlobal<NW, RS>::value ? (uint32_t*)(grows + 2 * (size_t)a.max_n * NW)
+                                               : (uint32_t*)(smem + L.map); // [sigma / 8][lane], 4 bits per node: slot + 1
 
   // ---- DAG tables (shared by the 64 candidates)
   for (int s = lane; s < N; s += WAVE) s_node[s] = make_uint2(a.t.wc[n0 + s], a.t.pp[n0 + s]);
@@ -782,9 +791,9 @@ __device__ void first_pass_tile(const SweepArgs& a, int item, unsigned char* sme
 }
 
 // Row region of workgroup `slot` (rows in global memory only).
-template <int NW>
+template <int NW, bool RS>
 __device__ inline uint64_t* rows_of(const SweepArgs& a, int slot) {
-  return a.grows ? a.grows + (size_t)slot * 2 * (size_t)a.max_n * NW : nullptr;
+  return a.grows ? a.grows + (size_t)slot * row_region_words(a.max_n, NW, RS) : nullptr;
 }
 
 template <int NW, bool SMALL, bool RS, bool TP>
@@ -805,7 +814,7 @@ template <int NW, bool SMALL, bool RS, bool TP>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_eval_persistent(SweepArgs a, uint32_t* counters, uint32_t* list,
                                                         int total) {
   extern __shared__ __align__(16) unsigned char smem[];
-  uint64_t* grows = rows_of<NW>(a, blockIdx.x);
+  uint64_t* grows = rows_of<NW, RS>(a, blockIdx.x);
   for (;;) {
     uint32_t item = 0;
     if (threadIdx.x == 0) item = atomicAdd(&counters[2], 1u);
@@ -824,7 +833,7 @@ __global__ __launch_bounds__(64) void k_eval_global(SweepArgs a, const uint32_t*
   extern __shared__ __align__(16) unsigned char smem[];
   const int count = direct ? total : (int)counters[0];
   uint32_t* gres = a.gres + (size_t)blockIdx.x * (size_t)a.max_n * WAVE;
-  uint64_t* grows = rows_of<NW>(a, blockIdx.x);
+  uint64_t* grows = rows_of<NW, RS>(a, blockIdx.x);
   for (int q = blockIdx.x; q < count; q += gridDim.x) {
     const int item = direct ? q : (int)list[q];
     eval_tile<NW, true, SMALL, RS, TP>(a, item, smem, gres, grows);
@@ -926,11 +935,11 @@ size_t sweep_rows_words(const int32_t class_max_n[NUM_CLASSES], const int32_t cl
   for (int c = 0; c < NUM_CLASSES; c++) {
     rows_off[c] = w;
     if (c >= 2 && c < LARGE_CLASS && class_off[c + 1] > class_off[c])
-      w += (size_t)ROW_REGIONS * 2 * (size_t)class_max_n[c] * (4u << (c - 2));
+      w += (size_t)ROW_REGIONS * row_region_words(class_max_n[c], 4 << (c - 2), true);
   }
   rows_off[NUM_CLASSES] = w;  // the one-launch mode's pool
   const int cls = class_of(max_n);
-  if (cls >= 2 && cls < LARGE_CLASS) w += (size_t)ROW_REGIONS * 2 * (size_t)max_n * (4u << (cls - 2));
+  if (cls >= 2 && cls < LARGE_CLASS) w += (size_t)ROW_REGIONS * row_region_words(max_n, 4 << (cls - 2), true);
   return w;
 }
 
