@@ -198,6 +198,38 @@ dagbound_status dagbound_eval_listed(dagbound_batch* batch, int32_t L, const int
                                      int64_t* cp_term, int64_t* intf_term, uint32_t ptr_kind, void* hip_stream);
 
 /*
+ * dagbound_eval_conditional -- makespan bounds of conditional DAG tasks (the
+ * extension the paper names as future work in Section 6), for every
+ * (DAG, candidate) of the current allocation set.  A conditional is a set of
+ * alternative branches of which exactly one executes at run time; a
+ * realization picks one branch of every conditional of a DAG.  The schedule
+ * is the method's schedule of the DAG with every branch present (Algorithms
+ * 1 and 2, spatial reading); in a realization the nodes of the branches not
+ * taken hold no SM and no time, and each slot's response is Lemma 1 over the
+ * slot's executed parts (members, parallel nodes launched whole, parallel
+ * segments), 0 for a slot with none.  The result is the largest
+ * realization bound.
+ *   cond_of    int32 [node_off[D]]: the node's conditional within its DAG
+ *              (0, 1, ...), or -1 for a node that always executes.
+ *   branch_of  int32 [node_off[D]]: its branch within that conditional,
+ *              0..254 (ignored for -1).  A conditional has max branch + 1
+ *              branches; conditionals do not nest.
+ *   bounds     int64 [D*K]: bounds[d*K + c] the largest realization bound.
+ *   worst      int32 [D*K] or NULL: the first realization reaching it, as a
+ *              mixed-radix index with conditional 0 the least significant
+ *              digit.
+ * Same memory kind (ptr_kind) for all four arrays.  With every node at -1
+ * the result equals dagbound_eval_bounds.  The call waits for its work.
+ * Limits: DAGs of up to 512 nodes, at most 4,096 realizations per DAG, the
+ * spatial reading of the launching loop.
+ * Errors: E_ARG, E_STATE (no allocations set), E_RANGE (ids outside the
+ * ranges above, too many realizations), E_UNSUPPORTED (a DAG above 512
+ * nodes, the temporal reading), E_OOM, E_DEVICE.
+ */
+dagbound_status dagbound_eval_conditional(dagbound_batch* batch, const int32_t* cond_of, const int32_t* branch_of,
+                                          int64_t* bounds, int32_t* worst, uint32_t ptr_kind, void* hip_stream);
+
+/*
  * dagbound_set_para_launch -- the reading of the launching loop of
  * Section 4.1 (Eqs. 6-7, Algorithm 2) used by every later evaluation of the
  * batch (eval_bounds, best_allocation, get_schedule, run_schedule).

@@ -1045,13 +1045,18 @@ dagbound_status dagbound_eval_listed(dagbound_batch* b, int32_t L, const int32_t
         return fail(DAGBOUND_E_ARG, "cand[%zu] = %d outside [0, %d)", i, cand[i], b->K);
   }
   void* tmp = nullptr;
-  size_t tmp_size = 5 * 256 + n * 4 + 4 + (host ? n * 8 * (1 + (cp_term != nullptr) + (intf_term != nullptr)) : 0);
+  // tiles handed to the second evaluation pass are listed per call: the
+  // batch's list holds the allocation set's tiles, a list may have more
+  const size_t tiles = (size_t)b->D * (size_t)((L + 63) / 64);
+  size_t tmp_size = 6 * 256 + n * 4 + 4 + tiles * 4 +
+                    (host ? n * 8 * (1 + (cp_term != nullptr) + (intf_term != nullptr)) : 0);
   hipError_t e = dev_alloc(&tmp, &tmp_size, b->device);
   if (e != hipSuccess) return hip_fail(e, "allocating list scratch");
   Carve c(tmp);
   uint32_t* bad = c.take<uint32_t>(1);
   SweepArgs a = sweep_args(b);
   a.K = L;
+  a.ovf_list = c.take<uint32_t>(tiles);
   a.best = b->best;
   if (host) {
     int32_t* dl = c.take<int32_t>(n);
@@ -1087,6 +1092,114 @@ dagbound_status dagbound_eval_listed(dagbound_batch* b, int32_t L, const int32_t
   if (e == hipSuccess) e = es;
   dev_release(tmp, tmp_size, b->device);
   if (e != hipSuccess) return hip_fail(e, "evaluating listed candidates");
+  return DAGBOUND_OK;
+}
+
+dagbound_status dagbound_eval_conditional(dagbound_batch* b, const int32_t* cond_of, const int32_t* branch_of,
+                                          int64_t* bounds, int32_t* worst, uint32_t ptr_kind, void* hip_stream) {
+  g_err.clear();
+  if (!b) return fail(DAGBOUND_E_ARG, "batch is NULL");
+  if (ptr_kind > DAGBOUND_PTR_DEVICE) return fail(DAGBOUND_E_ARG, "bad ptr_kind %u", ptr_kind);
+  if (!b->has_alloc) return fail(DAGBOUND_E_STATE, "set_allocations has not been called");
+  if (b->para_mode != DAGBOUND_PARA_SPATIAL)
+    return fail(DAGBOUND_E_UNSUPPORTED, "conditional DAGs are evaluated under the spatial launching reading only");
+  if (b->max_n > 512) return fail(DAGBOUND_E_UNSUPPORTED, "conditional DAGs of more than 512 nodes are not supported");
+  const int64_t D = b->D, K = b->K, T = b->tn;
+  if (D * K == 0) return DAGBOUND_OK;
+  if (!bounds) return fail(DAGBOUND_E_ARG, "bounds is NULL");
+  if (T > 0 && (!cond_of || !branch_of)) return fail(DAGBOUND_E_ARG, "cond_of/branch_of is NULL");
+  DeviceGuard g(b->device);
+  hipStream_t st = (hipStream_t)hip_stream;
+  const bool host = ptr_kind == DAGBOUND_PTR_HOST;
+  std::vector<int32_t> co((size_t)T), br((size_t)T);
+  std::vector<uint16_t> inv((size_t)T);
+  hipError_t e = hipSuccess;
+  if (host) {
+    std::copy(cond_of, cond_of + T, co.begin());
+    std::copy(branch_of, branch_of + T, br.begin());
+  } else {
+    e = hipMemcpyAsync(co.data(), cond_of, (size_t)T * 4, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(br.data(), branch_of, (size_t)T * 4, hipMemcpyDeviceToHost, st);
+  }
+  if (e == hipSuccess) e = hipMemcpyAsync(inv.data(), b->t.inv, (size_t)T * 2, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(e, "reading the conditional structure");
+  // per DAG: branches of each conditional, mixed-radix place values, realizations
+  std::vector<int32_t> R((size_t)D);
+  std::vector<uint32_t> tab((size_t)T);
+  int32_t Rmax = 1;
+  for (int64_t d = 0; d < D; d++) {
+    const int64_t n0 = b->node_off[d], n1 = b->node_off[d + 1];
+    int32_t nq = 0;
+    for (int64_t v = n0; v < n1; v++) {
+      if (co[v] < -1 || co[v] >= COND_MAX_REALIZATIONS)
+        return fail(DAGBOUND_E_RANGE, "cond_of[%lld] = %d outside [-1, %d)", (long long)v, co[v], COND_MAX_REALIZATIONS);
+      if (co[v] >= 0 && (br[v] < 0 || br[v] > 254))
+        return fail(DAGBOUND_E_RANGE, "branch_of[%lld] = %d outside [0, 254]", (long long)v, br[v]);
+      nq = std::max(nq, co[v] + 1);
+    }
+    std::vector<int32_t> nb((size_t)nq, 1), pre((size_t)nq, 1);
+    for (int64_t v = n0; v < n1; v++)
+      if (co[v] >= 0) nb[co[v]] = std::max(nb[co[v]], br[v] + 1);
+    int64_t r = 1;
+    for (int32_t q = 0; q < nq; q++) {
+      pre[q] = (int32_t)r;
+      r *= nb[q];
+      if (r > COND_MAX_REALIZATIONS)
+        return fail(DAGBOUND_E_RANGE, "DAG %lld has more than %d realizations", (long long)d, COND_MAX_REALIZATIONS);
+    }
+    R[d] = (int32_t)r;
+    Rmax = std::max(Rmax, (int32_t)r);
+    for (int64_t v = n0; v < n1; v++) {
+      const int64_t s = n0 + inv[v];
+      tab[s] = co[v] < 0 ? 1u
+                         : (uint32_t)pre[co[v]] | ((uint32_t)nb[co[v]] << 13) | ((uint32_t)br[v] << 21);
+    }
+  }
+  const int64_t L = K * Rmax;  // list entries per DAG: candidate c's realizations at c * Rmax + rho
+  if (L > INT32_MAX / 2 || D * ((L + 63) / 64) > INT32_MAX)
+    return fail(DAGBOUND_E_RANGE, "K x realizations = %lld per DAG is too large", (long long)L);
+  void* tmp = nullptr;
+  const size_t tiles = (size_t)D * (size_t)((L + 63) / 64);  // the second pass's list, per call
+  size_t tmp_size = 7 * 256 + (size_t)T * 4 + (size_t)D * 4 + (size_t)(D * L) * 4 + (size_t)(D * L) * 8 +
+                    tiles * 4 + (host ? (size_t)(D * K) * 12 : 0);
+  e = dev_alloc(&tmp, &tmp_size, b->device);
+  if (e != hipSuccess) return hip_fail(e, "allocating conditional scratch");
+  Carve c(tmp);
+  uint32_t* dtab = c.take<uint32_t>((size_t)T);
+  int32_t* dR = c.take<int32_t>((size_t)D);
+  int32_t* list = c.take<int32_t>((size_t)(D * L));
+  int64_t* rb = c.take<int64_t>((size_t)(D * L));
+  uint32_t* ovf = c.take<uint32_t>(tiles);
+  int64_t* ob = host ? c.take<int64_t>((size_t)(D * K)) : bounds;
+  int32_t* ow = host ? (worst ? c.take<int32_t>((size_t)(D * K)) : nullptr) : worst;
+  e = hipMemcpyAsync(dtab, tab.data(), (size_t)T * 4, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(dR, R.data(), (size_t)D * 4, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = launch_cond_list(list, D * L, L, Rmax, st);
+  if (e == hipSuccess) {
+    SweepArgs a = sweep_args(b);
+    a.K = (int32_t)L;
+    a.ovf_list = ovf;
+    a.cand_list = list;
+    a.bounds = rb;
+    a.cp = a.intf = nullptr;
+    a.best = b->best;  // reset by the launch; the conditional kernels leave it alone
+    a.cond_tab = dtab;
+    a.cond_R = Rmax;
+    a.node_lanes_class = LARGE_CLASS;  // the lane-per-candidate kernels of every class up to 512 nodes
+    e = run_sweep_plan(b, a, st);
+    b->best_gen = ~0ull;
+  }
+  if (e == hipSuccess) e = launch_cond_reduce(rb, dR, (int32_t)D, (int32_t)K, Rmax, ob, ow, st);
+  if (e == hipSuccess && host) {
+    e = hipMemcpyAsync(bounds, ob, (size_t)(D * K) * 8, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess && worst) e = hipMemcpyAsync(worst, ow, (size_t)(D * K) * 4, hipMemcpyDeviceToHost, st);
+  }
+  // the scratch is released below, so the work is waited for
+  const hipError_t es = hipStreamSynchronize(st);
+  if (e == hipSuccess) e = es;
+  dev_release(tmp, tmp_size, b->device);
+  if (e != hipSuccess) return hip_fail(e, "evaluating conditional DAGs");
   return DAGBOUND_OK;
 }
 

@@ -150,7 +150,21 @@ struct SweepArgs {
   int32_t small_indeg;          // every in-degree < 256
   int32_t persistent;           // first pass as a persistent kernel over a work counter
   int32_t node_lanes_class;     // classes from this one on run the lane-per-node kernel (3 or 4)
+  // Conditional DAGs (spatial reading, DAGs up to 512 nodes): per node by
+  // sigma rank, pre | nb << 13 | branch << 21 (nb = 0: always executes;
+  // else the node runs in realization rho iff (rho / pre) mod nb == branch),
+  // or nullptr.  List position p evaluates realization p mod cond_R.
+  const uint32_t* cond_tab;
+  int32_t cond_R;
 };
+// Largest number of realizations of one conditional DAG.
+constexpr int COND_MAX_REALIZATIONS = 4096;
+// bounds[d * K + c] = max over rho < R[d] of rb[(d * K + c) * Rmax + rho];
+// worst (nullable) the first rho reaching it.
+// list[i] = (i mod L) / Rmax for i < n: each candidate's realizations in turn.
+hipError_t launch_cond_list(int32_t* list, int64_t n, int64_t L, int32_t Rmax, hipStream_t stream);
+hipError_t launch_cond_reduce(const int64_t* rb, const int32_t* R, int32_t D, int32_t K, int32_t Rmax,
+                              int64_t* bounds, int32_t* worst, hipStream_t stream);
 
 // Packing of the per-DAG minimum: bound < 2^42 (the summed load is < 2^40)
 // and candidate < 2^22.

@@ -303,9 +303,14 @@ __device__ inline uint32_t round_share_small(uint32_t cv, uint32_t M, uint32_t W
 
 // One (DAG, 64-candidate tile).  Returns true if a lane's residual table
 // overflowed (nothing was written; the tile must be redone by the
-// global-table pass).
-template <int NW, bool BIG, bool SMALL, bool RS, bool TP>
+// global-table pass).  LM: the launching loop's reading, spatial (0) or
+// temporal (1); 2 is the spatial reading of a conditional DAG, where lane
+// (list position) p evaluates realization p mod a.cond_R of its candidate:
+// the same schedule, and each slot's response over its executed parts.
+template <int NW, bool BIG, bool SMALL, bool RS, int LM>
 __device__ bool eval_tile(const SweepArgs& a, int item, unsigned char* smem, uint32_t* gres, uint64_t* grows) {
+  constexpr bool TP = LM == 1;
+  constexpr bool CD = LM == 2;
   constexpr bool REG = RowsInRegs<NW, RS>::value;
   constexpr bool GROWS = RowsInGlobal<NW, RS>::value;
   const int ntile = (a.K + WAVE - 1) / WAVE;
@@ -446,6 +451,20 @@ __device__ bool eval_tile(const SweepArgs& a, int item, unsigned char* smem, uin
   }
   __syncthreads();
 
+  // Conditional DAGs: the nodes of this lane's realization that execute.
+  uint64_t xm[NW];
+  if constexpr (CD) {
+#pragma unroll
+    for (int w = 0; w < NW; w++) xm[w] = 0;
+    const uint32_t rho = active ? (uint32_t)(slot % a.cond_R) : 0u;
+    for (int s = 0; s < N; s++) {
+      const uint32_t t = a.cond_tab[n0 + s];
+      const uint32_t nb = (t >> 13) & 255u;
+      const bool ex = nb == 0 || (rho / (t & 0x1FFFu)) % nb == (t >> 21);
+      if (ex) bit_set_u<NW>(xm, s);
+    }
+  }
+
   // Remaining load of a segmented node.
   auto res_at = [&](int s) -> uint32_t* {
     if (BIG) return &res[s * WAVE + lane];
@@ -457,6 +476,7 @@ __device__ bool eval_tile(const SweepArgs& a, int item, unsigned char* smem, uin
   // and unfinished (Algorithm 2's Released_nodes); fin: finished; seg:
   // segmented and unfinished, remaining load in the residual table.
   uint64_t bound = 0, cp = 0;
+  uint64_t xbound = 0, xcp = 0;  // conditional: the realization's bound and maxC terms
   bool ovf = false;
   uint64_t FO[NW];  // nodes finished in some lane (wave-uniform)
 #pragma unroll
@@ -512,6 +532,8 @@ __device__ bool eval_tile(const SweepArgs& a, int item, unsigned char* smem, uin
     // the next member is read one step ahead.
     const float rw2 = SMALL ? __builtin_amdgcn_rcpf((float)(2ull * W)) : 0.0f;
     uint32_t maxC = 0, sm = 0;
+    uint32_t xmaxC = 0, xsm = 0;  // conditional: over the slot's executed parts
+    uint64_t xA = 0;
     // with loads below 2^20, m C < load + m < 2^21 per member and the sums
     // of up to 512 members stay below 2^30: 32-bit arithmetic
     uint64_t A = 0;
@@ -551,6 +573,11 @@ __device__ bool eval_tile(const SweepArgs& a, int item, unsigned char* smem, uin
         sm += m;
         if (SMALL) A32 += __umul24(m, C);
         else A += (uint64_t)m * C;
+        if (CD && bit_get_u<NW>(xm, s)) {
+          xmaxC = max(xmaxC, C);
+          xsm += m;
+          xA += (uint64_t)m * C;
+        }
       }
     }
     // Eqs. 6-7: parallel nodes (released, outside the group) take the S spare
@@ -609,6 +636,13 @@ __device__ bool eval_tile(const SweepArgs& a, int item, unsigned char* smem, uin
         csg = sg;
         cleft = cc - (uint32_t)cap;
       }
+      if (CD && bit_get<NW>(xm, cur)) {
+        // launched whole (C = ceil(load / m)) or as a segment (C = maxC)
+        const uint32_t Cp = fits ? ceil_div<SMALL>(cc, mc) : maxC;
+        xmaxC = max(xmaxC, Cp);
+        xsm += mc;
+        xA += (uint64_t)mc * Cp;
+      }
       if (TP) {
         T -= fits ? ceil_div<SMALL>(cc, mc) : 0u;
         go = fits && T != 0 && cn >= 0;
@@ -646,6 +680,12 @@ __device__ bool eval_tile(const SweepArgs& a, int item, unsigned char* smem, uin
       if (sm > M) R += SMALL ? (uint64_t)((A32 - maxC) / M) : (A - maxC) / M;
       bound += R;
       cp += maxC;
+      if (CD) {
+        uint64_t xR = xmaxC;
+        if (xsm > M) xR += (xA - xmaxC) / M;
+        xbound += xR;
+        xcp += xmaxC;
+      }
     }
     // Finished now: the unfinished members and the nodes launched whole.
     uint64_t Dn[NW], gone[NW], Fu[NW];
@@ -753,13 +793,17 @@ __device__ bool eval_tile(const SweepArgs& a, int item, unsigned char* smem, uin
     k = kend;
   }
 
+  if (CD) {
+    bound = xbound;
+    cp = xcp;
+  }
   if (active) {
     const int64_t o = (int64_t)d * a.K + slot;
     if (a.bounds) a.bounds[o] = (int64_t)bound;
     if (a.cp) a.cp[o] = (int64_t)cp;
     if (a.intf) a.intf[o] = (int64_t)(bound - cp);
   }
-  if (a.best) {
+  if (a.best && !CD) {
     unsigned long long key = active ? ((bound << BEST_SHIFT) | (uint64_t)slot) : ~0ull;
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
@@ -774,16 +818,16 @@ __device__ bool eval_tile(const SweepArgs& a, int item, unsigned char* smem, uin
 // First pass: one tile per workgroup, residual table in LDS.  A tile that
 // overflows it restarts at once with one of the global-memory tables, or,
 // when all are taken, is listed for the second pass.
-template <int NW, bool SMALL, bool RS, bool TP>
+template <int NW, bool SMALL, bool RS, int LM>
 __device__ void first_pass_tile(const SweepArgs& a, int item, unsigned char* smem, uint32_t* counters,
                                 uint32_t* list, uint64_t* grows) {
-  if (eval_tile<NW, false, SMALL, RS, TP>(a, item, smem, nullptr, grows)) {
+  if (eval_tile<NW, false, SMALL, RS, LM>(a, item, smem, nullptr, grows)) {
     uint32_t g = 0;
     if (threadIdx.x == 0) g = atomicAdd(&counters[1], 1u);
     g = __shfl(g, 0);
     __syncthreads();
     if (g < (uint32_t)GLOBAL_PASS_GRID) {
-      eval_tile<NW, true, SMALL, RS, TP>(a, item, smem, a.gres + (size_t)g * (size_t)a.max_n * WAVE, grows);
+      eval_tile<NW, true, SMALL, RS, LM>(a, item, smem, a.gres + (size_t)g * (size_t)a.max_n * WAVE, grows);
     } else if (threadIdx.x == 0) {
       list[atomicAdd(&counters[0], 1u)] = (uint32_t)item;
     }
@@ -796,13 +840,13 @@ __device__ inline uint64_t* rows_of(const SweepArgs& a, int slot) {
   return a.grows ? a.grows + (size_t)slot * row_region_words(a.max_n, NW, RS) : nullptr;
 }
 
-template <int NW, bool SMALL, bool RS, bool TP>
+template <int NW, bool SMALL, bool RS, int LM>
 __global__ __launch_bounds__(64) void k_eval(SweepArgs a, uint32_t* counters, uint32_t* list) {
   extern __shared__ __align__(16) unsigned char smem[];
   // rows in global memory run the persistent form only (their row regions
   // are per running workgroup)
   if constexpr (!RowsInGlobal<NW, RS>::value)
-    first_pass_tile<NW, SMALL, RS, TP>(a, blockIdx.x, smem, counters, list, nullptr);
+    first_pass_tile<NW, SMALL, RS, LM>(a, blockIdx.x, smem, counters, list, nullptr);
 }
 
 // Persistent form of the first pass: as many workgroups as fit on the device
@@ -810,7 +854,7 @@ __global__ __launch_bounds__(64) void k_eval(SweepArgs a, uint32_t* counters, ui
 // Every workgroup leaves the loop when the counter passes `total`.
 // At least two waves per SIMD: the eight-word-row class would otherwise take
 // one (a few spilled registers cost less than the lost latency hiding).
-template <int NW, bool SMALL, bool RS, bool TP>
+template <int NW, bool SMALL, bool RS, int LM>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_eval_persistent(SweepArgs a, uint32_t* counters, uint32_t* list,
                                                         int total) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -820,14 +864,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
     if (threadIdx.x == 0) item = atomicAdd(&counters[2], 1u);
     item = __shfl(item, 0);
     if (item >= (uint32_t)total) break;
-    first_pass_tile<NW, SMALL, RS, TP>(a, (int)item, smem, counters, list, grows);
+    first_pass_tile<NW, SMALL, RS, LM>(a, (int)item, smem, counters, list, grows);
     __syncthreads();
   }
 }
 
 // Second pass: the tiles the first pass listed (or every tile when
 // `direct`), residual tables in global memory sized to hold every node.
-template <int NW, bool SMALL, bool RS, bool TP>
+template <int NW, bool SMALL, bool RS, int LM>
 __global__ __launch_bounds__(64) void k_eval_global(SweepArgs a, const uint32_t* counters, const uint32_t* list,
                                                     int direct, int total) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -836,7 +880,7 @@ __global__ __launch_bounds__(64) void k_eval_global(SweepArgs a, const uint32_t*
   uint64_t* grows = rows_of<NW, RS>(a, blockIdx.x);
   for (int q = blockIdx.x; q < count; q += gridDim.x) {
     const int item = direct ? q : (int)list[q];
-    eval_tile<NW, true, SMALL, RS, TP>(a, item, smem, gres, grows);
+    eval_tile<NW, true, SMALL, RS, LM>(a, item, smem, gres, grows);
     __syncthreads();
   }
 }
@@ -858,7 +902,7 @@ __global__ void k_best_final(const unsigned long long* best, int32_t D, int32_t*
   }
 }
 
-template <int NW, bool SMALL, bool RS, bool TP>
+template <int NW, bool SMALL, bool RS, int LM>
 hipError_t launch_nw(const SweepArgs& a, uint32_t* counters, uint32_t* list, hipStream_t stream) {
   const int ntile = (a.K + WAVE - 1) / WAVE;
   const int total = a.list_len * ntile;
@@ -868,7 +912,7 @@ hipError_t launch_nw(const SweepArgs& a, uint32_t* counters, uint32_t* list, hip
   // rows in global memory need a row region per running workgroup: persistent only
   if (a.path != EVAL_PATH_GLOBAL && (a.persistent || GROWS)) {
     const size_t lds = lds_layout(a.max_n, NW, false, RS).total;
-    const void* fn = (const void*)k_eval_persistent<NW, SMALL, RS, TP>;
+    const void* fn = (const void*)k_eval_persistent<NW, SMALL, RS, LM>;
     e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     int per_cu = 0, dev = 0, cus = 0;
@@ -878,23 +922,23 @@ hipError_t launch_nw(const SweepArgs& a, uint32_t* counters, uint32_t* list, hip
     if (e != hipSuccess) return e;
     int grid = max(1, min(total, max(1, per_cu) * max(1, cus)));
     if (GROWS) grid = min(grid, ROW_REGIONS);
-    hipLaunchKernelGGL((k_eval_persistent<NW, SMALL, RS, TP>), dim3(grid), dim3(WAVE), lds, stream, a, counters, list,
+    hipLaunchKernelGGL((k_eval_persistent<NW, SMALL, RS, LM>), dim3(grid), dim3(WAVE), lds, stream, a, counters, list,
                        total);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   } else if (a.path != EVAL_PATH_GLOBAL) {
     const size_t lds = lds_layout(a.max_n, NW, false, RS).total;
-    e = hipFuncSetAttribute((const void*)k_eval<NW, SMALL, RS, TP>,
+    e = hipFuncSetAttribute((const void*)k_eval<NW, SMALL, RS, LM>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_eval<NW, SMALL, RS, TP>), dim3(total), dim3(WAVE), lds, stream, a, counters, list);
+    hipLaunchKernelGGL((k_eval<NW, SMALL, RS, LM>), dim3(total), dim3(WAVE), lds, stream, a, counters, list);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   const size_t lds = lds_layout(a.max_n, NW, true, RS).total;
-  e = hipFuncSetAttribute((const void*)k_eval_global<NW, SMALL, RS, TP>,
+  e = hipFuncSetAttribute((const void*)k_eval_global<NW, SMALL, RS, LM>,
                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   const int grid = a.path == EVAL_PATH_GLOBAL ? min(total, GLOBAL_PASS_GRID) : GLOBAL_PASS_GRID;
-  hipLaunchKernelGGL((k_eval_global<NW, SMALL, RS, TP>), dim3(grid), dim3(WAVE), lds, stream, a, counters, list,
+  hipLaunchKernelGGL((k_eval_global<NW, SMALL, RS, LM>), dim3(grid), dim3(WAVE), lds, stream, a, counters, list,
                      a.path == EVAL_PATH_GLOBAL ? 1 : 0, total);
   return hipGetLastError();
 }
@@ -902,13 +946,13 @@ hipError_t launch_nw(const SweepArgs& a, uint32_t* counters, uint32_t* list, hip
 // The candidate bytes of DAGs above 128 nodes stay out of LDS (seeded ones
 // drawn where they are used, explicit ones read from device memory), which
 // keeps several wavefronts per compute unit; smaller DAGs keep them in LDS.
-template <bool SMALL, bool TP>
+template <bool SMALL, int LM>
 hipError_t launch_class_tp(int cls, const SweepArgs& a, uint32_t* counters, uint32_t* list, hipStream_t stream) {
   switch (cls) {
-    case 0: return launch_nw<1, SMALL, false, TP>(a, counters, list, stream);
-    case 1: return launch_nw<2, SMALL, false, TP>(a, counters, list, stream);
-    case 2: return launch_nw<4, SMALL, true, TP>(a, counters, list, stream);
-    default: return launch_nw<8, SMALL, true, TP>(a, counters, list, stream);
+    case 0: return launch_nw<1, SMALL, false, LM>(a, counters, list, stream);
+    case 1: return launch_nw<2, SMALL, false, LM>(a, counters, list, stream);
+    case 2: return launch_nw<4, SMALL, true, LM>(a, counters, list, stream);
+    default: return launch_nw<8, SMALL, true, LM>(a, counters, list, stream);
   }
 }
 
@@ -916,8 +960,9 @@ hipError_t launch_class_tp(int cls, const SweepArgs& a, uint32_t* counters, uint
 // spatial one keeps its code and registers.
 template <bool SMALL>
 hipError_t launch_class(int cls, const SweepArgs& a, uint32_t* counters, uint32_t* list, hipStream_t stream) {
-  return a.temporal ? launch_class_tp<SMALL, true>(cls, a, counters, list, stream)
-                    : launch_class_tp<SMALL, false>(cls, a, counters, list, stream);
+  if (a.cond_tab) return launch_class_tp<SMALL, 2>(cls, a, counters, list, stream);
+  return a.temporal ? launch_class_tp<SMALL, 1>(cls, a, counters, list, stream)
+                    : launch_class_tp<SMALL, 0>(cls, a, counters, list, stream);
 }
 
 }  // namespace
@@ -1027,6 +1072,45 @@ hipError_t launch_check_list(const int32_t* list, int64_t n, int32_t K, uint32_t
     const int64_t blocks = (n + 255) / 256 < 4096 ? (n + 255) / 256 : 4096;
     hipLaunchKernelGGL(k_check_list, dim3((unsigned)blocks), dim3(256), 0, stream, list, n, K, bad);
   }
+  return hipGetLastError();
+}
+
+namespace {
+__global__ void k_cond_reduce(const int64_t* rb, const int32_t* R, int32_t D, int32_t K, int32_t Rmax,
+                              int64_t* bounds, int32_t* worst) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)D * K) return;
+  const int d = (int)(i / K);
+  const int64_t* x = rb + i * Rmax;
+  int64_t best = -1;
+  int32_t arg = 0;
+  for (int r = 0; r < R[d]; r++)
+    if (x[r] > best) { best = x[r]; arg = r; }
+  bounds[i] = best < 0 ? 0 : best;
+  if (worst) worst[i] = arg;
+}
+}  // namespace
+
+namespace {
+__global__ void k_cond_list(int32_t* list, int64_t n, int64_t L, int32_t Rmax) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    list[i] = (int32_t)((i % L) / Rmax);
+}
+}  // namespace
+
+hipError_t launch_cond_list(int32_t* list, int64_t n, int64_t L, int32_t Rmax, hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  const int64_t blocks = (n + 255) / 256 < 8192 ? (n + 255) / 256 : 8192;
+  hipLaunchKernelGGL(k_cond_list, dim3((unsigned)blocks), dim3(256), 0, stream, list, n, L, Rmax);
+  return hipGetLastError();
+}
+
+hipError_t launch_cond_reduce(const int64_t* rb, const int32_t* R, int32_t D, int32_t K, int32_t Rmax,
+                              int64_t* bounds, int32_t* worst, hipStream_t stream) {
+  const int64_t n = (int64_t)D * K;
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_cond_reduce, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, rb, R, D, K, Rmax, bounds,
+                     worst);
   return hipGetLastError();
 }
 

@@ -32,7 +32,8 @@ MODEL_PARAMS = 100356
 # Every symbol include/dagbound.h declares.
 EXPORTS = (
     "dagbound_create_batch", "dagbound_set_allocations", "dagbound_eval_bounds",
-    "dagbound_best_allocation", "dagbound_best_allocation_static", "dagbound_eval_listed", "dagbound_get_division", "dagbound_get_schedule", "dagbound_baselines", "dagbound_run_schedule",
+    "dagbound_best_allocation", "dagbound_best_allocation_static", "dagbound_eval_listed",
+    "dagbound_eval_conditional", "dagbound_get_division", "dagbound_get_schedule", "dagbound_baselines", "dagbound_run_schedule",
     "dagbound_set_para_launch",
     "dagbound_set_tuning",
     "dagbound_destroy_batch", "dagbound_model_create", "dagbound_model_destroy",
@@ -85,6 +86,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.dagbound_eval_bounds.argtypes = [P, P, P, P, U32, P]
     lib.dagbound_eval_listed.restype = I32
     lib.dagbound_eval_listed.argtypes = [P, I32, P, P, P, P, U32, P]
+    lib.dagbound_eval_conditional.restype = I32
+    lib.dagbound_eval_conditional.argtypes = [P, P, P, P, P, U32, P]
     lib.dagbound_model_save.restype = I32
     lib.dagbound_model_save.argtypes = [P, ctypes.c_char_p]
     lib.dagbound_model_load.restype = I32
@@ -322,6 +325,17 @@ def best_allocation(batch: Batch, best_idx, best_bound, search: int = SEARCH_EXH
     mh = ctypes.c_void_p(model.handle) if model is not None else None
     _check(lib.dagbound_best_allocation(ctypes.c_void_p(batch.handle), int(search), int(top_k),
                                         mh, p_i, p_b, kind, _stream_ptr(stream, keep)))
+
+
+def eval_conditional(batch: Batch, cond_of, branch_of, bounds, worst=None, stream=None) -> None:
+    """dagbound_eval_conditional: bounds[d*K + c] the largest realization
+    bound of conditional DAG d under candidate c (and the first realization
+    reaching it in worst)."""
+    lib = load_library()
+    (pc, pb, po, pw), kind, keep = _marshal([(cond_of, "int32"), (branch_of, "int32"), (bounds, "int64"),
+                                             (worst, "int32")])
+    _check(lib.dagbound_eval_conditional(ctypes.c_void_p(batch.handle), pc, pb, po, pw, kind,
+                                         _stream_ptr(stream, keep)))
 
 
 def best_allocation_static(batch: Batch, model, top_k: int, best_idx, best_bound, stream=None) -> None:
