@@ -19,7 +19,9 @@
 //     LDS; the slot of a node is its rank within the segmented set).  A tile
 //     whose table would overflow is handed to a second pass of the same code
 //     whose table lives in global memory and holds every node;
-//   - candidate bytes: [node][lane] bytes in LDS.
+//   - candidate bytes: explicit ones read from the lane's own row in device
+//     memory where they are used; seeded ones drawn from the counter hash
+//     (into LDS as [node][lane] bytes for DAGs of up to 128 nodes).
 // Releases use per-candidate counters of unfinished predecessors, packed in
 // LDS dwords [node][lane].  All arithmetic is integer.
 #include "internal.h"
@@ -220,13 +222,13 @@ template <int NW, bool RS> struct RowsInGlobal { static constexpr bool value = N
 template <int NW, bool RS> struct RowsInRegs {
   static constexpr bool value = NW <= 4 && !RowsInGlobal<NW, RS>::value;
 };
-// Eight-word rows keep the residual-slot map in the row region too (after
-// the two row blocks): 16 KB of LDS less per wavefront at 512 nodes.
-template <int NW, bool RS> struct MapInGlobal { static constexpr bool value = NW == 8 && RS; };
+// Rows in the row region keep the residual-slot map there too (after the
+// two row blocks): 16 KB of LDS less per wavefront at 512 nodes, 8 KB at 256.
+template <int NW, bool RS> struct MapInGlobal { static constexpr bool value = NW >= 4 && RS; };
 // 64-bit words of one workgroup's row region (two row blocks, and the map
 // where it lives there) for DAGs of up to max_n nodes.
 __host__ __device__ inline size_t row_region_words(int max_n, int nw, bool rs) {
-  return 2 * (size_t)max_n * nw + (nw == 8 && rs ? 4 * ((size_t)max_n + 7) : 0);
+  return 2 * (size_t)max_n * nw + (nw >= 4 && rs ? 4 * ((size_t)max_n + 7) : 0);
 }
 
 // LDS layout of one wavefront (bytes), for the batch's largest DAG.
@@ -254,11 +256,14 @@ __host__ __device__ inline Lds lds_layout(int maxn, int nw, bool big, bool rs) {
     static_assert(RES_SLOTS * WAVE * 4 >= 2 * 512 * 2, "id tables fit in the residual table");
   }
   l.r = o;    o += rs ? 0 : (size_t)maxn * WAVE;  // candidate bytes [sigma][lane] (none when drawn on the fly)
-  l.map = o;  o += (big || (nw == 8 && rs)) ? 0 : (size_t)((maxn + 7) / 8) * WAVE * 4;  // residual slot of a node, 4 bits
+  l.map = o;  o += (big || (nw >= 4 && rs)) ? 0 : (size_t)((maxn + 7) / 8) * WAVE * 4;  // residual slot of a node, 4 bits
   if (regs) {
-    // built in the candidate-byte region before the bytes are loaded
-    l.pb = l.r;
-    l.sb = l.r + (size_t)maxn * nw * 8;
+    // built in the candidate-byte region (or, without bytes in LDS, in the
+    // residual-slot map's) before that region is first written
+    const size_t base = rs ? l.map : l.r;
+    l.pb = base;
+    l.sb = base + (size_t)maxn * nw * 8;
+    if (base + 2 * (size_t)maxn * nw * 8 > o) o = base + 2 * (size_t)maxn * nw * 8;
   } else if (grows) {
     l.pb = l.sb = 0;  // in global memory
   } else {
@@ -943,14 +948,17 @@ hipError_t launch_nw(const SweepArgs& a, uint32_t* counters, uint32_t* list, hip
   return hipGetLastError();
 }
 
-// The candidate bytes of DAGs above 128 nodes stay out of LDS (seeded ones
-// drawn where they are used, explicit ones read from device memory), which
-// keeps several wavefronts per compute unit; smaller DAGs keep them in LDS.
+// Explicit candidate bytes stay out of LDS (each lane reads its row from
+// device memory one use ahead), which keeps more wavefronts per compute
+// unit; seeded bytes of DAGs above 128 nodes are drawn where they are used,
+// smaller DAGs' seeded bytes are drawn once into LDS.
 template <bool SMALL, int LM>
 hipError_t launch_class_tp(int cls, const SweepArgs& a, uint32_t* counters, uint32_t* list, hipStream_t stream) {
   switch (cls) {
-    case 0: return launch_nw<1, SMALL, false, LM>(a, counters, list, stream);
-    case 1: return launch_nw<2, SMALL, false, LM>(a, counters, list, stream);
+    case 0: return a.alloc ? launch_nw<1, SMALL, true, LM>(a, counters, list, stream)
+                           : launch_nw<1, SMALL, false, LM>(a, counters, list, stream);
+    case 1: return a.alloc ? launch_nw<2, SMALL, true, LM>(a, counters, list, stream)
+                           : launch_nw<2, SMALL, false, LM>(a, counters, list, stream);
     case 2: return launch_nw<4, SMALL, true, LM>(a, counters, list, stream);
     default: return launch_nw<8, SMALL, true, LM>(a, counters, list, stream);
   }
