@@ -194,7 +194,8 @@ struct dagbound_batch {
   uint64_t tune_gen = 0;
   float plan_ms[8] = {};               // last autotune: (node lanes from 257 nodes, persistent, class_streams) = (l, p, s) at 4l + 2p + s
   size_t gres_off[NUM_CLASSES] = {};
-  uint64_t* grows = nullptr;           // row regions for DAGs of 129-512 nodes
+  uint64_t* grows = nullptr;           // residual-slot map regions for DAGs of 129-512 nodes
+  int32_t adj_uniform_nw = 0;          // the adjacency rows' words: 0 per size class, else this for every DAG
   size_t rows_off[NUM_CLASSES + 1] = {};
   hipEvent_t ev[NUM_CLASSES + 1] = {};  // fork, joins
   // per-allocation-set scratch: tiles handed to the global pass
@@ -354,7 +355,25 @@ hipError_t plan_resources(dagbound_batch* b, SweepStreams* ss) {
 
 // One evaluation launch of a batch: the size classes on the device's side
 // streams when there is more than one class to run.
+// Words of a bitset row of a DAG of n <= 512 nodes.
+int row_words(int64_t n) { return n <= 64 ? 1 : n <= 128 ? 2 : n <= 256 ? 4 : 8; }
+
+// The adjacency rows in the layout the next launch reads: rows of each
+// size class's words, or, while the batch runs as one launch over DAGs of up
+// to 512 nodes, rows of the largest DAG's words for every DAG.  Rewritten
+// (on `st`) only when that layout changes.
+hipError_t ensure_adj(dagbound_batch* b, hipStream_t st) {
+  if (!b->t.adj) return hipSuccess;
+  const int want = !b->size_classes && b->max_n <= 512 ? row_words(b->max_n) : 0;
+  if (want == b->adj_uniform_nw) return hipSuccess;
+  const hipError_t e = launch_adj(b->t, b->order, b->class_off, b->class_max_n, want, st);
+  if (e == hipSuccess) b->adj_uniform_nw = want;
+  return e;
+}
+
 hipError_t run_sweep_plan(dagbound_batch* b, const SweepArgs& a, hipStream_t st) {
+  const hipError_t ea = ensure_adj(b, st);
+  if (ea != hipSuccess) return ea;
   int classes = 0;
   for (int c = 0; c < NUM_CLASSES; c++) classes += b->class_off[c + 1] > b->class_off[c];
   if (!a.order || !b->class_streams || classes < 2) return launch_sweep(a, st, nullptr);
@@ -479,7 +498,13 @@ dagbound_status dagbound_create_batch(int32_t num_dags, const int64_t* node_off,
   const int32_t n_records = b->class_off[LARGE_CLASS + 1] - b->class_off[3];
   const size_t gres_words = sweep_gres_words(b->class_max_n, b->class_off, (int32_t)max_n, b->gres_off);
   const size_t rows_words = sweep_rows_words(b->class_max_n, b->class_off, (int32_t)max_n, b->rows_off);
-  b->block_size = table_bytes(D, tn, te, gres_words, n_records > 0) + rows_words * 8 + 256;
+  // adjacency rows: 2 * (words of the largest DAG up to 512 nodes) per node
+  int32_t adj_max_n = 0;
+  for (int c = 0; c < LARGE_CLASS; c++)
+    if (b->class_off[c + 1] > b->class_off[c]) adj_max_n = std::max(adj_max_n, b->class_max_n[c]);
+  const int32_t adj_node = adj_max_n > 0 ? 2 * row_words(adj_max_n) : 0;
+  const size_t adj_words = (size_t)adj_node * (size_t)tn;
+  b->block_size = table_bytes(D, tn, te, gres_words, n_records > 0) + rows_words * 8 + adj_words * 8 + 512;
   hipError_t e = dev_alloc(&b->block, &b->block_size, device);
   if (e != hipSuccess) {
     delete b;
@@ -495,6 +520,8 @@ dagbound_status dagbound_create_batch(int32_t num_dags, const int64_t* node_off,
   b->err = cv.take<unsigned long long>(3);
   b->gres = cv.take<uint32_t>(gres_words);
   if (rows_words) b->grows = cv.take<uint64_t>(rows_words);
+  b->t.adj = adj_words ? cv.take<uint64_t>(adj_words) : nullptr;
+  b->t.adj_node = adj_node;
   b->t.wc = cv.take<uint32_t>(tn);
   b->t.soff = cv.take<uint32_t>(tn + D);
   b->t.ngroups = cv.take<int32_t>(D);
@@ -563,6 +590,9 @@ dagbound_status dagbound_create_batch(int32_t num_dags, const int64_t* node_off,
     e = launch_prep(b->t, in, num_dags, num_cus, (int32_t)max_n, b->order, b->class_off, b->err, lscratch,
                     b->class_max_n, class_max_e, fork_ok ? side : nullptr, fork_ok ? b->ev[0] : nullptr,
                     fork_ok ? b->ev + 1 : nullptr, st);
+  // adjacency rows of each size class (they read the successor lists
+  // clamped to each DAG's ranges: safe before the validation below)
+  if (e == hipSuccess && b->t.adj) e = launch_adj(b->t, b->order, b->class_off, b->class_max_n, 0, st);
   unsigned long long errw[2] = {~0ull, 0};
   if (e == hipSuccess) e = hipMemcpyAsync(errw, b->err, sizeof errw, hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
@@ -699,6 +729,7 @@ dagbound_status dagbound_eval_bounds(dagbound_batch* b, int64_t* bounds, int64_t
       SweepStreams ss;
       e = plan_resources(b, &ss);
       hipGraph_t graph = nullptr;
+      if (e == hipSuccess) e = ensure_adj(b, st);  // outside the graph
       if (e == hipSuccess) e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
       if (e == hipSuccess) {
         const hipError_t el = run_sweep_plan(b, a, st);
@@ -1697,7 +1728,8 @@ extern "C" dagbound_status dagbound_best_allocation_static(dagbound_batch* b, co
     a.best = b->best;
     // the size classes one after another on the caller's stream (no side
     // streams or events to create)
-    e = launch_sweep(a, st, nullptr);
+    e = ensure_adj(b, st);
+    if (e == hipSuccess) e = launch_sweep(a, st, nullptr);
     b->best_gen = ~0ull;  // the per-DAG minimum now holds list positions
   }
   if (e == hipSuccess) e = launch_best_final(b->best, b->D, best_idx, best_bound, cand, kk, st);

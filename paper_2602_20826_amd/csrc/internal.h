@@ -29,6 +29,12 @@ struct Tables {
   // first successor (offset in the DAG's succ), local id | out-degree << 16}.
   uint4* nrec;              // [T_N] by sigma rank (last = 0)
   uint4* mrec;              // [T_N] in group order (last marks a group's last member)
+  // Adjacency rows of the DAGs of up to 512 nodes: N_d predecessor bitsets,
+  // then N_d successor bitsets, by sigma rank, nw 64-bit words each (nw of
+  // the DAG's size class, or of the batch's largest DAG while the batch runs
+  // as one launch), DAG d's from adj + adj_node * node_off[d].
+  uint64_t* adj;            // [adj_node * T_N]
+  int32_t adj_node;         // words per node: 2 * nw of the largest DAG up to 512 nodes
 };
 
 struct PrepInputs {
@@ -93,10 +99,10 @@ constexpr int RES_SLOTS = 12;
 // that overflows its LDS table takes one and finishes at once; the second
 // pass (one workgroup per table) takes the tiles left when all are taken.
 constexpr int GLOBAL_PASS_GRID = 256;
-// Global row regions for bitsets kept in global memory: one per workgroup
-// of the persistent first pass (at most this many) and of the second pass;
-// enough that the persistent grid reaches the occupancy limit (about 5
-// wavefronts per CU for eight-word rows, 10 for four-word rows).
+// Global-memory regions for the residual-slot maps of DAGs of 129-512 nodes:
+// one per workgroup of the persistent first pass (at most this many) and of
+// the second pass; enough that the persistent grid reaches the occupancy
+// limit.
 constexpr int ROW_REGIONS = 4096;
 enum : int32_t { EVAL_PATH_AUTO = 0, EVAL_PATH_GLOBAL = 1 };
 
@@ -138,9 +144,9 @@ struct SweepArgs {
                                 // tables of class_max_n[c] * 64 words from gres + gres_off[c];
                                 // the large class owns LARGE_SLOTS regions of class_max_n words
   size_t gres_off[NUM_CLASSES]; // host: word offset of each class's tables
-  uint64_t* grows;              // row regions (predecessor and successor rows kept in global memory):
-                                // class c owns ROW_REGIONS regions of 2 * class_max_n[c] * NW words
-                                // from grows + rows_off[c]; rows_off[NUM_CLASSES] is the one-launch pool
+  uint64_t* grows;              // map regions (residual-slot maps kept in global memory): class c
+                                // owns ROW_REGIONS regions of 4 * (class_max_n[c] + 7) words from
+                                // grows + rows_off[c]; rows_off[NUM_CLASSES] is the one-launch pool
   size_t rows_off[NUM_CLASSES + 1];
   int32_t max_n, max_e;
   const int32_t* cand_list;     // [D][K] candidate ids to evaluate, or nullptr (ids 0..K-1)
@@ -157,6 +163,14 @@ struct SweepArgs {
   const uint32_t* cond_tab;
   int32_t cond_R;
 };
+// Writes the adjacency rows (Tables::adj) of the DAGs of classes 0-3, each
+// class's DAGs with rows of the class's words, or with `uniform_nw` words
+// when it is nonzero (the one-launch mode).  Reads only soff/succ, clamped
+// to each DAG's own ranges, so a batch that failed validation cannot make
+// it read out of bounds.
+hipError_t launch_adj(const Tables& t, const int32_t* order, const int32_t class_off[NUM_CLASSES + 1],
+                      const int32_t class_max_n[NUM_CLASSES], int uniform_nw, hipStream_t stream);
+
 // Largest number of realizations of one conditional DAG.
 constexpr int COND_MAX_REALIZATIONS = 4096;
 // bounds[d * K + c] = max over rho < R[d] of rb[(d * K + c) * Rmax + rho];
@@ -188,7 +202,7 @@ struct SweepStreams {
   hipEvent_t join[NUM_CLASSES];
 };
 
-// Words of row regions a batch needs, and each pool's offset.
+// Words of map regions a batch needs, and each pool's offset.
 size_t sweep_rows_words(const int32_t class_max_n[NUM_CLASSES], const int32_t class_off[NUM_CLASSES + 1],
                         int32_t max_n, size_t rows_off[NUM_CLASSES + 1]);
 

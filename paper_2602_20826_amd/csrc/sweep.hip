@@ -163,6 +163,10 @@ __device__ inline int bit_count(const uint64_t (&b)[NW]) {
 }
 
 __device__ inline uint32_t uni(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ inline uint64_t readlane64(uint64_t x, int l) {
+  return ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(x >> 32), l) << 32) |
+         (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, l);
+}
 
 // ceil(a / b) for 1 <= a < 2^20 and 1 <= b < 2^16, exactly: with a - 1 =
 // q b + r, (a - 1/2) / b lies in [q + 1/(2b), q + 1 - 1/(2b)], and the
@@ -211,33 +215,22 @@ __device__ inline uint64_t wave_or64(uint64_t x) {
   return ((uint64_t)wave_or32((uint32_t)(x >> 32)) << 32) | wave_or32((uint32_t)x);
 }
 
-// Predecessor and successor bitsets of the DAG's nodes live in registers
-// (lane x holds the rows of nodes x, 64 + x, ...) while they are small, and
-// in LDS above that.
-// Eight-word rows (DAGs of 257-512 nodes), and four-word rows when the
-// candidate bytes are drawn on the fly (RS), live in a global-memory region
-// of the workgroup instead of LDS, which keeps the workgroup's LDS small
-// enough for several waves per compute unit.
-template <int NW, bool RS> struct RowsInGlobal { static constexpr bool value = NW == 8 || (NW == 4 && RS); };
-template <int NW, bool RS> struct RowsInRegs {
-  static constexpr bool value = NW <= 4 && !RowsInGlobal<NW, RS>::value;
-};
-// Rows in the row region keep the residual-slot map there too (after the
-// two row blocks): 16 KB of LDS less per wavefront at 512 nodes, 8 KB at 256.
+// With the candidate bytes out of LDS (RS), the residual-slot map of DAGs
+// above 128 nodes lives in a global-memory region of the workgroup instead
+// of LDS, which keeps the workgroup's LDS small enough for several waves per
+// compute unit.
 template <int NW, bool RS> struct MapInGlobal { static constexpr bool value = NW >= 4 && RS; };
-// 64-bit words of one workgroup's row region (two row blocks, and the map
-// where it lives there) for DAGs of up to max_n nodes.
+// 64-bit words of one workgroup's region (the map) for DAGs of up to max_n
+// nodes.
 __host__ __device__ inline size_t row_region_words(int max_n, int nw, bool rs) {
-  return 2 * (size_t)max_n * nw + (nw >= 4 && rs ? 4 * ((size_t)max_n + 7) : 0);
+  return nw >= 4 && rs ? 4 * ((size_t)max_n + 7) : 0;
 }
 
 // LDS layout of one wavefront (bytes), for the batch's largest DAG.
 struct Lds {
-  size_t mem, node, ppv, inv, pb, sb, res, r, map, total;
+  size_t mem, node, ppv, inv, res, r, map, stage, total;
 };
 __host__ __device__ inline Lds lds_layout(int maxn, int nw, bool big, bool rs) {
-  const bool grows = nw == 8 || (nw == 4 && rs);
-  const bool regs = nw <= 4 && !grows;
   Lds l;
   size_t o = 0;
   l.mem = o;  o += (size_t)maxn * 8;            // members in group order
@@ -257,40 +250,11 @@ __host__ __device__ inline Lds lds_layout(int maxn, int nw, bool big, bool rs) {
   }
   l.r = o;    o += rs ? 0 : (size_t)maxn * WAVE;  // candidate bytes [sigma][lane] (none when drawn on the fly)
   l.map = o;  o += (big || (nw >= 4 && rs)) ? 0 : (size_t)((maxn + 7) / 8) * WAVE * 4;  // residual slot of a node, 4 bits
-  if (regs) {
-    // built in the candidate-byte region (or, without bytes in LDS, in the
-    // residual-slot map's) before that region is first written
-    const size_t base = rs ? l.map : l.r;
-    l.pb = base;
-    l.sb = base + (size_t)maxn * nw * 8;
-    if (base + 2 * (size_t)maxn * nw * 8 > o) o = base + 2 * (size_t)maxn * nw * 8;
-  } else if (grows) {
-    l.pb = l.sb = 0;  // in global memory
-  } else {
-    l.pb = o; o += (size_t)maxn * nw * 8;       // predecessor bitsets by sigma rank
-    l.sb = o; o += (size_t)maxn * nw * 8;       // successor bitsets by sigma rank
-  }
+  o = (o + 15) & ~(size_t)15;
+  l.stage = o; o += nw <= 2 ? 0 : (size_t)WAVE * nw * 8;  // predecessor rows of release candidates [lane][nw]
+                                                          // (rows of DAGs up to 128 nodes stay in registers)
   l.total = (o + 15) & ~(size_t)15;
   return l;
-}
-
-template <int NW>
-__device__ inline void load_row(uint64_t (&b)[NW], const uint64_t* row) {
-  if constexpr (NW == 1) {
-    b[0] = row[0];
-  } else {
-#pragma unroll
-    for (int k = 0; k < NW; k += 2) {
-      const ulonglong2 q = *(const ulonglong2*)(row + k);
-      b[k] = q.x;
-      b[k + 1] = q.y;
-    }
-  }
-}
-
-__device__ inline uint64_t readlane64(uint64_t x, int l) {
-  return ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(x >> 32), l) << 32) |
-         (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, l);
 }
 
 // Eq. 5's half-up share for loads below 2^20: W < 2^29 then, and a float
@@ -316,8 +280,6 @@ template <int NW, bool BIG, bool SMALL, bool RS, int LM>
 __device__ bool eval_tile(const SweepArgs& a, int item, unsigned char* smem, uint32_t* gres, uint64_t* grows) {
   constexpr bool TP = LM == 1;
   constexpr bool CD = LM == 2;
-  constexpr bool REG = RowsInRegs<NW, RS>::value;
-  constexpr bool GROWS = RowsInGlobal<NW, RS>::value;
   const int ntile = (a.K + WAVE - 1) / WAVE;
   const int li = item / ntile;
   const int tile = item - li * ntile;
@@ -328,25 +290,22 @@ __device__ bool eval_tile(const SweepArgs& a, int item, unsigned char* smem, uin
   const int c = a.cand_list ? (active ? a.cand_list[(int64_t)d * a.K + slot] : 0) : slot;  // candidate id
   const int64_t n0 = a.t.node_off[d];
   const int N = (int)uni((uint32_t)(a.t.node_off[d + 1] - n0));
-  const int64_t e0 = a.t.edge_off[d];
   const uint32_t M = (uint32_t)a.M;
+  const bool mpow2 = (M & (M - 1u)) == 0u;  // division by M as a shift
+  const uint32_t msh = (uint32_t)__builtin_ctz(M);
   const Lds L = lds_layout(a.max_n, NW, BIG, RS);
   uint2* s_mem = (uint2*)(smem + L.mem);       // {C_hat, pp | s << 16 | last << 31}
   uint2* s_node = (uint2*)(smem + L.node);     // {C_hat, pp | local id << 16} by sigma rank
   uint16_t* s_ppv = (uint16_t*)(smem + L.ppv); // [local id]
   uint16_t* s_inv = (uint16_t*)(smem + L.inv); // [local id]
-  uint64_t* s_pb = GROWS ? grows : (uint64_t*)(smem + L.pb);  // [sigma][NW]
-  uint64_t* s_sb = GROWS ? grows + (size_t)a.max_n * NW : (uint64_t*)(smem + L.sb);  // [sigma][NW]
   uint32_t* res = BIG ? gres : (uint32_t*)(smem + L.res);  // [slot][lane], or [sigma][lane] when BIG
   uint8_t* s_r = smem + L.r;                   // [sigma][lane]
-  uint32_t* s_map = MapInGlobal<NW, RS>::value ? (uint32_t*)(grows + 2 * (size_t)a.max_n * NW)
+  uint32_t* s_map = MapInGlobal<NW, RS>::value ? (uint32_t*)grows
                                                : (uint32_t*)(smem + L.map); // [sigma / 8][lane], 4 bits per node: slot + 1
 
   // ---- DAG tables (shared by the 64 candidates)
   for (int s = lane; s < N; s += WAVE) s_node[s] = make_uint2(a.t.wc[n0 + s], a.t.pp[n0 + s]);
   for (int v = lane; v < N; v += WAVE) s_inv[v] = a.t.inv[n0 + v];
-  for (int i = lane; i < N * NW; i += WAVE) { s_pb[i] = 0; s_sb[i] = 0; }
-  if (GROWS) __threadfence_block();
   __syncthreads();
   for (int v = lane; v < N; v += WAVE) {
     const int s = s_inv[v];
@@ -354,21 +313,6 @@ __device__ bool eval_tile(const SweepArgs& a, int item, unsigned char* smem, uin
     s_ppv[v] = (uint16_t)y;
     s_node[s].y = y | ((uint32_t)v << 16);
   }
-  // successor bitset of x (this lane's row) and predecessor bits of its successors
-  for (int x = lane; x < N; x += WAVE) {
-    uint64_t row[NW];
-#pragma unroll
-    for (int w = 0; w < NW; w++) row[w] = 0;
-    const uint32_t ea = a.t.soff[n0 + d + x], eb = a.t.soff[n0 + d + x + 1];
-    for (uint32_t e = ea; e < eb; e++) {
-      const int u = a.t.succ[e0 + e];
-      bit_set<NW>(row, u);
-      atomicOr((unsigned long long*)&s_pb[u * NW + (x >> 6)], 1ull << (x & 63));
-    }
-#pragma unroll
-    for (int w = 0; w < NW; w++) s_sb[x * NW + w] = row[w];
-  }
-  if (GROWS) __threadfence_block();
   for (int k = lane; k < N; k += WAVE) {
     const uint32_t g = a.t.gl[n0 + k];
     const int s = g & 0x7FFF;
@@ -376,32 +320,30 @@ __device__ bool eval_tile(const SweepArgs& a, int item, unsigned char* smem, uin
     s_mem[k] = make_uint2(nd.x, (nd.y & 0xFFFFu) | ((uint32_t)s << 16) | ((g & 0x8000u) << 16));
   }
   __syncthreads();
-  // released: the sources; finished: none.  With REG, lane x keeps the rows
-  // of nodes w * 64 + x.
+  // Predecessor and successor rows of the DAG's nodes (NW words each, by
+  // sigma rank) come from the batch's adjacency rows.
+  const uint64_t* prow_v = a.t.adj + (size_t)a.t.adj_node * (size_t)n0;
+  const uint64_t* srow_v = prow_v + (size_t)N * NW;
+  uint64_t* s_stage = (uint64_t*)(smem + L.stage);  // [lane][NW] rows of the release candidates
+  // released: the sources; finished: none.  Rows of DAGs up to 128 nodes
+  // stay in registers (REG): lane x keeps those of nodes w * 64 + x.
+  constexpr bool REG = NW <= 2;
   uint64_t rel[NW], fin[NW], seg[NW];
   uint64_t PB[REG ? NW : 1][REG ? NW : 1], SB[REG ? NW : 1][REG ? NW : 1];
 #pragma unroll
   for (int w = 0; w < NW; w++) {
     const int u = w * WAVE + lane;
-    uint64_t pr[NW], sr[NW];
-#pragma unroll
-    for (int k = 0; k < NW; k++) { pr[k] = 0; sr[k] = 0; }
-    if (u < N) {
-      load_row<NW>(pr, s_pb + u * NW);
-      if (REG) load_row<NW>(sr, s_sb + u * NW);
-    }
-    uint64_t any = 0;
-#pragma unroll
-    for (int k = 0; k < NW; k++) any |= pr[k];
-    rel[w] = __ballot(u < N && any == 0);
+    rel[w] = __ballot(u < N && a.t.indeg[n0 + u] == 0);
     fin[w] = 0;
     seg[w] = 0;
     if constexpr (REG) {
 #pragma unroll
-      for (int k = 0; k < NW; k++) { PB[w][k] = pr[k]; SB[w][k] = sr[k]; }
+      for (int k2 = 0; k2 < NW; k2++) {
+        PB[w][k2] = u < N ? prow_v[(size_t)u * NW + k2] : 0ull;
+        SB[w][k2] = u < N ? srow_v[(size_t)u * NW + k2] : 0ull;
+      }
     }
   }
-  if (REG) __syncthreads();  // the rows' LDS becomes the candidate bytes
   if (!BIG) {
     for (int i = 0; i < (N + 7) / 8; i++) s_map[i * WAVE + lane] = 0;
   }
@@ -634,12 +576,23 @@ __device__ bool eval_tile(const SweepArgs& a, int item, unsigned char* smem, uin
       if (!BIG) mw = s_map[(ci >> 3) * WAVE + lane];
       const uint32_t mx = min(ndc.y & 0xFFFFu, cc);
       const uint32_t mc = min(rcc ? min(rcc, mx) : mx, S);
-      const uint64_t cap = (uint64_t)(TP ? T : maxC) * mc;
-      const bool fits = (uint64_t)cc <= cap;
+      // capacity (time left) * m; with loads below 2^20 and M below 2^12 the
+      // product stays below 2^32.  Below the load it is exact in 32 bits.
+      const uint32_t tl = TP ? T : maxC;
+      uint32_t cap32;
+      bool fits;
+      if (SMALL) {
+        cap32 = __umul24(tl, mc);
+        fits = cc <= cap32;
+      } else {
+        const uint64_t cap = (uint64_t)tl * mc;
+        fits = (uint64_t)cc <= cap;
+        cap32 = (uint32_t)cap;
+      }
       if (!fits) {
         cseg = cur;
         csg = sg;
-        cleft = cc - (uint32_t)cap;
+        cleft = cc - cap32;
       }
       if (CD && bit_get<NW>(xm, cur)) {
         // launched whole (C = ceil(load / m)) or as a segment (C = maxC)
@@ -682,7 +635,7 @@ __device__ bool eval_tile(const SweepArgs& a, int item, unsigned char* smem, uin
     // Lemma 1, plus the list-scheduling term if the members oversubscribe.
     if (W != 0) {
       uint64_t R = maxC;
-      if (sm > M) R += SMALL ? (uint64_t)((A32 - maxC) / M) : (A - maxC) / M;
+      if (sm > M) R += SMALL ? (uint64_t)(mpow2 ? (A32 - maxC) >> msh : (A32 - maxC) / M) : (A - maxC) / M;
       bound += R;
       cp += maxC;
       if (CD) {
@@ -712,84 +665,74 @@ __device__ bool eval_tile(const SweepArgs& a, int item, unsigned char* smem, uin
     }
     // Releases: a successor of a node finished now (in some lane) is
     // released in the lanes where all its predecessors have finished.
-    // Lane-parallel over nodes (lane x takes node w * 64 + x): successor rows
-    // of the nodes finished now are OR-ed into the candidates, and nodes with
-    // a predecessor unfinished in every lane (outside FO, the nodes finished
-    // in some lane) are dropped from them.
-    uint64_t cand[NW];
+    // Lane-parallel over nodes (lane x takes node w * 64 + x): the successor
+    // rows of the nodes finished now are OR-ed into the candidates; the
+    // candidates' predecessor rows are read, and those with a predecessor
+    // unfinished in every lane (outside FO, the nodes finished in some lane)
+    // dropped; the rest go through LDS, from where every lane reads each
+    // candidate's row (one broadcast read) and tests it against its own
+    // finished set.
     {
-      uint64_t acc[NW], blocked[NW];
+      uint64_t acc[NW], cand[NW];
 #pragma unroll
       for (int k2 = 0; k2 < NW; k2++) {
         acc[k2] = 0;
         FO[k2] |= Fu[k2];
       }
-      if constexpr (REG) {
 #pragma unroll
-        for (int w = 0; w < NW; w++) {
-          uint64_t open = 0;
+      for (int w = 0; w < NW; w++) {
+        if ((Fu[w] >> lane) & 1) {
+          const uint64_t* r = srow_v + (size_t)(w * WAVE + lane) * NW;
 #pragma unroll
-          for (int k2 = 0; k2 < NW; k2++) open |= PB[w][k2] & ~FO[k2];
-          blocked[w] = __ballot(open != 0);
-          if ((Fu[w] >> lane) & 1) {
-#pragma unroll
-            for (int k2 = 0; k2 < NW; k2++) acc[k2] |= SB[w][k2];
-          }
+          for (int k2 = 0; k2 < NW; k2++) acc[k2] |= REG ? SB[w][k2] : r[k2];
         }
+      }
 #pragma unroll
-        for (int k2 = 0; k2 < NW; k2++) cand[k2] = (__ballot(acc[k2] != 0) ? wave_or64(acc[k2]) : 0ull) & ~blocked[k2];
-      } else {
-        // rows from LDS or the row region: successor rows of the finished
-        // nodes (lane-parallel), then, one word of candidates at a time, the
-        // predecessor rows of those candidates (lane-parallel, one load
-        // round trip per word), broadcast from the lane holding each row
+      for (int k2 = 0; k2 < NW; k2++) cand[k2] = __ballot(acc[k2] != 0) ? wave_or64(acc[k2]) : 0ull;
+      // A node found ready is added to rel even where it has finished
+      // already; rel is cut back to the unfinished nodes below.
 #pragma unroll
-        for (int w = 0; w < NW; w++) {
-          if ((Fu[w] >> lane) & 1) {
-            uint64_t sr[NW];
-            load_row<NW>(sr, s_sb + (w * WAVE + lane) * NW);
+      for (int w = 0; w < NW; w++) {
+        if (cand[w] == 0) continue;
+        uint64_t pr[NW];
 #pragma unroll
-            for (int k2 = 0; k2 < NW; k2++) acc[k2] |= sr[k2];
-          }
+        for (int k2 = 0; k2 < NW; k2++) pr[k2] = 0;
+        if ((cand[w] >> lane) & 1) {
+          const uint64_t* r = prow_v + (size_t)(w * WAVE + lane) * NW;
+#pragma unroll
+          for (int k2 = 0; k2 < NW; k2++) pr[k2] = REG ? PB[w][k2] : r[k2];
         }
+        uint64_t open = 0;
 #pragma unroll
-        for (int k2 = 0; k2 < NW; k2++) cand[k2] = __ballot(acc[k2] != 0) ? wave_or64(acc[k2]) : 0ull;
-#pragma unroll
-        for (int w = 0; w < NW; w++) {
-          if (cand[w] == 0) continue;
-          uint64_t pr[NW];
-#pragma unroll
-          for (int k2 = 0; k2 < NW; k2++) pr[k2] = 0;
-          if ((cand[w] >> lane) & 1) load_row<NW>(pr, s_pb + (w * WAVE + lane) * NW);
-          uint64_t open = 0;
-#pragma unroll
-          for (int k2 = 0; k2 < NW; k2++) open |= pr[k2] & ~FO[k2];
-          uint64_t cw = cand[w] & ~__ballot(open != 0);
+        for (int k2 = 0; k2 < NW; k2++) open |= pr[k2] & ~FO[k2];
+        uint64_t cw = cand[w] & ~__ballot(open != 0);
+        if (!cw) continue;
+        if constexpr (REG) {
+          // rows in registers: broadcast from the lane holding each
           while (cw) {
             const int ul = __builtin_ctzll(cw);
             cw &= cw - 1;
             uint64_t o = 0;
 #pragma unroll
-            for (int k2 = 0; k2 < NW; k2++) o |= readlane64(pr[k2], ul) & ~fin[k2];
+            for (int k2 = 0; k2 < NW; k2++) o |= readlane64(PB[w][k2], ul) & ~fin[k2];
             if (o == 0) rel[w] |= 1ull << ul;
           }
+          continue;
         }
-      }
-    }
-    // A node found ready is added to rel even where it has finished already;
-    // rel is cut back to the unfinished nodes after the walk.
-    if constexpr (REG) {
+        if ((cw >> lane) & 1) {
 #pragma unroll
-      for (int w = 0; w < NW; w++) {
-        uint64_t cw = cand[w];
+          for (int k2 = 0; k2 < NW; k2++) s_stage[lane * NW + k2] = pr[k2];
+        }
+        __builtin_amdgcn_wave_barrier();
         while (cw) {
           const int ul = __builtin_ctzll(cw);
           cw &= cw - 1;
-          uint64_t open = 0;
+          uint64_t o = 0;
 #pragma unroll
-          for (int k2 = 0; k2 < NW; k2++) open |= readlane64(PB[w][k2], ul) & ~fin[k2];
-          if (open == 0) rel[w] |= 1ull << ul;
+          for (int k2 = 0; k2 < NW; k2++) o |= s_stage[ul * NW + k2] & ~fin[k2];
+          if (o == 0) rel[w] |= 1ull << ul;
         }
+        __builtin_amdgcn_wave_barrier();
       }
     }
 #pragma unroll
@@ -839,7 +782,7 @@ __device__ void first_pass_tile(const SweepArgs& a, int item, unsigned char* sme
   }
 }
 
-// Row region of workgroup `slot` (rows in global memory only).
+// Region of workgroup `slot` (maps in global memory only).
 template <int NW, bool RS>
 __device__ inline uint64_t* rows_of(const SweepArgs& a, int slot) {
   return a.grows ? a.grows + (size_t)slot * row_region_words(a.max_n, NW, RS) : nullptr;
@@ -848,9 +791,9 @@ __device__ inline uint64_t* rows_of(const SweepArgs& a, int slot) {
 template <int NW, bool SMALL, bool RS, int LM>
 __global__ __launch_bounds__(64) void k_eval(SweepArgs a, uint32_t* counters, uint32_t* list) {
   extern __shared__ __align__(16) unsigned char smem[];
-  // rows in global memory run the persistent form only (their row regions
+  // maps in global memory run the persistent form only (their regions
   // are per running workgroup)
-  if constexpr (!RowsInGlobal<NW, RS>::value)
+  if constexpr (!MapInGlobal<NW, RS>::value)
     first_pass_tile<NW, SMALL, RS, LM>(a, blockIdx.x, smem, counters, list, nullptr);
 }
 
@@ -890,6 +833,49 @@ __global__ __launch_bounds__(64) void k_eval_global(SweepArgs a, const uint32_t*
   }
 }
 
+// Adjacency rows of one DAG per wavefront: lane x builds the successor row
+// of node x in registers and sets x in its successors' predecessor rows in
+// LDS; both go out with NW-word rows.
+template <int NW>
+__global__ __launch_bounds__(64) void k_adj(Tables t, const int32_t* list) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  uint64_t* s_pb = (uint64_t*)smem;
+  const int d = list[blockIdx.x];
+  const int lane = threadIdx.x;
+  const int64_t n0 = t.node_off[d];
+  const int N = (int)(t.node_off[d + 1] - n0);
+  const int64_t e0 = t.edge_off[d];
+  const uint32_t E = (uint32_t)(t.edge_off[d + 1] - e0);
+  uint64_t* pb = t.adj + (size_t)t.adj_node * (size_t)n0;
+  uint64_t* sb = pb + (size_t)N * NW;
+  for (int i = lane; i < N * NW; i += WAVE) s_pb[i] = 0;
+  __syncthreads();
+  for (int x = lane; x < N; x += WAVE) {
+    uint64_t row[NW];
+#pragma unroll
+    for (int w = 0; w < NW; w++) row[w] = 0;
+    const uint32_t ea = min(t.soff[n0 + d + x], E);
+    const uint32_t eb = min(max(t.soff[n0 + d + x + 1], ea), E);
+    for (uint32_t e = ea; e < eb; e++) {
+      const int u = t.succ[e0 + e];
+      if (u >= N) continue;
+      bit_set<NW>(row, u);
+      atomicOr((unsigned long long*)&s_pb[u * NW + (x >> 6)], 1ull << (x & 63));
+    }
+#pragma unroll
+    for (int w = 0; w < NW; w++) sb[(size_t)x * NW + w] = row[w];
+  }
+  __syncthreads();
+  for (int i = lane; i < N * NW; i += WAVE) pb[i] = s_pb[i];
+}
+
+template <int NW>
+hipError_t launch_adj_nw(const Tables& t, const int32_t* list, int count, int max_n, hipStream_t stream) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_adj<NW>, dim3(count), dim3(WAVE), (size_t)max_n * NW * 8, stream, t, list);
+  return hipGetLastError();
+}
+
 __global__ void k_eval_init(unsigned long long* best, int32_t D, uint32_t* counters) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < D) best[i] = ~0ull;
@@ -913,8 +899,8 @@ hipError_t launch_nw(const SweepArgs& a, uint32_t* counters, uint32_t* list, hip
   const int total = a.list_len * ntile;
   hipError_t e = hipSuccess;
   if (total <= 0) return e;
-  constexpr bool GROWS = RowsInGlobal<NW, RS>::value;
-  // rows in global memory need a row region per running workgroup: persistent only
+  constexpr bool GROWS = MapInGlobal<NW, RS>::value;
+  // maps in global memory need a region per running workgroup: persistent only
   if (a.path != EVAL_PATH_GLOBAL && (a.persistent || GROWS)) {
     const size_t lds = lds_layout(a.max_n, NW, false, RS).total;
     const void* fn = (const void*)k_eval_persistent<NW, SMALL, RS, LM>;
@@ -974,6 +960,23 @@ hipError_t launch_class(int cls, const SweepArgs& a, uint32_t* counters, uint32_
 }
 
 }  // namespace
+
+hipError_t launch_adj(const Tables& t, const int32_t* order, const int32_t class_off[NUM_CLASSES + 1],
+                      const int32_t class_max_n[NUM_CLASSES], int uniform_nw, hipStream_t stream) {
+  hipError_t e = hipSuccess;
+  for (int c = 0; c < LARGE_CLASS && e == hipSuccess; c++) {
+    const int count = class_off[c + 1] - class_off[c];
+    const int32_t* list = order + class_off[c];
+    switch (uniform_nw ? uniform_nw : 1 << c) {
+      case 1: e = launch_adj_nw<1>(t, list, count, class_max_n[c], stream); break;
+      case 2: e = launch_adj_nw<2>(t, list, count, class_max_n[c], stream); break;
+      case 4: e = launch_adj_nw<4>(t, list, count, class_max_n[c], stream); break;
+      case 8: e = launch_adj_nw<8>(t, list, count, class_max_n[c], stream); break;
+      default: e = hipErrorInvalidValue;
+    }
+  }
+  return e;
+}
 
 size_t sweep_lds_need(int max_n, int max_e) {
   (void)max_e;
@@ -1047,8 +1050,8 @@ hipError_t launch_sweep(const SweepArgs& a, hipStream_t stream, const SweepStrea
     uint32_t* counters = a.ovf_count + COUNTERS_PER_CLASS * c;
     uint32_t* list = a.ovf_list + (size_t)(a.order ? a.class_off[c] : 0) * ntile;
     if (c >= a.node_lanes_class) e = launch_eval_large(ac, counters, sc);
-    else e = a.small_loads ? launch_class<true>(c, ac, counters, list, sc)
-                           : launch_class<false>(c, ac, counters, list, sc);
+    else e = a.small_loads && a.M < 4096 ? launch_class<true>(c, ac, counters, list, sc)
+                                         : launch_class<false>(c, ac, counters, list, sc);
     if (e == hipSuccess && fork) {
       e = hipEventRecord(ss->join[c], sc);
       launched[c] = 1;
