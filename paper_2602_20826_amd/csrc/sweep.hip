@@ -510,7 +510,17 @@ __device__ bool eval_tile(const SweepArgs& a, int item, unsigned char* smem, uin
         }
         if (!bit_get_u<NW>(rel, s)) continue;
         uint32_t cv = (uint32_t)__builtin_amdgcn_readlane((int)rec.x, i);
-        if (bit_get_u<NW>(seg, s)) cv = *res_at(s);
+        if (bit_get_u<NW>(seg, s)) {
+          // a segmented member: its remaining load, and its residual slot
+          // is free again (the member finishes in this slot)
+          if (BIG) {
+            cv = res[s * WAVE + lane];
+          } else {
+            const uint32_t sl = ((s_map[(s >> 3) * WAVE + lane] >> (4 * (s & 7))) & 15u) - 1u;
+            cv = res[sl * WAVE + lane];
+            freem |= 1u << sl;
+          }
+        }
         const uint32_t mx = min((uint32_t)__builtin_amdgcn_readlane((int)rec.y, i) & 0xFFFFu, cv);
         uint32_t m;
         if (rv) m = min(rv, mx);
@@ -559,11 +569,12 @@ __device__ bool eval_tile(const SweepArgs& a, int item, unsigned char* smem, uin
       // waiting for it leaves those reads in flight
       bool sg;
       uint32_t cc = ndc.x;
+      uint32_t nib = 0;
       if (BIG) {
         sg = bit_get<NW>(seg, cur);
         if (sg) cc = res[cur * WAVE + lane];
       } else {
-        const uint32_t nib = (mwc >> (4 * (cur & 7))) & 15u;
+        nib = (mwc >> (4 * (cur & 7))) & 15u;
         sg = nib != 0;
         const uint32_t rv = res[(sg ? nib - 1u : 0u) * WAVE + lane];
         cc = sg ? rv : cc;
@@ -593,6 +604,8 @@ __device__ bool eval_tile(const SweepArgs& a, int item, unsigned char* smem, uin
         cseg = cur;
         csg = sg;
         cleft = cc - cap32;
+      } else if (!BIG && sg) {
+        freem |= 1u << (nib - 1u);  // a segmented node launched whole: its slot is free again
       }
       if (CD && bit_get<NW>(xm, cur)) {
         // launched whole (C = ceil(load / m)) or as a segment (C = maxC)
@@ -646,22 +659,14 @@ __device__ bool eval_tile(const SweepArgs& a, int item, unsigned char* smem, uin
       }
     }
     // Finished now: the unfinished members and the nodes launched whole.
-    uint64_t Dn[NW], gone[NW], Fu[NW];
+    uint64_t Dn[NW], Fu[NW];
 #pragma unroll
     for (int w = 0; w < NW; w++) {
       Dn[w] = (rel[w] & gm[w]) | Lw[w];
-      gone[w] = seg[w] & Dn[w];
       seg[w] &= ~Dn[w];
       rel[w] &= ~Dn[w];
       fin[w] |= Dn[w];
       Fu[w] = gm[w] | (__ballot(Lw[w] != 0) ? wave_or64(Lw[w]) : 0ull);  // finished now in some lane
-    }
-    if (!BIG) {  // free the residual slots of finished segmented nodes
-      while (bits_any<NW>(gone)) {
-        const int x = pop_first<NW>(gone);
-        const uint32_t sl = (s_map[(x >> 3) * WAVE + lane] >> (4 * (x & 7))) & 15u;
-        freem |= 1u << (sl - 1u);
-      }
     }
     // Releases: a successor of a node finished now (in some lane) is
     // released in the lanes where all its predecessors have finished.
