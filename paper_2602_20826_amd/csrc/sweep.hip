@@ -163,6 +163,15 @@ __device__ inline int bit_count(const uint64_t (&b)[NW]) {
 }
 
 __device__ inline uint32_t uni(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+// (a & ~b) | c in one instruction per dword; OR-accumulates the bits of a
+// row r outside a set f into o.
+__device__ inline uint32_t andn_or(uint32_t a, uint32_t b, uint32_t c) {
+  return __builtin_amdgcn_bitop3_b32(a, b, c, 0xBA);
+}
+__device__ inline uint32_t outside(uint64_t r, uint64_t f, uint32_t o) {
+  o = andn_or((uint32_t)r, (uint32_t)f, o);
+  return andn_or((uint32_t)(r >> 32), (uint32_t)(f >> 32), o);
+}
 __device__ inline uint64_t readlane64(uint64_t x, int l) {
   return ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(x >> 32), l) << 32) |
          (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, l);
@@ -558,6 +567,7 @@ __device__ bool eval_tile(const SweepArgs& a, int item, unsigned char* smem, uin
     uint32_t rc = RS ? (XB ? (uint32_t)xrow[nd.y >> 16] : 0u) : s_r[ci * WAVE + lane];
     uint32_t mw = BIG ? 0u : s_map[(ci >> 3) * WAVE + lane];
     bool go = cn >= 0;
+    const bool walked = go;
     // temporal reading: S stays for every node, the launched nodes run one
     // after another and spend the slot's time maxC
     uint32_t T = maxC;
@@ -622,11 +632,17 @@ __device__ bool eval_tile(const SweepArgs& a, int item, unsigned char* smem, uin
         go = fits && S != 0 && cn >= 0;
       }
     }
-    if (CURSOR) pq.rest(Q);
-    if (cn >= 0) bit_set<NW>(Q, cn);  // read ahead, not launched
+    // Launched whole: the nodes of Q before the first one not launched
+    // whole (the segmented one, else the one read ahead), or all of Q when
+    // the walk ran out of nodes.
+    {
+      const int stop = cseg >= 0 ? cseg : (cn >= 0 ? cn : (walked ? NW * WAVE : 0));
 #pragma unroll
-    for (int w = 0; w < NW; w++) Lw[w] = rel[w] & ~gm[w] & ~Q[w];  // taken from the walk's set
-    if (cseg >= 0) bit_clear<NW>(Lw, cseg);
+      for (int w = 0; w < NW; w++) {
+        const int t = min(max(stop - w * WAVE, 0), WAVE);
+        Lw[w] = rel[w] & ~gm[w] & (t ? ~0ull >> (WAVE - t) : 0ull);
+      }
+    }
     if (cseg >= 0) {
       if (csg) {
         *res_at(cseg) = cleft;
@@ -707,9 +723,9 @@ __device__ bool eval_tile(const SweepArgs& a, int item, unsigned char* smem, uin
 #pragma unroll
           for (int k2 = 0; k2 < NW; k2++) pr[k2] = REG ? PB[w][k2] : r[k2];
         }
-        uint64_t open = 0;
+        uint32_t open = 0;
 #pragma unroll
-        for (int k2 = 0; k2 < NW; k2++) open |= pr[k2] & ~FO[k2];
+        for (int k2 = 0; k2 < NW; k2++) open = outside(pr[k2], FO[k2], open);
         uint64_t cw = cand[w] & ~__ballot(open != 0);
         if (!cw) continue;
         if constexpr (REG) {
@@ -717,9 +733,9 @@ __device__ bool eval_tile(const SweepArgs& a, int item, unsigned char* smem, uin
           while (cw) {
             const int ul = __builtin_ctzll(cw);
             cw &= cw - 1;
-            uint64_t o = 0;
+            uint32_t o = 0;
 #pragma unroll
-            for (int k2 = 0; k2 < NW; k2++) o |= readlane64(PB[w][k2], ul) & ~fin[k2];
+            for (int k2 = 0; k2 < NW; k2++) o = outside(readlane64(PB[w][k2], ul), fin[k2], o);
             if (o == 0) rel[w] |= 1ull << ul;
           }
           continue;
@@ -732,9 +748,9 @@ __device__ bool eval_tile(const SweepArgs& a, int item, unsigned char* smem, uin
         while (cw) {
           const int ul = __builtin_ctzll(cw);
           cw &= cw - 1;
-          uint64_t o = 0;
+          uint32_t o = 0;
 #pragma unroll
-          for (int k2 = 0; k2 < NW; k2++) o |= s_stage[ul * NW + k2] & ~fin[k2];
+          for (int k2 = 0; k2 < NW; k2++) o = outside(s_stage[ul * NW + k2], fin[k2], o);
           if (o == 0) rel[w] |= 1ull << ul;
         }
         __builtin_amdgcn_wave_barrier();
