@@ -821,10 +821,10 @@ __global__ __launch_bounds__(64) void k_eval(SweepArgs a, uint32_t* counters, ui
 // Persistent form of the first pass: as many workgroups as fit on the device
 // at once, each taking tiles from a work counter until all `total` are taken.
 // Every workgroup leaves the loop when the counter passes `total`.
-// At least two waves per SIMD: the eight-word-row class would otherwise take
-// one (a few spilled registers cost less than the lost latency hiding).
+// At least three waves per SIMD: the eight-word-row class would otherwise
+// take two (the registers it spills cost less than the lost latency hiding).
 template <int NW, bool SMALL, bool RS, int LM>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_eval_persistent(SweepArgs a, uint32_t* counters, uint32_t* list,
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_eval_persistent(SweepArgs a, uint32_t* counters, uint32_t* list,
                                                         int total) {
   extern __shared__ __align__(16) unsigned char smem[];
   uint64_t* grows = rows_of<NW, RS>(a, blockIdx.x);
