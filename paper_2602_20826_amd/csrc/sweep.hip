@@ -237,7 +237,7 @@ __host__ __device__ inline size_t row_region_words(int max_n, int nw, bool rs) {
 
 // LDS layout of one wavefront (bytes), for the batch's largest DAG.
 struct Lds {
-  size_t mem, node, ppv, inv, res, r, map, stage, total;
+  size_t mem, node, ppv, inv, res, r, map, stage, uni, total;
 };
 __host__ __device__ inline Lds lds_layout(int maxn, int nw, bool big, bool rs) {
   Lds l;
@@ -262,6 +262,7 @@ __host__ __device__ inline Lds lds_layout(int maxn, int nw, bool big, bool rs) {
   o = (o + 15) & ~(size_t)15;
   l.stage = o; o += nw <= 2 ? 0 : (size_t)WAVE * nw * 8;  // predecessor rows of release candidates [lane][nw]
                                                           // (rows of DAGs up to 128 nodes stay in registers)
+  l.uni = o;  o += nw <= 2 ? 0 : (size_t)2 * nw * 8;     // wave-uniform sets above 128 nodes: FO, members
   l.total = (o + 15) & ~(size_t)15;
   return l;
 }
@@ -434,9 +435,18 @@ __device__ bool eval_tile(const SweepArgs& a, int item, unsigned char* smem, uin
   uint64_t bound = 0, cp = 0;
   uint64_t xbound = 0, xcp = 0;  // conditional: the realization's bound and maxC terms
   bool ovf = false;
-  uint64_t FO[NW];  // nodes finished in some lane (wave-uniform)
+  // FO: nodes finished in some lane (wave-uniform).  Above 128 nodes FO and
+  // the group's member set wait in LDS while they are not needed, which
+  // leaves their registers to the walk and the release.
+  constexpr bool ULDS = NW >= 4;
+  uint64_t FO[ULDS ? 1 : NW];
+  uint64_t* s_uni = (uint64_t*)(smem + L.uni);  // [0, NW): FO, [NW, 2 NW): members
+  if constexpr (ULDS) {
+    if (lane < NW) s_uni[lane] = 0;
+  } else {
 #pragma unroll
-  for (int w = 0; w < NW; w++) FO[w] = 0;
+    for (int w = 0; w < NW; w++) FO[w] = 0;
+  }
   int k = 0;
   while (k < N) {
     // The group's extent from the members' end marks, 64 records at a time;
@@ -555,6 +565,12 @@ __device__ bool eval_tile(const SweepArgs& a, int item, unsigned char* smem, uin
     uint64_t Q[NW], Lw[NW];
 #pragma unroll
     for (int w = 0; w < NW; w++) Q[w] = rel[w] & ~gm[w];
+    if constexpr (ULDS) {
+      if (lane == 0) {
+#pragma unroll
+        for (int w = 0; w < NW; w++) s_uni[NW + w] = gm[w];
+      }
+    }
     int cseg = -1;
     bool csg = false;
     uint32_t cleft = 0;
@@ -640,7 +656,7 @@ __device__ bool eval_tile(const SweepArgs& a, int item, unsigned char* smem, uin
 #pragma unroll
       for (int w = 0; w < NW; w++) {
         const int t = min(max(stop - w * WAVE, 0), WAVE);
-        Lw[w] = rel[w] & ~gm[w] & (t ? ~0ull >> (WAVE - t) : 0ull);
+        Lw[w] = rel[w] & ~(ULDS ? s_uni[NW + w] : gm[w]) & (t ? ~0ull >> (WAVE - t) : 0ull);
       }
     }
     if (cseg >= 0) {
@@ -678,11 +694,12 @@ __device__ bool eval_tile(const SweepArgs& a, int item, unsigned char* smem, uin
     uint64_t Dn[NW], Fu[NW];
 #pragma unroll
     for (int w = 0; w < NW; w++) {
-      Dn[w] = (rel[w] & gm[w]) | Lw[w];
+      const uint64_t g = ULDS ? s_uni[NW + w] : gm[w];
+      Dn[w] = (rel[w] & g) | Lw[w];
       seg[w] &= ~Dn[w];
       rel[w] &= ~Dn[w];
       fin[w] |= Dn[w];
-      Fu[w] = gm[w] | (__ballot(Lw[w] != 0) ? wave_or64(Lw[w]) : 0ull);  // finished now in some lane
+      Fu[w] = g | (__ballot(Lw[w] != 0) ? wave_or64(Lw[w]) : 0ull);  // finished now in some lane
     }
     // Releases: a successor of a node finished now (in some lane) is
     // released in the lanes where all its predecessors have finished.
@@ -698,7 +715,13 @@ __device__ bool eval_tile(const SweepArgs& a, int item, unsigned char* smem, uin
 #pragma unroll
       for (int k2 = 0; k2 < NW; k2++) {
         acc[k2] = 0;
-        FO[k2] |= Fu[k2];
+        if (!ULDS) FO[ULDS ? 0 : k2] |= Fu[k2];
+      }
+      if constexpr (ULDS) {
+        if (lane == 0) {
+#pragma unroll
+          for (int k2 = 0; k2 < NW; k2++) s_uni[k2] |= Fu[k2];
+        }
       }
 #pragma unroll
       for (int w = 0; w < NW; w++) {
@@ -725,7 +748,7 @@ __device__ bool eval_tile(const SweepArgs& a, int item, unsigned char* smem, uin
         }
         uint32_t open = 0;
 #pragma unroll
-        for (int k2 = 0; k2 < NW; k2++) open = outside(pr[k2], FO[k2], open);
+        for (int k2 = 0; k2 < NW; k2++) open = outside(pr[k2], ULDS ? s_uni[k2] : FO[ULDS ? 0 : k2], open);
         uint64_t cw = cand[w] & ~__ballot(open != 0);
         if (!cw) continue;
         if constexpr (REG) {
