@@ -242,7 +242,7 @@ struct Lds {
 __host__ __device__ inline Lds lds_layout(int maxn, int nw, bool big, bool rs) {
   Lds l;
   size_t o = 0;
-  l.mem = o;  o += (size_t)maxn * 8;            // members in group order
+  l.mem = o;  o += nw == 8 ? 0 : (size_t)maxn * 8;  // members in group order (above 256 nodes: device memory)
   l.node = o; o += (size_t)maxn * 8;            // node info by sigma rank
   const size_t idb = ((size_t)maxn * 2 + 15) & ~(size_t)15;
   if (big) {
@@ -323,11 +323,26 @@ __device__ bool eval_tile(const SweepArgs& a, int item, unsigned char* smem, uin
     s_ppv[v] = (uint16_t)y;
     s_node[s].y = y | ((uint32_t)v << 16);
   }
-  for (int k = lane; k < N; k += WAVE) {
-    const uint32_t g = a.t.gl[n0 + k];
-    const int s = g & 0x7FFF;
-    const uint2 nd = s_node[s];
-    s_mem[k] = make_uint2(nd.x, (nd.y & 0xFFFFu) | ((uint32_t)s << 16) | ((g & 0x8000u) << 16));
+  // Member records in group order.  Above 256 nodes (GREC) they are read
+  // from the batch's member records in device memory, the next group's
+  // first 64 one group ahead, which leaves their LDS to more wavefronts.
+  constexpr bool GREC = NW == 8;
+  const uint4* mrec = GREC ? a.t.mrec + n0 : nullptr;
+  auto mem_rec = [&](int i) -> uint2 {
+    if constexpr (GREC) {
+      const uint4 r = mrec[i];
+      return make_uint2(r.x, r.y);
+    } else {
+      return s_mem[i];
+    }
+  };
+  if (!GREC) {
+    for (int k = lane; k < N; k += WAVE) {
+      const uint32_t g = a.t.gl[n0 + k];
+      const int s = g & 0x7FFF;
+      const uint2 nd = s_node[s];
+      s_mem[k] = make_uint2(nd.x, (nd.y & 0xFFFFu) | ((uint32_t)s << 16) | ((g & 0x8000u) << 16));
+    }
   }
   __syncthreads();
   // Predecessor and successor rows of the DAG's nodes (NW words each, by
@@ -448,11 +463,14 @@ __device__ bool eval_tile(const SweepArgs& a, int item, unsigned char* smem, uin
     for (int w = 0; w < NW; w++) FO[w] = 0;
   }
   int k = 0;
+  uint2 nxt = make_uint2(0u, 0u);
+  if (GREC && lane < N) nxt = mem_rec(lane);
   while (k < N) {
     // The group's extent from the members' end marks, 64 records at a time;
     // the first 64 records stay in registers (lane i holds member k + i).
     uint2 rec0 = make_uint2(0u, 0u);
-    if (k + lane < N) rec0 = s_mem[k + lane];
+    if (GREC) rec0 = nxt;
+    else if (k + lane < N) rec0 = s_mem[k + lane];
     int kend;
     {
       const uint64_t ends = __ballot(k + lane < N && (rec0.y >> 31));
@@ -461,13 +479,17 @@ __device__ bool eval_tile(const SweepArgs& a, int item, unsigned char* smem, uin
       } else {
         kend = k + WAVE;
         while (kend < N) {
-          const bool e = kend + lane < N && (s_mem[kend + lane].y >> 31);
+          const bool e = kend + lane < N && (mem_rec(kend + lane).y >> 31);
           const uint64_t m = __ballot(e);
           if (m) { kend += 1 + __builtin_ctzll(m); break; }
           kend += WAVE;
         }
         kend = min(kend, N);
       }
+    }
+    if (GREC) {
+      nxt = make_uint2(0u, 0u);
+      if (kend + lane < N) nxt = mem_rec(kend + lane);
     }
     // Pass 1: member set and W(pi_j), the remaining load of the members
     // unfinished in this lane (Eq. 5).
@@ -478,7 +500,7 @@ __device__ bool eval_tile(const SweepArgs& a, int item, unsigned char* smem, uin
     uint32_t W32 = 0;  // loads below 2^20: up to 512 of them sum below 2^29
     for (int base = k; base < kend; base += WAVE) {
       uint2 rec = rec0;
-      if (base != k && base + lane < kend) rec = s_mem[base + lane];
+      if (base != k && base + lane < kend) rec = mem_rec(base + lane);
       const int cnt = min(WAVE, kend - base);
       for (int i = 0; i < cnt; i++) {
         const int s = ((uint32_t)__builtin_amdgcn_readlane((int)rec.y, i) >> 16) & 0x7FFF;
@@ -506,7 +528,7 @@ __device__ bool eval_tile(const SweepArgs& a, int item, unsigned char* smem, uin
     uint32_t A32 = 0;
     for (int base = k; base < kend; base += WAVE) {
       uint2 rec = rec0;
-      if (base != k && base + lane < kend) rec = s_mem[base + lane];
+      if (base != k && base + lane < kend) rec = mem_rec(base + lane);
       const int cnt = min(WAVE, kend - base);
       uint32_t rnext = 0, recv = 0;
       if (RS) {  // local ids of the chunk's members
@@ -943,6 +965,9 @@ hipError_t launch_nw(const SweepArgs& a, uint32_t* counters, uint32_t* list, hip
   const int total = a.list_len * ntile;
   hipError_t e = hipSuccess;
   if (total <= 0) return e;
+  // eight-word rows read the member records of the batch (written whenever
+  // it holds a DAG above 256 nodes, which such a launch implies)
+  if (NW == 8 && !a.t.mrec) return hipErrorInvalidValue;
   constexpr bool GROWS = MapInGlobal<NW, RS>::value;
   // maps in global memory need a region per running workgroup: persistent only
   if (a.path != EVAL_PATH_GLOBAL && (a.persistent || GROWS)) {
