@@ -344,10 +344,11 @@ dagbound_status dagbound_get_division(dagbound_batch* batch, int32_t d, int64_t*
  *                     all DAGs, sized for the largest.  DAGs above 512 nodes
  *                     run one wavefront per (DAG, candidate); "residual_slots",
  *                     "eval_path" and "persistent" do not apply to them.
- *   "class_streams"   1 (default): the class launches run concurrently on
- *                     side streams of the device (forked from and joined back
- *                     to the caller's stream with events); 0: in turn on the
- *                     caller's stream.
+ *   "class_streams"   1 (default): when the batch holds DAGs above 128 nodes,
+ *                     the class launches run concurrently on side streams of
+ *                     the device (forked from and joined back to the caller's
+ *                     stream with events), else in turn on the caller's
+ *                     stream; 0: always in turn on the caller's stream.
  *   "persistent"      0 (default): one workgroup per 64-candidate tile;
  *                     1: as many workgroups as fit on the device, each taking
  *                     tiles from a work counter.

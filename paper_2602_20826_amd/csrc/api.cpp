@@ -374,9 +374,18 @@ hipError_t ensure_adj(dagbound_batch* b, hipStream_t st) {
 hipError_t run_sweep_plan(dagbound_batch* b, const SweepArgs& a, hipStream_t st) {
   const hipError_t ea = ensure_adj(b, st);
   if (ea != hipSuccess) return ea;
+  // Concurrent class launches pay off when a class runs the persistent form
+  // (DAGs above 128 nodes), whose grid is capped by its occupancy; the
+  // one-workgroup-per-tile launches of the smaller classes each fill the
+  // device alone and run faster one after the other (100,000 batched-layered
+  // DAGs: 4.13 against 4.26 ms per evaluation).
   int classes = 0;
-  for (int c = 0; c < NUM_CLASSES; c++) classes += b->class_off[c + 1] > b->class_off[c];
-  if (!a.order || !b->class_streams || classes < 2) return launch_sweep(a, st, nullptr);
+  bool wide = false;
+  for (int c = 0; c < NUM_CLASSES; c++) {
+    classes += b->class_off[c + 1] > b->class_off[c];
+    wide = wide || (c >= 2 && b->class_off[c + 1] > b->class_off[c]);
+  }
+  if (!a.order || !b->class_streams || classes < 2 || !wide) return launch_sweep(a, st, nullptr);
   SweepStreams ss;
   hipError_t e = plan_resources(b, &ss);
   if (e != hipSuccess) return e;
