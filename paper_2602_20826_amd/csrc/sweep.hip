@@ -267,16 +267,19 @@ __host__ __device__ inline Lds lds_layout(int maxn, int nw, bool big, bool rs) {
   return l;
 }
 
-// Eq. 5's half-up share for loads below 2^20: W < 2^29 then, and a float
-// estimate from the slot's reciprocal of 2W is within one of the quotient;
-// one exact integer step corrects it.
+// Eq. 5's half-up share floor((2 cv M + W) / (2 W)) for loads below 2^20
+// and M below 2^12: cv M < 2^32 and W < 2^29 then.  A float estimate from
+// the slot's reciprocal of 2W is within one of the quotient; the remainder
+// 2 cv M + W - 2 W q then lies in [-2W, 4W), inside the signed 32-bit range,
+// so wrapping 32-bit arithmetic gives it exactly and one signed test
+// corrects the estimate.
 __device__ inline uint32_t round_share_small(uint32_t cv, uint32_t M, uint32_t W, float rw2) {
-  const uint64_t num = 2ull * cv * M + W;
-  const uint64_t den = 2ull * W;
+  const uint32_t num = 2u * __umul24(cv, M) + W;  // modulo 2^32
+  const uint32_t den = 2u * W;
   uint32_t q = (uint32_t)(__builtin_fmaf(2.0f * (float)cv, (float)M, (float)W) * rw2);
-  const uint64_t pq = (uint64_t)q * den;
-  if (pq > num) q--;
-  else if (pq + den <= num) q++;
+  const int32_t r = (int32_t)(num - q * den);
+  if (r < 0) q--;
+  else if (r >= (int32_t)den) q++;
   return q;
 }
 
