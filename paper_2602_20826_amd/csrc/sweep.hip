@@ -353,11 +353,11 @@ __device__ bool eval_tile(const SweepArgs& a, int item, unsigned char* smem, uin
   const uint64_t* prow_v = a.t.adj + (size_t)a.t.adj_node * (size_t)n0;
   const uint64_t* srow_v = prow_v + (size_t)N * NW;
   uint64_t* s_stage = (uint64_t*)(smem + L.stage);  // [lane][NW] rows of the release candidates
-  // released: the sources; finished: none.  Rows of DAGs up to 128 nodes
-  // stay in registers (REG): lane x keeps those of nodes w * 64 + x.
+  // released: the sources; finished: none.  Predecessor rows of DAGs up to
+  // 128 nodes stay in registers (REG): lane x keeps those of nodes w * 64 + x.
   constexpr bool REG = NW <= 2;
   uint64_t rel[NW], fin[NW], seg[NW];
-  uint64_t PB[REG ? NW : 1][REG ? NW : 1], SB[REG ? NW : 1][REG ? NW : 1];
+  uint64_t PB[REG ? NW : 1][REG ? NW : 1];
 #pragma unroll
   for (int w = 0; w < NW; w++) {
     const int u = w * WAVE + lane;
@@ -368,7 +368,6 @@ __device__ bool eval_tile(const SweepArgs& a, int item, unsigned char* smem, uin
 #pragma unroll
       for (int k2 = 0; k2 < NW; k2++) {
         PB[w][k2] = u < N ? prow_v[(size_t)u * NW + k2] : 0ull;
-        SB[w][k2] = u < N ? srow_v[(size_t)u * NW + k2] : 0ull;
       }
     }
   }
@@ -736,28 +735,42 @@ __device__ bool eval_tile(const SweepArgs& a, int item, unsigned char* smem, uin
     // candidate's row (one broadcast read) and tests it against its own
     // finished set.
     {
-      uint64_t acc[NW], cand[NW];
+      uint64_t cand[NW];
 #pragma unroll
-      for (int k2 = 0; k2 < NW; k2++) {
-        acc[k2] = 0;
+      for (int k2 = 0; k2 < NW; k2++)
         if (!ULDS) FO[ULDS ? 0 : k2] |= Fu[k2];
-      }
       if constexpr (ULDS) {
         if (lane == 0) {
 #pragma unroll
           for (int k2 = 0; k2 < NW; k2++) s_uni[k2] |= Fu[k2];
         }
       }
+      if constexpr (REG) {
+        // lane x holds node w * 64 + x's predecessor row: a candidate when
+        // one of its predecessors finished now in some lane
 #pragma unroll
-      for (int w = 0; w < NW; w++) {
-        if ((Fu[w] >> lane) & 1) {
-          const uint64_t* r = srow_v + (size_t)(w * WAVE + lane) * NW;
+        for (int w = 0; w < NW; w++) {
+          uint32_t hit = 0;
 #pragma unroll
-          for (int k2 = 0; k2 < NW; k2++) acc[k2] |= REG ? SB[w][k2] : r[k2];
+          for (int k2 = 0; k2 < NW; k2++)
+            hit |= ((uint32_t)PB[w][k2] & (uint32_t)Fu[k2]) | ((uint32_t)(PB[w][k2] >> 32) & (uint32_t)(Fu[k2] >> 32));
+          cand[w] = __ballot(hit != 0);
         }
-      }
+      } else {
+        uint64_t acc[NW];
 #pragma unroll
-      for (int k2 = 0; k2 < NW; k2++) cand[k2] = __ballot(acc[k2] != 0) ? wave_or64(acc[k2]) : 0ull;
+        for (int k2 = 0; k2 < NW; k2++) acc[k2] = 0;
+#pragma unroll
+        for (int w = 0; w < NW; w++) {
+          if ((Fu[w] >> lane) & 1) {
+            const uint64_t* r = srow_v + (size_t)(w * WAVE + lane) * NW;
+#pragma unroll
+            for (int k2 = 0; k2 < NW; k2++) acc[k2] |= r[k2];
+          }
+        }
+#pragma unroll
+        for (int k2 = 0; k2 < NW; k2++) cand[k2] = __ballot(acc[k2] != 0) ? wave_or64(acc[k2]) : 0ull;
+      }
       // A node found ready is added to rel even where it has finished
       // already; rel is cut back to the unfinished nodes below.
 #pragma unroll
