@@ -661,6 +661,9 @@ WORKLOAD_KEYS = {"persistent-mixed": 3, "batched-layered": 2, "large-compiler": 
 
 def describe(wk: int, D: int, K: int, seeded: bool) -> str:
     kind = "seeded" if seeded else "explicit"
+    if wk == 1:
+        return (f"small-er: {D} DAGs, 10-20 nodes, ER p=0.2, WCET 1-100, parallelism 1-8, M=8, "
+                f"{K} {kind} candidates")
     if wk == 2:
         return (f"batched-layered: {D} DAGs, 20-100 internal nodes (+source/sink), layered width 1-16 p=0.3, "
                 f"WCET 1-1000, parallelism 1-32, M=256, {K} {kind} candidates")
@@ -805,6 +808,18 @@ def main() -> int:
                                   "seconds": dt, "oracle_evals_per_s": wb.size / dt}
         out["batched_layered"] = r2
         del b2, h2
+        # the small-er configuration (1,000 DAGs of 10-20 nodes, 16 candidates)
+        r1, b1, h1 = exact_block(torch, db, W, 1, args.steps, args.warmup, tuning=tuning, para=args.para,
+                                 keep_head=0 if args.no_cpu_baseline else W.WORKLOADS[1].num_dags)
+        r1["workload"] = describe(1, b1.num_dags, W.WORKLOADS[1].K, False)
+        if not args.no_cpu_baseline:
+            wb, dt = oracle_rate(b1, W.WORKLOADS[1].num_cus, W.WORKLOADS[1].K, W.WORKLOADS[1].seed, b1.num_dags,
+                                 max(1, min(ORACLE_THREADS, os.cpu_count() or 1)),
+                                 1 if args.para == "temporal" else 0)
+            r1["oracle_check"] = {"evals_checked": int(wb.size), "mismatches_vs_gpu": int(np.count_nonzero(wb != h1)),
+                                  "seconds": dt, "oracle_evals_per_s": wb.size / dt}
+        out["small_er"] = r1
+        del b1, h1
     if not args.no_search:
         out["best_gap"] = search_block(torch, db, W, args.search_train, args.search_test, args.search_epochs,
                                        check=not args.no_cpu_baseline)
