@@ -332,7 +332,8 @@ dagbound_status dagbound_get_division(dagbound_batch* batch, int32_t d, int64_t*
 /*
  * dagbound_set_tuning -- launch-plan options of the evaluation kernels; they
  * never change results.
- *   "residual_slots"  1..12 (default 12): per-candidate LDS table slots for
+ *   "residual_slots"  1..12 (default 12; DAGs up to 128 nodes use at most
+ *                     10): per-candidate LDS table slots for
  *                     the remaining loads of segmented nodes; a 64-candidate
  *                     tile that needs more restarts with a table in global
  *                     memory that holds every node (256 such tables per

@@ -94,7 +94,11 @@ hipError_t realize_schedule(const int64_t* rec, int64_t nrec, int32_t n, const i
 
 // Slots of the per-lane table of segmented residuals in the first
 // evaluation pass; a tile that needs more goes to the global-memory pass.
+// DAGs of up to 128 nodes keep RES_SLOTS_SMALL of them, which leaves their
+// wavefronts' LDS small enough for one more wavefront per compute unit.
 constexpr int RES_SLOTS = 12;
+constexpr int RES_SLOTS_SMALL = 10;
+__host__ __device__ constexpr int res_slots_of(int nw) { return nw <= 2 ? RES_SLOTS_SMALL : RES_SLOTS; }
 // Global-memory residual tables (max_n * 64 words each): a first-pass tile
 // that overflows its LDS table takes one and finishes at once; the second
 // pass (one workgroup per table) takes the tiles left when all are taken.

@@ -252,10 +252,11 @@ __host__ __device__ inline Lds lds_layout(int maxn, int nw, bool big, bool rs) {
   } else {
     // the two id tables serve the set-up only, before the residual table
     // is first written: they share its space (12 * 64 words >= 2 * 512 ids)
-    l.res = o;  o += (size_t)RES_SLOTS * WAVE * 4;  // residual table [slot][lane]
+    l.res = o;  o += (size_t)res_slots_of(nw) * WAVE * 4;  // residual table [slot][lane]
     l.ppv = l.res;
     l.inv = l.res + idb;
-    static_assert(RES_SLOTS * WAVE * 4 >= 2 * 512 * 2, "id tables fit in the residual table");
+    static_assert(RES_SLOTS * WAVE * 4 >= 2 * 512 * 2 && RES_SLOTS_SMALL * WAVE * 4 >= 2 * 128 * 2,
+                  "id tables fit in the residual table");
   }
   l.r = o;    o += rs ? 0 : (size_t)maxn * WAVE;  // candidate bytes [sigma][lane] (none when drawn on the fly)
   l.map = o;  o += (big || (nw >= 4 && rs)) ? 0 : (size_t)((maxn + 7) / 8) * WAVE * 4;  // residual slot of a node, 4 bits
@@ -274,7 +275,7 @@ __host__ __device__ inline Lds lds_layout(int maxn, int nw, bool big, bool rs) {
 // so wrapping 32-bit arithmetic gives it exactly and one signed test
 // corrects the estimate.
 __device__ inline uint32_t round_share_small(uint32_t cv, uint32_t M, uint32_t W, float rw2) {
-  const uint32_t num = 2u * __umul24(cv, M) + W;  // modulo 2^32
+  const uint32_t num = __umul24(2u * cv, M) + W;  // modulo 2^32
   const uint32_t den = 2u * W;
   uint32_t q = (uint32_t)(__builtin_fmaf(2.0f * (float)cv, (float)M, (float)W) * rw2);
   const int32_t r = (int32_t)(num - q * den);
@@ -374,7 +375,7 @@ __device__ bool eval_tile(const SweepArgs& a, int item, unsigned char* smem, uin
   if (!BIG) {
     for (int i = 0; i < (N + 7) / 8; i++) s_map[i * WAVE + lane] = 0;
   }
-  uint32_t freem = (1u << a.res_slots) - 1u;  // free residual slots
+  uint32_t freem = (1u << min(a.res_slots, res_slots_of(NW))) - 1u;  // free residual slots
   // ---- candidate bytes of this lane, by sigma rank.  Candidate 0 is the
   // paper's own rule (all zero); lanes past K run zeros and store nothing.
   // With RS the bytes stay out of LDS: seeded bytes are drawn where they are
@@ -567,7 +568,7 @@ __device__ bool eval_tile(const SweepArgs& a, int item, unsigned char* smem, uin
         const uint32_t mx = min((uint32_t)__builtin_amdgcn_readlane((int)rec.y, i) & 0xFFFFu, cv);
         uint32_t m;
         if (rv) m = min(rv, mx);
-        else m = max(1u, min(mx, SMALL ? round_share_small(cv, M, (uint32_t)W, rw2) : round_share(cv, M, W)));
+        else m = max(1u, min(mx, SMALL ? round_share_small(cv, M, W32, rw2) : round_share(cv, M, W)));
         const uint32_t C = ceil_div<SMALL>(cv, m);
         maxC = max(maxC, C);
         sm += m;
