@@ -242,7 +242,8 @@ struct Lds {
 __host__ __device__ inline Lds lds_layout(int maxn, int nw, bool big, bool rs) {
   Lds l;
   size_t o = 0;
-  l.mem = o;  o += nw == 8 ? 0 : (size_t)maxn * 8;  // members in group order (above 256 nodes: device memory)
+  // members in group order, sigma | last << 15 (above 256 nodes: device memory)
+  l.mem = o;  o += nw == 8 ? 0 : ((size_t)maxn * 2 + 15) & ~(size_t)15;
   l.node = o; o += (size_t)maxn * 8;            // node info by sigma rank
   const size_t idb = ((size_t)maxn * 2 + 15) & ~(size_t)15;
   if (big) {
@@ -308,7 +309,7 @@ __device__ bool eval_tile(const SweepArgs& a, int item, unsigned char* smem, uin
   const bool mpow2 = (M & (M - 1u)) == 0u;  // division by M as a shift
   const uint32_t msh = (uint32_t)__builtin_ctz(M);
   const Lds L = lds_layout(a.max_n, NW, BIG, RS);
-  uint2* s_mem = (uint2*)(smem + L.mem);       // {C_hat, pp | s << 16 | last << 31}
+  uint16_t* s_mem = (uint16_t*)(smem + L.mem); // sigma | last << 15, in group order
   uint2* s_node = (uint2*)(smem + L.node);     // {C_hat, pp | local id << 16} by sigma rank
   uint16_t* s_ppv = (uint16_t*)(smem + L.ppv); // [local id]
   uint16_t* s_inv = (uint16_t*)(smem + L.inv); // [local id]
@@ -329,7 +330,9 @@ __device__ bool eval_tile(const SweepArgs& a, int item, unsigned char* smem, uin
   }
   // Member records in group order.  Above 256 nodes (GREC) they are read
   // from the batch's member records in device memory, the next group's
-  // first 64 one group ahead, which leaves their LDS to more wavefronts.
+  // first 64 one group ahead, which leaves their LDS to more wavefronts;
+  // smaller DAGs keep only the group order (sigma ranks) in LDS and take
+  // the rest of a record from the node table.
   constexpr bool GREC = NW == 8;
   const uint4* mrec = GREC ? a.t.mrec + n0 : nullptr;
   auto mem_rec = [&](int i) -> uint2 {
@@ -337,16 +340,14 @@ __device__ bool eval_tile(const SweepArgs& a, int item, unsigned char* smem, uin
       const uint4 r = mrec[i];
       return make_uint2(r.x, r.y);
     } else {
-      return s_mem[i];
+      // {C_hat, pp | s << 16 | last << 31} from the node's record
+      const uint32_t g = s_mem[i];
+      const uint2 nd = s_node[g & 0x7FFFu];
+      return make_uint2(nd.x, (nd.y & 0xFFFFu) | ((g & 0x7FFFu) << 16) | ((g & 0x8000u) << 16));
     }
   };
   if (!GREC) {
-    for (int k = lane; k < N; k += WAVE) {
-      const uint32_t g = a.t.gl[n0 + k];
-      const int s = g & 0x7FFF;
-      const uint2 nd = s_node[s];
-      s_mem[k] = make_uint2(nd.x, (nd.y & 0xFFFFu) | ((uint32_t)s << 16) | ((g & 0x8000u) << 16));
-    }
+    for (int k = lane; k < N; k += WAVE) s_mem[k] = a.t.gl[n0 + k];
   }
   __syncthreads();
   // Predecessor and successor rows of the DAG's nodes (NW words each, by
@@ -473,7 +474,7 @@ __device__ bool eval_tile(const SweepArgs& a, int item, unsigned char* smem, uin
     // the first 64 records stay in registers (lane i holds member k + i).
     uint2 rec0 = make_uint2(0u, 0u);
     if (GREC) rec0 = nxt;
-    else if (k + lane < N) rec0 = s_mem[k + lane];
+    else if (k + lane < N) rec0 = mem_rec(k + lane);
     int kend;
     {
       const uint64_t ends = __ballot(k + lane < N && (rec0.y >> 31));
