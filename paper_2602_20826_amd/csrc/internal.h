@@ -66,9 +66,12 @@ hipError_t launch_prep(const Tables& t, const PrepInputs& in, int32_t D, int32_t
                        const hipStream_t* side, hipEvent_t fork, const hipEvent_t* join, hipStream_t stream);
 
 // Largest DAG the large-DAG kernels take, and the most workgroups of a
-// workgroup-per-DAG preprocessing launch (each with its own scratch region).
+// workgroup-per-DAG preprocessing launch (each with its own scratch region):
+// DAGs of 257-512 nodes take workgroups of four wavefronts, five per compute
+// unit; larger DAGs take sixteen wavefronts, one per compute unit.
 constexpr int LARGE_MAX_N = 8000;
-constexpr int PREP_LARGE_GRID = 512;
+constexpr int PREP_LARGE_GRID = 1280;
+constexpr int PREP_LARGE_GRID_BIG = 256;
 // Global scratch of a workgroup-per-DAG preprocessing launch over `count`
 // DAGs of up to max_n nodes and max_e edges.
 size_t prep_large_scratch_bytes(int32_t count, int32_t max_n, int32_t max_e);

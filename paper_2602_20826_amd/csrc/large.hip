@@ -1,7 +1,7 @@
 // DAGs above 512 nodes on gfx950.
 //
-// Preprocessing (k_prep_large): one workgroup of 16 wavefronts per DAG, each
-// workgroup looping over DAGs from a work counter.  The ancestor bit-matrix
+// Preprocessing (k_prep_large): one workgroup per DAG (4 wavefronts up to
+// 512 nodes, 16 above), each workgroup looping over DAGs from a work counter.  The ancestor bit-matrix
 // (N x ceil(N/64) words, too large for LDS) lives in a global-memory region
 // of the workgroup; the tables it writes are the ones the small-DAG kernel
 // writes (prep.hip), plus the member records in group order.
@@ -1146,7 +1146,7 @@ hipError_t launch_large_c(const SweepArgs& a, unsigned long long* counter, uint6
 // compute unit) for DAGs up to 512 nodes, 1024 threads (one per compute
 // unit, whose LDS the largest DAGs fill) above.
 static int prep_large_grid(int32_t count, int32_t max_n) {
-  return std::max(0, std::min(count, max_n <= 512 ? PREP_LARGE_GRID : PREP_LARGE_GRID / 2));
+  return std::max(0, std::min(count, max_n <= 512 ? PREP_LARGE_GRID : PREP_LARGE_GRID_BIG));
 }
 
 size_t prep_large_scratch_bytes(int32_t count, int32_t max_n, int32_t max_e) {
@@ -1173,7 +1173,7 @@ hipError_t launch_prep_large(const Tables& t, const PrepInputs& in, int32_t coun
   if (NL > LARGE_MAX_N || !scratch) return hipErrorInvalidValue;
   hipError_t e = hipMemsetAsync(err + 2, 0, sizeof(unsigned long long), stream);  // work counter
   if (e != hipSuccess) return e;
-  return NL <= 512 ? launch_prep_pt<512>(t, in, count, M, list, err, scratch, NL, EL, stream)
+  return NL <= 512 ? launch_prep_pt<256>(t, in, count, M, list, err, scratch, NL, EL, stream)
                    : launch_prep_pt<1024>(t, in, count, M, list, err, scratch, NL, EL, stream);
 }
 
