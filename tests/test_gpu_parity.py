@@ -240,11 +240,14 @@ def test_seeded_mode_matches_explicit_bytes(torch_dev):
 
 
 @pytest.mark.parametrize("tuning", [{"eval_path": 1}, {"residual_slots": 1}, {"residual_slots": 2},
-                                    {"size_classes": 0}, {"size_classes": 0, "residual_slots": 1}],
-                         ids=["global-pass-only", "one-slot", "two-slots", "one-launch", "one-launch-one-slot"])
+                                    {"residual_slots": 12}, {"size_classes": 0},
+                                    {"size_classes": 0, "residual_slots": 1}],
+                         ids=["global-pass-only", "one-slot", "two-slots", "twelve-slots", "one-launch",
+                              "one-launch-one-slot"])
 def test_second_pass_paths(torch_dev, tuning):
     # The global-memory pass alone, and the first pass with tiny residual
-    # tables so that many tiles overflow and are handed over.
+    # tables so that many tiles overflow and are handed over; twelve slots
+    # asked of DAGs up to 128 nodes, whose tables hold ten.
     wl = W.WORKLOADS[2]
     batch = W.generate_workload(2, count=700, first=50)
     alloc = W.alloc_bytes(batch, wl.num_cus, wl.K, seed=21, first=50)
