@@ -67,10 +67,11 @@ hipError_t launch_prep(const Tables& t, const PrepInputs& in, int32_t D, int32_t
 
 // Largest DAG the large-DAG kernels take, and the most workgroups of a
 // workgroup-per-DAG preprocessing launch (each with its own scratch region):
-// DAGs of 257-512 nodes take workgroups of four wavefronts, five per compute
-// unit; larger DAGs take sixteen wavefronts, one per compute unit.
+// DAGs of 257-512 nodes take workgroups of four wavefronts, six per compute
+// unit (six wavefronts per SIMD); larger DAGs take sixteen wavefronts, one
+// per compute unit.
 constexpr int LARGE_MAX_N = 8000;
-constexpr int PREP_LARGE_GRID = 1280;
+constexpr int PREP_LARGE_GRID = 1536;
 constexpr int PREP_LARGE_GRID_BIG = 256;
 // Global scratch of a workgroup-per-DAG preprocessing launch over `count`
 // DAGs of up to max_n nodes and max_e edges.

@@ -640,7 +640,7 @@ __device__ void prep_one(const Tables& t, const PrepInputs& in, int32_t M, int d
 }
 
 template <int PT>
-__global__ __launch_bounds__(PT) void k_prep_large(Tables t, PrepInputs in, int32_t M, const int32_t* list,
+__global__ __launch_bounds__(PT) __attribute__((amdgpu_waves_per_eu(6))) void k_prep_large(Tables t, PrepInputs in, int32_t M, const int32_t* list,
                                                    int32_t count, unsigned long long* err, unsigned char* scratch,
                                                    int32_t NL, int32_t EL) {
   extern __shared__ __align__(16) unsigned char smem[];
