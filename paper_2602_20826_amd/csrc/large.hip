@@ -1,7 +1,8 @@
 // DAGs above 512 nodes on gfx950.
 //
 // Preprocessing (k_prep_large): one workgroup per DAG (4 wavefronts up to
-// 512 nodes, 16 above), each workgroup looping over DAGs from a work counter.  The ancestor bit-matrix
+// 512 nodes, 16 above), each workgroup looping over DAGs from a work
+// counter.  The ancestor bit-matrix
 // (N x ceil(N/64) words, too large for LDS) lives in a global-memory region
 // of the workgroup; the tables it writes are the ones the small-DAG kernel
 // writes (prep.hip), plus the member records in group order.
@@ -640,9 +641,9 @@ __device__ void prep_one(const Tables& t, const PrepInputs& in, int32_t M, int d
 }
 
 template <int PT>
-__global__ __launch_bounds__(PT) __attribute__((amdgpu_waves_per_eu(6))) void k_prep_large(Tables t, PrepInputs in, int32_t M, const int32_t* list,
-                                                   int32_t count, unsigned long long* err, unsigned char* scratch,
-                                                   int32_t NL, int32_t EL) {
+__global__ __launch_bounds__(PT) __attribute__((amdgpu_waves_per_eu(6))) void k_prep_large(
+    Tables t, PrepInputs in, int32_t M, const int32_t* list, int32_t count, unsigned long long* err,
+    unsigned char* scratch, int32_t NL, int32_t EL) {
   extern __shared__ __align__(16) unsigned char smem[];
   const PrepLds L = prep_lds(NL);
   const PrepScratch S0 = prep_scratch(nullptr, NL, EL);
@@ -1142,7 +1143,7 @@ hipError_t launch_large_c(const SweepArgs& a, unsigned long long* counter, uint6
 
 }  // namespace
 
-// Workgroups of one preprocessing launch: 512 threads (two workgroups per
+// Workgroups of one preprocessing launch: 256 threads (six workgroups per
 // compute unit) for DAGs up to 512 nodes, 1024 threads (one per compute
 // unit, whose LDS the largest DAGs fill) above.
 static int prep_large_grid(int32_t count, int32_t max_n) {

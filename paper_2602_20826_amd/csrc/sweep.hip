@@ -252,7 +252,8 @@ __host__ __device__ inline Lds lds_layout(int maxn, int nw, bool big, bool rs) {
     l.res = o;
   } else {
     // the two id tables serve the set-up only, before the residual table
-    // is first written: they share its space (12 * 64 words >= 2 * 512 ids)
+    // is first written: they share its space (12 * 64 words hold 2 * 512
+    // ids, 10 * 64 words the 2 * 128 of DAGs up to 128 nodes)
     l.res = o;  o += (size_t)res_slots_of(nw) * WAVE * 4;  // residual table [slot][lane]
     l.ppv = l.res;
     l.inv = l.res + idb;
