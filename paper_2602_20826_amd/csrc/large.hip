@@ -616,14 +616,42 @@ __device__ void prep_one(const Tables& t, const PrepInputs& in, int32_t M, int d
     const int u = S.perm[s];
     const uint32_t a0 = S.succoff[u], a1 = S.succoff[u + 1];
     uint16_t* out = t.succ + e0 + soff[s];
-    for (uint32_t e = a0; e < a1; e++) {
-      const uint16_t x = t.inv[n0 + S.succl[e]];
-      uint32_t j = e - a0;
-      while (j > 0 && out[j - 1] > x) {
-        out[j] = out[j - 1];
-        j--;
+    if (a1 - a0 <= 16) {
+      // up to 16 successors: loaded together and sorted in registers by a
+      // bitonic network (padding above every sigma rank sorts last)
+      const uint32_t deg = a1 - a0;
+      uint32_t b[16];
+#pragma unroll
+      for (int j = 0; j < 16; j++) b[j] = (uint32_t)j < deg ? (uint32_t)t.inv[n0 + S.succl[a0 + j]] : 0xFFFFu;
+#pragma unroll
+      for (int k = 2; k <= 16; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+#pragma unroll
+          for (int i = 0; i < 16; i++) {
+            const int l = i ^ j;
+            if (l > i) {
+              const uint32_t lo = min(b[i], b[l]), hi = max(b[i], b[l]);
+              const bool up = (i & k) == 0;
+              b[i] = up ? lo : hi;
+              b[l] = up ? hi : lo;
+            }
+          }
+        }
       }
-      out[j] = x;
+#pragma unroll
+      for (int j = 0; j < 16; j++)
+        if ((uint32_t)j < deg) out[j] = (uint16_t)b[j];
+    } else {
+      for (uint32_t e = a0; e < a1; e++) {
+        const uint16_t x = t.inv[n0 + S.succl[e]];
+        uint32_t j = e - a0;
+        while (j > 0 && out[j - 1] > x) {
+          out[j] = out[j - 1];
+          j--;
+        }
+        out[j] = x;
+      }
     }
     if (t.nrec)
       t.nrec[n0 + s] = make_uint4(wcl[u], min(S.par[u], (uint32_t)M) | ((uint32_t)s << 16), soff[s],
